@@ -1,0 +1,126 @@
+"""Seeded synthetic inputs shared by the oracle-side tests and the HIP-side tests/benchmark.
+
+This module holds problem sizes, coefficient fields and random vectors only.  It contains none of
+the discretisation arithmetic (no quadrature rules, no basis functions, no matrices): callers pass
+in the physical coordinates at which a coefficient field is wanted.
+
+Coefficient model (Section 2.7, coefficient expansion): a(x, xi) = sum_mu a_mu(x) Psi_mu(xi).
+Every workload here is affine in xi, so the active set is {0, e_1, ..., e_M} and Psi_{e_m} = xi_m.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, asdict
+
+import numpy as np
+
+# Seeds (fixed so every run sees the same data).
+SEED_APPLY_INPUT = 0
+SEED_SOLVE_TARGET = 1
+SEED_MC_DRAWS = 2
+
+
+@dataclass(frozen=True)
+class Workload:
+    """Sizes of one slab problem; the names follow the paper's notation."""
+    name: str
+    dim: int              # d
+    n_cells_1d: int       # finest uniform Cartesian mesh: n_cells_1d^d cells of (lo, hi)^d
+    fe_degree: int        # k of Q_k
+    time_degree: int      # r of dG(r)
+    tau: float            # slab length
+    n_vars: int           # M
+    chaos_degree: int     # p_xi (total degree)
+    n_levels: int         # geometric multigrid levels (level 0 finest)
+    field: str            # coefficient field, see coefficient_modes()
+    lo: float = 0.0
+    hi: float = 1.0
+    pre_smooth: int = 1
+    post_smooth: int = 1
+    vanka_omega: float = 1.0
+    fgmres_restart: int = 30
+
+    @property
+    def n_chaos(self) -> int:
+        return math.comb(self.n_vars + self.chaos_degree, self.chaos_degree)
+
+    @property
+    def n_time(self) -> int:
+        return self.time_degree + 1
+
+    def n_nodes_1d(self, level: int = 0) -> int:
+        return (self.n_cells_1d >> level) * self.fe_degree + 1
+
+    def n_nodes(self, level: int = 0) -> int:
+        return self.n_nodes_1d(level) ** self.dim
+
+    def n_dofs(self, level: int = 0) -> int:
+        return self.n_chaos * self.n_time * self.n_nodes(level)
+
+    def with_(self, **kw) -> "Workload":
+        d = asdict(self)
+        d.update(kw)
+        return Workload(**d)
+
+
+WORKLOADS = {
+    # 2D unit square, Q2 on 8x8 cells, dG(1), dt = 0.01, M = 2, p_xi = 2 (6 modes): 3468 DoFs.
+    "c1": Workload("c1", 2, 8, 2, 1, 0.01, 2, 2, 3, "c1"),
+    # 3D unit cube, Q2 on 32^3 cells, dG(1), M = 4, p_xi = 3 (35 modes): 19,223,750 DoFs, 4 levels.
+    "c2": Workload("c2", 3, 32, 2, 1, 1.0 / 32, 4, 3, 4, "sine"),
+    # 3D unit cube, Q3 on 24^3 cells, dG(2), M = 3, p_xi = 4 (35 modes): 40,846,785 DoFs, 4 levels.
+    "c3": Workload("c3", 3, 24, 3, 2, 1.0 / 24, 3, 4, 4, "sine"),
+    # Small cases used by the tests (several cells per direction, ragged sizes, every degree).
+    "t2q1": Workload("t2q1", 2, 6, 1, 0, 0.05, 2, 2, 2, "sine"),
+    "t2q2": Workload("t2q2", 2, 6, 2, 1, 0.02, 2, 2, 2, "sine"),
+    "t2q3": Workload("t2q3", 2, 4, 3, 2, 0.02, 3, 2, 2, "sine"),
+    "t3q1": Workload("t3q1", 3, 4, 1, 1, 0.05, 2, 1, 2, "sine"),
+    "t3q2": Workload("t3q2", 3, 4, 2, 1, 0.05, 3, 2, 2, "sine"),
+    "t3q3": Workload("t3q3", 3, 2, 3, 2, 0.05, 2, 2, 1, "sine"),
+    "t3q4": Workload("t3q4", 3, 2, 4, 1, 0.05, 2, 1, 1, "sine"),
+}
+
+
+def _sine_shape(m: int, x: np.ndarray) -> np.ndarray:
+    """phi_1 = prod_k sin(pi x_k); phi_m (m >= 2) doubles the frequency in direction (m - 2) mod d."""
+    d = x.shape[-1]
+    out = np.ones(x.shape[:-1])
+    for k in range(d):
+        freq = 2.0 if (m >= 2 and (m - 2) % d == k) else 1.0
+        out = out * np.sin(freq * math.pi * x[..., k])
+    return out
+
+
+def coefficient_modes(w: Workload, x: np.ndarray):
+    """Affine coefficient of workload ``w`` at physical points ``x`` (shape [..., d]).
+
+    Returns ``(mu_list, values)`` with ``values[k]`` = a_{mu_k}(x).  The first mode is mu = 0.
+    * "c1":   a = 1 + 0.1 xi_1 sin(pi x) sin(pi y) + 0.05 xi_2 sin(2 pi x) sin(pi y)
+    * "sine": a = 1 + sum_m (0.1 / m^2) xi_m phi_m(x)
+    """
+    x = np.asarray(x, dtype=np.float64)
+    M = w.n_vars
+    mus = [tuple([0] * M)]
+    vals = [np.ones(x.shape[:-1])]
+    for m in range(1, M + 1):
+        e = [0] * M
+        e[m - 1] = 1
+        mus.append(tuple(e))
+        if w.field == "c1":
+            if m == 1:
+                v = 0.1 * np.sin(math.pi * x[..., 0]) * np.sin(math.pi * x[..., 1])
+            elif m == 2:
+                v = 0.05 * np.sin(2 * math.pi * x[..., 0]) * np.sin(math.pi * x[..., 1])
+            else:
+                v = np.zeros(x.shape[:-1])
+        elif w.field == "sine":
+            v = (0.1 / m ** 2) * _sine_shape(m, x)
+        else:
+            raise ValueError(f"unknown field {w.field}")
+        vals.append(v)
+    return mus, np.stack(vals)
+
+
+def uniform_vector(n: int, seed: int) -> np.ndarray:
+    """FP64 vector of ``n`` entries drawn from U[-1, 1] with numpy's PCG64 generator."""
+    return np.random.Generator(np.random.PCG64(seed)).uniform(-1.0, 1.0, size=n)
