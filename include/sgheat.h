@@ -1,0 +1,134 @@
+/*
+ * sgheat.h -- C ABI of libsgheat.so: matrix-free stochastic-Galerkin space-time slab operator, its
+ * Vanka-smoothed geometric-multigrid preconditioner and the flexible-GMRES slab solve, on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The problem is the slab system of the paper (Problem "tensor-product-slab-system", eqs.
+ * local_tensor_system and local_rhs_tensor):
+ *
+ *     AA U = rhs,   AA = I_xi (x) A_t (x) M_x + sum_{mu in M_a} G_mu (x) B_t (x) K_mu,
+ *
+ * with the dG(r) right-Radau time matrices A_t (evolution, eq. At) and B_t (mass, eq. Bt), the
+ * Hermite triple-product tensors G_mu (eq. triple_stoch) and the Q_k mass / coefficient-weighted
+ * stiffness matrices M_x, K_mu on a uniform Cartesian mesh of (lo, hi)^d.
+ *
+ * Conventions shared by every entry point:
+ *   - Vectors are DEVICE pointers owned by the caller, contiguous, in the precision named by the
+ *     argument type, laid out mode-major: index = alpha * (N_t * N_x) + i * N_x + node, where
+ *     alpha runs over the total-degree chaos index set (graded by |alpha|, lexicographically
+ *     descending inside a degree), i over the N_t = r+1 time DoFs, and node over the
+ *     (n k + 1)^d Lagrange nodes (Gauss-Lobatto support points), lexicographic with x fastest.
+ *     Boundary nodes are part of the vector.
+ *   - Homogeneous Dirichlet condition: rows of boundary DoFs are identity rows; boundary columns
+ *     are dropped from the other rows.
+ *   - Streams: `hip_stream` is a hipStream_t passed as void* (NULL = the default stream).  Work is
+ *     enqueued on that stream only.
+ *   - Errors: every call returns an sg_status; arguments are checked before anything is enqueued.
+ *     No C++ exception crosses the ABI.  sg_last_error() gives a thread-local message for the last
+ *     non-OK status of the calling thread.
+ *   - Aliasing: input and output vectors of one call must not overlap (SG_EINVAL).
+ */
+#ifndef SGHEAT_H
+#define SGHEAT_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sg_handle_s* sg_handle;
+
+typedef enum {
+    SG_OK = 0,
+    SG_NOT_CONVERGED = 1,   /* fgmres_solve_slab hit max_iter; x and info still hold the best iterate */
+    SG_EINVAL = -1,         /* invalid argument (null pointer, bad size, aliasing, unsupported combination) */
+    SG_ENOMEM = -2,         /* device or host allocation failed */
+    SG_EHIP = -3,           /* a HIP runtime call failed; the message names it */
+    SG_ESINGULAR = -4,      /* a Vanka patch matrix or the coarsest-level matrix is singular */
+    SG_EUNSUPPORTED = -5    /* valid request this build does not implement (e.g. non-affine preconditioner) */
+} sg_status;
+
+typedef enum {
+    SG_FP64 = 0,            /* every step in FP64 */
+    SG_MIXED = 1            /* V-cycle and Vanka in FP32 on fine levels, FP64 coarsest LU, FP64 outer FGMRES */
+} sg_precision;
+
+/* Problem description (all arrays are HOST memory, copied by sg_create). */
+typedef struct {
+    int dim;                /* d in {2, 3} (Section 2.1)                                              */
+    int n_cells_1d;         /* finest mesh: n^d cells of (lo, hi)^d                                   */
+    double lo, hi;          /* domain bounds                                                          */
+    int fe_degree;          /* k of Q_k, 1..4 (Section 2.4)                                          */
+    int time_degree;        /* r of dG(r), 0..3, right Gauss-Radau nodal basis (Section 2.5)          */
+    double tau;             /* slab length                                                            */
+    int n_vars;             /* M, number of standard Gaussian variables (eq. random_varibale_law)     */
+    int chaos_degree;       /* p_xi, total degree of the chaos space (Section 2.6)                   */
+    int n_coef_modes;       /* |M_a|, active coefficient modes (eq. coeff_expansion)                  */
+    const int* coef_mu;     /* [n_coef_modes][n_vars] multi-indices; must contain mu = 0              */
+    const double* coef_qp;  /* [n_levels][n_coef_modes][n_cells(l)][(k+1)^d]: a_mu at the Gauss points
+                               of level l (cells and points lexicographic, x fastest)                */
+    int n_levels;           /* multigrid levels, 0 = finest; n_cells_1d must be divisible by 2^(n_levels-1) */
+    int pre_smooth, post_smooth;  /* Vanka sweeps before / after the coarse correction               */
+    double vanka_omega;     /* damping of the additive Vanka correction                              */
+    int fgmres_restart;     /* Krylov basis length before restart (<= 64)                            */
+    sg_precision precision;
+} sg_problem_desc;
+
+/* Counters of one slab solve (mirrors the paper's Table tab:finite-size-work-solver-performance). */
+typedef struct {
+    int iterations;         /* FGMRES iterations (= preconditioner calls)                             */
+    int restarts;           /* Arnoldi cycles started                                                 */
+    int vcycles;            /* gmg V-cycles applied                                                   */
+    int applies;            /* operator applications (vmult calls), including true-residual checks    */
+    int converged;          /* 1 if ||b - AA x|| / ||b|| <= rtol                                      */
+    double rel_residual_true;
+    double t_apply_ms, t_prec_ms, t_total_ms;   /* accumulated, from HIP events on the stream         */
+    double work_proxy;      /* N_SG,slab * preconditioner calls (eq. work-proxy)                     */
+} sg_solve_info;
+
+/* Build the handle: copies the description, builds the chaos coupling lists, time matrices, 1D
+ * tables and level data, uploads coefficients, forms and inverts every Vanka patch matrix on the
+ * device (LU with partial pivoting) and the coarsest-level matrix on the host.  Synchronous.
+ * Returns SG_EINVAL for inconsistent descriptions, SG_ESINGULAR for a singular patch. */
+sg_status sg_create(const sg_problem_desc* desc, sg_handle* out);
+
+/* Release every device and host resource of the handle.  NULL is accepted. */
+sg_status sg_destroy(sg_handle h);
+
+/* Number of entries N_xi * N_t * N_x(level) of a vector on multigrid level `level`. */
+sg_status sg_vector_length(sg_handle h, int level, long long* n);
+
+/* y = AA x on the finest level (Problem tensor-product-slab-system, left-hand side; Remark
+ * solver-matrix-free-sg: only the action is formed).  FP64.  Asynchronous on the stream. */
+sg_status sg_operator_apply(sg_handle h, const double* x, double* y, void* hip_stream);
+
+/* `sweeps` additive Vanka sweeps on the mean block I_xi (x) A_0 of level `level`, A_0 =
+ * A_t (x) M_x + B_t (x) K_{a_0} (Remark solver-matrix-free-sg):
+ *     x <- x + omega sum_K R_K^T W_K A_{0,K}^{-1} R_K (b - A_0 x),   then x_D = b_D on Dirichlet DoFs.
+ * b and x are FP64 on every level; with SG_MIXED the sweep runs in FP32 internally for level 0 and
+ * the levels above the coarsest.  x is updated in place.  Asynchronous on the stream. */
+sg_status sg_vanka_smooth(sg_handle h, int level, const double* b, double* x, int sweeps, void* hip_stream);
+
+/* z = one V-cycle for (I_xi (x) A_0) z = r: the stochastic block-Jacobi preconditioner with the
+ * mean-based diagonal block (every diagonal block equals A_0 for an affine coefficient).
+ * Requires an affine coefficient set (mu in {0, e_1..e_M}), else SG_EUNSUPPORTED at create.
+ * FP64 interface; FP32 inside with SG_MIXED.  Asynchronous on the stream. */
+sg_status gmg_vcycle(sg_handle h, const double* r, double* z, void* hip_stream);
+
+/* Solve AA x = b by right-preconditioned flexible GMRES (restart fgmres_restart, CGS2,
+ * preconditioner gmg_vcycle) starting from the x passed in, until ||b - AA x||_2 / ||b||_2 <= rtol
+ * (true residual) or max_iter iterations.  Synchronises the stream (Krylov scalars go to the host).
+ * `info` may be NULL.  Returns SG_NOT_CONVERGED if the tolerance was not reached. */
+sg_status fgmres_solve_slab(sg_handle h, const double* b, double* x, double rtol, int max_iter,
+                            sg_solve_info* info, void* hip_stream);
+
+/* Physical coordinates of the Gauss points of level `level`, written to the HOST array
+ * xyz[n_cells(l)][(k+1)^d][d] (the points at which coef_qp is sampled).  Needs no handle. */
+sg_status sg_quadrature_points(const sg_problem_desc* desc, int level, double* xyz);
+
+/* Message for the last non-OK status returned on the calling thread ("" if none). */
+const char* sg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SGHEAT_H */

@@ -1,0 +1,90 @@
+// Launchers of the gfx950 kernels.  Every launcher enqueues on the given stream and returns the
+// launch status; argument validity is checked by the caller (sgheat.cpp) before any launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+
+namespace sg {
+
+// ---- slab operator ------------------------------------------------------------------------------
+// y = AA x, or y = b - AA x when b != nullptr, restricted to the coupling list given.
+// coef: [n_mu][n_cells][(k+1)^d] values a_mu(x_q) * w_q * h^(d-2).
+// Coupling CSR: row alpha * n_mu + mu lists (beta, [G_mu]_{alpha beta}).
+template <typename T>
+struct ApplyOp {
+    int dim, k, nt;
+    Grid g;
+    int n_xi, n_mu;
+    const T* coef;
+    long long coef_mode_stride;   // n_cells * (k+1)^d
+    const int* cptr;
+    const int* cbeta;
+    const int* cmu;               // mu index of every entry
+    const T* cw;
+    const Tables<T>* tables;      // host copy, passed by value to the kernel
+    int cells_per_block;          // cells handled by one workgroup
+};
+template <typename T>
+hipError_t launch_apply(const ApplyOp<T>& op, const T* x, T* y, const T* b, hipStream_t s);
+template <typename T>
+size_t apply_lds_bytes(const ApplyOp<T>& op, int cells_per_block);
+
+// ---- Vanka -----------------------------------------------------------------------------------------
+// Element stiffness of the mean coefficient: E[cell][a][b] = sum_q c0(cell,q) sum_d dphi_a dphi_b.
+struct ElemTables {
+    double S[kMaxN1 * kMaxN1];    // l_a(g_q)
+    double Dn[kMaxN1 * kMaxN1];   // l_a'(g_q)
+};
+hipError_t launch_elem_stiffness(int dim, int k, Grid g, const double* coef0, const ElemTables& et,
+                                 double* E, hipStream_t s);
+
+// Form every patch matrix A_{0,K} = A_t (x) M_K + B_t (x) K_K (restrictions of the assembled
+// matrices; Dirichlet local DoFs replaced by identity rows and columns), invert it by Gauss-Jordan
+// elimination with partial pivoting in FP64, and store the inverse in FP64 and/or FP32.
+struct PatchTime {
+    double At[kMaxNT * kMaxNT];
+    double Bt[kMaxNT];
+};
+hipError_t launch_patch_invert(int dim, int k, int nt, Grid g, const double* E, const double* Me,
+                               const PatchTime& pt, double* inv64, float* inv32, int* status,
+                               hipStream_t s);
+
+// x <- x + omega sum_K R_K^T W_K inv_K R_K r over the cells; x_D = b_D on Dirichlet nodes.
+template <typename T>
+hipError_t launch_vanka_apply(int dim, int k, int nt, Grid g, int n_xi, const T* inv, const T* r,
+                              const T* b, T* x, T omega, hipStream_t s);
+
+// ---- transfers ---------------------------------------------------------------------------------------
+// One 1D pass along `dir`: out[c][.., o, ..] (+)= sum_w tw[o*width + w] in[c][.., tidx[o*width + w], ..]
+template <typename T>
+hipError_t launch_transfer_1d(int dim, int ncomp, const int* in_dims, const int* out_dims, int dir,
+                              const int* tidx, const T* tw, int width, const T* in, T* out,
+                              bool accumulate, hipStream_t s);
+
+// ---- coarsest level ------------------------------------------------------------------------------
+// x = b, then on interior DoFs x[alpha][dof_r] = sum_l AinvT[l][r] b[alpha][dof_l] in FP64.
+template <typename T>
+hipError_t launch_coarse_solve(const double* AinvT, int nint, const int* dofs, int n_xi,
+                               long long mode_len, const T* b, T* x, hipStream_t s);
+
+// ---- vector kernels (FP64 unless noted) -----------------------------------------------------------
+hipError_t launch_multidot(const double* V, long long ldv, int k, const double* w, long long n,
+                           double* partial, int nblk, hipStream_t s);
+hipError_t launch_update_dot(const double* V, long long ldv, int k, const double* h, const double* w,
+                             double* wout, long long n, double* partial, int nblk, bool dot,
+                             hipStream_t s);
+hipError_t launch_reduce_partials(const double* partial, int nblk, int k, double* out, hipStream_t s);
+hipError_t launch_multi_axpy(const double* V, long long ldv, int k, const double* y, double* x,
+                             long long n, hipStream_t s);
+hipError_t launch_axpby(double a, const double* x, double b, const double* y, double* out,
+                        long long n, hipStream_t s);     // out = a x + b y
+template <typename S, typename D>
+hipError_t launch_convert(const S* in, D* out, long long n, hipStream_t s);
+template <typename T>
+hipError_t launch_fill(T* out, T v, long long n, hipStream_t s);
+
+constexpr int kDotBlocks = 1024;   // fixed partial-sum count: reductions are deterministic
+
+}  // namespace sg

@@ -1,0 +1,301 @@
+// Grid transfers, coarsest-level solve and the vector kernels of the Krylov solver.
+//
+// Transfers: the prolongation is nodal interpolation of the coarse Q_k function at the fine nodes
+// (zero on Dirichlet nodes); on a uniform hierarchy it is the tensor product of one 1D matrix per
+// direction, so both P and R = P^T are applied as d banded 1D passes.
+//
+// Reductions are deterministic: a fixed number of blocks writes partial sums, and one block adds
+// them in a fixed order.
+#include "kernels.hpp"
+
+namespace sg {
+
+namespace {
+
+template <typename T>
+__global__ void k_transfer_1d(int dim, long long total, int i0, int i1, int o0, int o1, int o2, int dir,
+                              const int* __restrict__ tidx, const T* __restrict__ tw, int width,
+                              const T* __restrict__ in, T* __restrict__ out, bool accumulate,
+                              long long in_comp, long long out_comp) {
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+         idx += (long long)gridDim.x * blockDim.x) {
+        long long r = idx;
+        const int x0 = r % o0;
+        r /= o0;
+        const int x1 = r % o1;
+        r /= o1;
+        int x2 = 0;
+        if (dim == 3) { x2 = r % o2; r /= o2; }
+        const long long c = r;
+        const int o = dir == 0 ? x0 : (dir == 1 ? x1 : x2);
+        T acc = T(0);
+        for (int w = 0; w < width; ++w) {
+            const T wt = tw[o * width + w];
+            if (wt == T(0)) continue;
+            const int src = tidx[o * width + w];
+            const int y0 = dir == 0 ? src : x0;
+            const int y1 = dir == 1 ? src : x1;
+            const int y2 = dir == 2 ? src : x2;
+            acc += wt * in[c * in_comp + ((long long)y2 * i1 + y1) * i0 + y0];
+        }
+        if (accumulate) out[idx] += acc;
+        else out[idx] = acc;
+    }
+}
+
+template <typename T>
+__global__ void k_coarse_solve(const double* __restrict__ AinvT, int nint, const int* __restrict__ dofs, int n_xi,
+                               long long mode_len, const T* __restrict__ b, T* __restrict__ x) {
+    const long long total = (long long)nint * n_xi;
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int row = idx % nint;
+        const int al = idx / nint;
+        const T* bm = b + al * mode_len;
+        double acc = 0.0;
+        for (int l = 0; l < nint; ++l) acc += AinvT[(long long)l * nint + row] * (double)bm[dofs[l]];
+        x[al * mode_len + dofs[row]] = (T)acc;
+    }
+}
+
+template <typename T>
+__global__ void k_copy(const T* __restrict__ in, T* __restrict__ out, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        out[i] = in[i];
+}
+
+constexpr int kDotThreads = 256;
+constexpr int kG = 8;   // vectors per register group
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kDotThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// partial[blk][j] = sum over this block's share of V[j][i] w[i], j < k
+__global__ void __launch_bounds__(kDotThreads)
+    k_multidot(const double* __restrict__ V, long long ldv, int k, const double* __restrict__ w, long long n,
+               double* __restrict__ partial) {
+    __shared__ double sh[kDotThreads];
+    for (int j0 = 0; j0 < k; j0 += kG) {
+        double acc[kG];
+#pragma unroll
+        for (int u = 0; u < kG; ++u) acc[u] = 0.0;
+        for (long long i = blockIdx.x * (long long)kDotThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kDotThreads) {
+            const double wv = w[i];
+#pragma unroll
+            for (int u = 0; u < kG; ++u)
+                if (j0 + u < k) acc[u] += V[(j0 + u) * ldv + i] * wv;
+        }
+#pragma unroll
+        for (int u = 0; u < kG; ++u) {
+            if (j0 + u < k) {
+                const double s = block_sum(acc[u], sh);
+                if (threadIdx.x == 0) partial[(long long)blockIdx.x * k + j0 + u] = s;
+            }
+        }
+    }
+}
+
+// wout = w - sum_j h[j] V[j]; if dot, partial[blk][j] = sum V[j] wout (j < k), else partial[blk][0] = |wout|^2
+template <int KMAX>
+__global__ void __launch_bounds__(kDotThreads)
+    k_update_dot(const double* __restrict__ V, long long ldv, int k, const double* __restrict__ h,
+                 const double* __restrict__ w, double* __restrict__ wout, long long n, double* __restrict__ partial,
+                 bool dot) {
+    __shared__ double sh[kDotThreads];
+    double hc[KMAX];
+    double acc[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+        hc[j] = j < k ? h[j] : 0.0;
+        acc[j] = 0.0;
+    }
+    double nrm = 0.0;
+    for (long long i = blockIdx.x * (long long)kDotThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kDotThreads) {
+        double v[KMAX];
+        double s = w[i];
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) {
+            v[j] = j < k ? V[j * ldv + i] : 0.0;
+            s -= hc[j] * v[j];
+        }
+        wout[i] = s;
+        if (dot) {
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j) acc[j] += v[j] * s;
+        } else {
+            nrm += s * s;
+        }
+    }
+    if (dot) {
+        for (int j = 0; j < k; ++j) {
+            double a = 0.0;
+#pragma unroll
+            for (int u = 0; u < KMAX; ++u) if (u == j) a = acc[u];
+            const double sum = block_sum(a, sh);
+            if (threadIdx.x == 0) partial[(long long)blockIdx.x * k + j] = sum;
+        }
+    } else {
+        const double sum = block_sum(nrm, sh);
+        if (threadIdx.x == 0) partial[blockIdx.x] = sum;
+    }
+}
+
+__global__ void __launch_bounds__(kDotThreads) k_reduce_partials(const double* __restrict__ partial, int nblk, int k,
+                                                                  double* __restrict__ out) {
+    __shared__ double sh[kDotThreads];
+    for (int j = 0; j < k; ++j) {
+        double a = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += kDotThreads) a += partial[(long long)b * k + j];
+        const double s = block_sum(a, sh);
+        if (threadIdx.x == 0) out[j] = s;
+    }
+}
+
+// x += sum_j y[j] V[j]
+template <int KMAX>
+__global__ void k_multi_axpy(const double* __restrict__ V, long long ldv, int k, const double* __restrict__ y,
+                             double* __restrict__ x, long long n) {
+    double yc[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) yc[j] = j < k ? y[j] : 0.0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        double s = x[i];
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j)
+            if (j < k) s += yc[j] * V[j * ldv + i];
+        x[i] = s;
+    }
+}
+
+__global__ void k_axpby(double a, const double* __restrict__ x, double b, const double* __restrict__ y,
+                        double* __restrict__ out, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        out[i] = a * x[i] + (y ? b * y[i] : 0.0);
+}
+
+template <typename S, typename D>
+__global__ void k_convert(const S* __restrict__ in, D* __restrict__ out, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        out[i] = (D)in[i];
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ out, T v, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        out[i] = v;
+}
+
+unsigned grid_for(long long n, int threads, unsigned cap = 8192) {
+    long long b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_transfer_1d(int dim, int ncomp, const int* in_dims, const int* out_dims, int dir, const int* tidx,
+                              const T* tw, int width, const T* in, T* out, bool accumulate, hipStream_t s) {
+    long long out_comp = (long long)out_dims[0] * out_dims[1] * (dim == 3 ? out_dims[2] : 1);
+    long long in_comp = (long long)in_dims[0] * in_dims[1] * (dim == 3 ? in_dims[2] : 1);
+    const long long total = out_comp * ncomp;
+    hipLaunchKernelGGL(k_transfer_1d<T>, dim3(grid_for(total, 256, 65536)), dim3(256), 0, s, dim, total, in_dims[0],
+                       in_dims[1], out_dims[0], out_dims[1], dim == 3 ? out_dims[2] : 1, dir, tidx, tw, width, in, out,
+                       accumulate, in_comp, out_comp);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_coarse_solve(const double* AinvT, int nint, const int* dofs, int n_xi, long long mode_len,
+                               const T* b, T* x, hipStream_t s) {
+    const long long n = mode_len * n_xi;
+    hipLaunchKernelGGL(k_copy<T>, dim3(grid_for(n, 256)), dim3(256), 0, s, b, x, n);
+    const long long total = (long long)nint * n_xi;
+    hipLaunchKernelGGL(k_coarse_solve<T>, dim3(grid_for(total, 64, 65536)), dim3(64), 0, s, AinvT, nint, dofs, n_xi,
+                       mode_len, b, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_multidot(const double* V, long long ldv, int k, const double* w, long long n, double* partial,
+                           int nblk, hipStream_t s) {
+    hipLaunchKernelGGL(k_multidot, dim3(nblk), dim3(kDotThreads), 0, s, V, ldv, k, w, n, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_dot(const double* V, long long ldv, int k, const double* h, const double* w, double* wout,
+                             long long n, double* partial, int nblk, bool dot, hipStream_t s) {
+#define SG_UD(KM)                                                                                               \
+    if (k <= KM) {                                                                                              \
+        hipLaunchKernelGGL((k_update_dot<KM>), dim3(nblk), dim3(kDotThreads), 0, s, V, ldv, k, h, w, wout, n, partial, dot); \
+        return hipGetLastError();                                                                              \
+    }
+    SG_UD(8)
+    SG_UD(16)
+    SG_UD(32)
+    SG_UD(65)
+#undef SG_UD
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce_partials(const double* partial, int nblk, int k, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kDotThreads), 0, s, partial, nblk, k, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_multi_axpy(const double* V, long long ldv, int k, const double* y, double* x, long long n,
+                             hipStream_t s) {
+#define SG_MA(KM)                                                                                   \
+    if (k <= KM) {                                                                                  \
+        hipLaunchKernelGGL((k_multi_axpy<KM>), dim3(grid_for(n, 256)), dim3(256), 0, s, V, ldv, k, y, x, n); \
+        return hipGetLastError();                                                                  \
+    }
+    SG_MA(8)
+    SG_MA(16)
+    SG_MA(32)
+    SG_MA(64)
+#undef SG_MA
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_axpby(double a, const double* x, double b, const double* y, double* out, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpby, dim3(grid_for(n, 256)), dim3(256), 0, s, a, x, b, y, out, n);
+    return hipGetLastError();
+}
+
+template <typename S, typename D>
+hipError_t launch_convert(const S* in, D* out, long long n, hipStream_t s) {
+    hipLaunchKernelGGL((k_convert<S, D>), dim3(grid_for(n, 256)), dim3(256), 0, s, in, out, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill(T* out, T v, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n, 256)), dim3(256), 0, s, out, v, n);
+    return hipGetLastError();
+}
+
+template hipError_t launch_transfer_1d<double>(int, int, const int*, const int*, int, const int*, const double*, int,
+                                               const double*, double*, bool, hipStream_t);
+template hipError_t launch_transfer_1d<float>(int, int, const int*, const int*, int, const int*, const float*, int,
+                                              const float*, float*, bool, hipStream_t);
+template hipError_t launch_coarse_solve<double>(const double*, int, const int*, int, long long, const double*, double*,
+                                                hipStream_t);
+template hipError_t launch_coarse_solve<float>(const double*, int, const int*, int, long long, const float*, float*,
+                                               hipStream_t);
+template hipError_t launch_convert<double, float>(const double*, float*, long long, hipStream_t);
+template hipError_t launch_convert<float, double>(const float*, double*, long long, hipStream_t);
+template hipError_t launch_convert<double, double>(const double*, double*, long long, hipStream_t);
+template hipError_t launch_fill<double>(double*, double, long long, hipStream_t);
+template hipError_t launch_fill<float>(float*, float, long long, hipStream_t);
+
+}  // namespace sg

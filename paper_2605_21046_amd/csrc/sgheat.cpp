@@ -1,0 +1,936 @@
+// C ABI of libsgheat.so (declared in include/sgheat.h): handle set-up and the host orchestration of
+// the slab operator, the Vanka smoother, the geometric-multigrid V-cycle and flexible GMRES.
+//
+// Everything numerical runs in the gfx950 kernels of kernels_*.hip; this file only validates
+// arguments, builds small host tables (1D bases, time matrices, chaos coupling lists, transfer
+// stencils), inverts the coarsest-level matrix once, and enqueues kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/sgheat.h"
+#include "basis.hpp"
+#include "kernels.hpp"
+
+using namespace sg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+sg_status fail(sg_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+#define SG_HIP(call)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return fail(SG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));                  \
+    } while (0)
+
+#define SG_TRY(call)                                                                                   \
+    do {                                                                                               \
+        sg_status s_ = (call);                                                                         \
+        if (s_ != SG_OK) return s_;                                                                    \
+    } while (0)
+
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+    sg_status alloc(size_t count, const char* what) {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = count;
+        if (count == 0) return SG_OK;
+        if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            return fail(SG_ENOMEM, std::string("device allocation failed: ") + what);
+        }
+        return SG_OK;
+    }
+    sg_status upload(const T* host, size_t count, const char* what) {
+        SG_TRY(alloc(count, what));
+        if (count) SG_HIP(hipMemcpy(p, host, count * sizeof(T), hipMemcpyHostToDevice));
+        return SG_OK;
+    }
+};
+
+struct Level {
+    Grid g{};
+    double h = 0.0;
+    Tables<double> tab64{};
+    Tables<float> tab32{};
+    DevBuf<double> coef64;   // level 0: every mode; other levels: the mean mode only
+    DevBuf<float> coef32;
+    DevBuf<double> inv64;    // patch inverses [n_cells][npp][npp]
+    DevBuf<float> inv32;
+    // transfer stencils between this level (fine) and level + 1 (coarse)
+    int wp = 0, wr = 0;
+    DevBuf<int> p_idx, r_idx;
+    DevBuf<double> p_w64, r_w64;
+    DevBuf<float> p_w32, r_w32;
+    // work vectors of the V-cycle
+    DevBuf<double> b64, x64, r64;
+    DevBuf<float> b32, x32, r32;
+    long long len = 0;       // N_xi * N_t * n_nodes
+};
+
+}  // namespace
+
+struct sg_handle_s {
+    sg_problem_desc d{};
+    std::vector<int> coef_mu;
+    int NP = 0, NT = 0, n_xi = 0, n_mu = 0, npp = 0;
+    Coupling cpl;
+    bool mixed = false;
+    std::vector<double> At, Bt;
+    std::vector<Level> lv;
+    // coupling lists
+    DevBuf<int> cptr, cbeta, cmu, cptr_m, cbeta_m, cmu_m;
+    DevBuf<double> cw64, cw_m64;
+    DevBuf<float> cw32, cw_m32;
+    // coarsest level
+    int nint = 0;
+    DevBuf<double> coarse_invT;
+    DevBuf<int> coarse_dofs;
+    // transfer temporaries
+    DevBuf<double> t64a, t64b;
+    DevBuf<float> t32a, t32b;
+    // Krylov workspace
+    int restart = 30;
+    DevBuf<double> V, Z, w1, w2, partial, dscal;
+    std::vector<double> hbuf;
+    long long N = 0;
+};
+
+namespace {
+
+int ipow_h(int b, int e) {
+    int r = 1;
+    while (e--) r *= b;
+    return r;
+}
+
+template <typename T>
+void fill_tables(Tables<T>* tb, const std::vector<double>& S, const std::vector<double>& D,
+                 const std::vector<double>& w, const std::vector<double>& At, const std::vector<double>& Bt, int N1,
+                 int NT, double vol) {
+    std::memset(tb, 0, sizeof(*tb));
+    for (int i = 0; i < N1 * N1; ++i) {
+        tb->S[i] = (T)S[i];
+        tb->D[i] = (T)D[i];
+    }
+    for (int i = 0; i < N1; ++i) tb->w[i] = (T)w[i];
+    for (int i = 0; i < NT; ++i) {
+        tb->Bt[i] = (T)Bt[i];
+        for (int j = 0; j < NT; ++j) tb->As[i * NT + j] = (T)(At[i * NT + j] / Bt[i]);
+    }
+    tb->vol = (T)vol;
+}
+
+sg_status validate(const sg_problem_desc* d) {
+    if (!d) return fail(SG_EINVAL, "desc is NULL");
+    if (d->dim != 2 && d->dim != 3) return fail(SG_EINVAL, "dim must be 2 or 3");
+    if (d->fe_degree < 1 || d->fe_degree > 4) return fail(SG_EINVAL, "fe_degree must be in 1..4");
+    if (d->time_degree < 0 || d->time_degree > 3) return fail(SG_EINVAL, "time_degree must be in 0..3");
+    if (d->n_cells_1d < 1) return fail(SG_EINVAL, "n_cells_1d must be >= 1");
+    if (!(d->hi > d->lo)) return fail(SG_EINVAL, "hi must exceed lo");
+    if (!(d->tau > 0.0)) return fail(SG_EINVAL, "tau must be positive");
+    if (d->n_vars < 1 || d->chaos_degree < 0) return fail(SG_EINVAL, "n_vars >= 1 and chaos_degree >= 0 required");
+    if (d->n_coef_modes < 1 || !d->coef_mu || !d->coef_qp) return fail(SG_EINVAL, "coefficient arrays missing");
+    if (d->n_levels < 1 || d->n_levels > 12) return fail(SG_EINVAL, "n_levels must be in 1..12");
+    if (d->n_cells_1d % (1 << (d->n_levels - 1)) != 0)
+        return fail(SG_EINVAL, "n_cells_1d must be divisible by 2^(n_levels-1)");
+    if (d->pre_smooth < 0 || d->post_smooth < 0) return fail(SG_EINVAL, "smoothing counts must be >= 0");
+    if (d->fgmres_restart < 1 || d->fgmres_restart > 64) return fail(SG_EINVAL, "fgmres_restart must be in 1..64");
+    if (d->precision != SG_FP64 && d->precision != SG_MIXED) return fail(SG_EINVAL, "unknown precision");
+    return SG_OK;
+}
+
+// 1D prolongation stencil from a coarse level with nc cells to the fine level with 2 nc cells:
+// fine node f takes sum_a l_a(t) * coarse node (c k + a); rows and columns of Dirichlet nodes are 0.
+void prolong_1d(int nc, int k, const std::vector<double>& gll, std::vector<int>* idx, std::vector<double>* w) {
+    const int nf1 = 2 * nc * k + 1, nc1 = nc * k + 1;
+    idx->assign((size_t)nf1 * (k + 1), 0);
+    w->assign((size_t)nf1 * (k + 1), 0.0);
+    for (int f = 0; f < nf1; ++f) {
+        const int cellf = std::min(f / k, 2 * nc - 1);
+        const int af = f - cellf * k;
+        const double xf = (cellf + gll[af]) * 0.5;   // in coarse-cell units
+        int c = (int)std::floor(xf);
+        if (c > nc - 1) c = nc - 1;
+        const double t = xf - c;
+        for (int a = 0; a <= k; ++a) {
+            const int ci = c * k + a;
+            double v = lagrange_value(gll, a, t);
+            if (f == 0 || f == nf1 - 1 || ci == 0 || ci == nc1 - 1) v = 0.0;
+            if (std::fabs(v) < 1e-15) v = 0.0;
+            (*idx)[f * (k + 1) + a] = ci;
+            (*w)[f * (k + 1) + a] = v;
+        }
+    }
+}
+
+// Host Gauss-Jordan inversion with partial pivoting (coarsest level only).
+bool invert_dense(std::vector<double>& A, int n) {
+    std::vector<int> perm(n);
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        double best = std::fabs(A[(size_t)k * n + k]);
+        for (int i = k + 1; i < n; ++i)
+            if (std::fabs(A[(size_t)i * n + k]) > best) { best = std::fabs(A[(size_t)i * n + k]); p = i; }
+        if (!(best > 0.0)) return false;
+        perm[k] = p;
+        if (p != k)
+            for (int j = 0; j < n; ++j) std::swap(A[(size_t)k * n + j], A[(size_t)p * n + j]);
+        const double ipiv = 1.0 / A[(size_t)k * n + k];
+        double* rowk = &A[(size_t)k * n];
+        for (int j = 0; j < n; ++j) rowk[j] *= ipiv;
+        rowk[k] = ipiv;
+        auto work = [&](int i0, int i1) {
+            for (int i = i0; i < i1; ++i) {
+                if (i == k) continue;
+                double* ri = &A[(size_t)i * n];
+                const double f = ri[k];
+                if (f == 0.0) continue;
+                for (int j = 0; j < n; ++j) ri[j] -= f * rowk[j];
+                ri[k] = -f * ipiv;
+            }
+        };
+        if (n < 256 || nth == 1) {
+            work(0, n);
+        } else {
+            std::vector<std::thread> th;
+            const int chunk = (n + (int)nth - 1) / (int)nth;
+            for (unsigned t = 0; t < nth; ++t) {
+                const int i0 = (int)t * chunk, i1 = std::min(n, i0 + chunk);
+                if (i0 < i1) th.emplace_back(work, i0, i1);
+            }
+            for (auto& t : th) t.join();
+        }
+    }
+    for (int k = n - 1; k >= 0; --k)
+        if (perm[k] != k)
+            for (int i = 0; i < n; ++i) std::swap(A[(size_t)i * n + k], A[(size_t)i * n + perm[k]]);
+    return true;
+}
+
+sg_status build(sg_handle h) {
+    const sg_problem_desc& d = h->d;
+    const int dim = d.dim, k = d.fe_degree, N1 = k + 1;
+    h->NP = ipow_h(N1, dim);
+    h->NT = d.time_degree + 1;
+    h->mixed = d.precision == SG_MIXED;
+    std::string err;
+    if (!build_coupling(d.n_vars, d.chaos_degree, d.n_coef_modes, h->coef_mu.data(), &h->cpl, &err))
+        return fail(SG_EINVAL, err);
+    h->n_xi = h->cpl.n_xi;
+    h->n_mu = d.n_coef_modes;
+    h->npp = h->NT * h->NP;
+    if (h->n_xi * h->NT * 1 > 512) return fail(SG_EUNSUPPORTED, "N_xi * N_t must be <= 512");
+    if (!h->cpl.affine)
+        return fail(SG_EUNSUPPORTED, "the block-Jacobi preconditioner needs an affine coefficient (mu in {0, e_m})");
+    if (h->npp > 256) return fail(SG_EUNSUPPORTED, "Vanka patches larger than 256 DoFs are not supported");
+    {
+        const size_t lds_apply = (size_t)(h->n_xi * h->NT + h->n_mu) * h->NP * sizeof(double);
+        const size_t lds_vanka = 2 * (size_t)h->npp * ((h->n_xi + 3) & ~3) * sizeof(double);
+        if (lds_apply > 160 * 1024 || lds_vanka > 160 * 1024)
+            return fail(SG_EUNSUPPORTED, "problem too large for one workgroup's LDS (N_xi * N_t * (k+1)^d)");
+    }
+    if (!time_matrices(d.time_degree, d.tau, &h->At, &h->Bt))
+        return fail(SG_EINVAL, "time matrices: B_t is not diagonal");
+
+    // coupling lists (full operator and mean block)
+    {
+        std::vector<int> cmu_h(h->cpl.beta.size());
+        for (int row = 0; row < h->n_xi * h->n_mu; ++row)
+            for (int e = h->cpl.ptr[row]; e < h->cpl.ptr[row + 1]; ++e) cmu_h[e] = row % h->n_mu;
+        std::vector<float> w32(h->cpl.w.begin(), h->cpl.w.end());
+        SG_TRY(h->cptr.upload(h->cpl.ptr.data(), h->cpl.ptr.size(), "coupling"));
+        SG_TRY(h->cbeta.upload(h->cpl.beta.data(), h->cpl.beta.size(), "coupling"));
+        SG_TRY(h->cmu.upload(cmu_h.data(), cmu_h.size(), "coupling"));
+        SG_TRY(h->cw64.upload(h->cpl.w.data(), h->cpl.w.size(), "coupling"));
+        SG_TRY(h->cw32.upload(w32.data(), w32.size(), "coupling"));
+        std::vector<int> pm(h->n_xi + 1), bm(h->n_xi), mm(h->n_xi, 0);
+        std::vector<double> wm(h->n_xi, 1.0);
+        std::vector<float> wm32(h->n_xi, 1.0f);
+        for (int a = 0; a <= h->n_xi; ++a) pm[a] = a;
+        for (int a = 0; a < h->n_xi; ++a) bm[a] = a;
+        SG_TRY(h->cptr_m.upload(pm.data(), pm.size(), "coupling"));
+        SG_TRY(h->cbeta_m.upload(bm.data(), bm.size(), "coupling"));
+        SG_TRY(h->cmu_m.upload(mm.data(), mm.size(), "coupling"));
+        SG_TRY(h->cw_m64.upload(wm.data(), wm.size(), "coupling"));
+        SG_TRY(h->cw_m32.upload(wm32.data(), wm32.size(), "coupling"));
+    }
+
+    // 1D tables
+    std::vector<double> gw;
+    const std::vector<double> gq = gauss_points(N1, &gw);
+    const std::vector<double> gll = gll_points(k);
+    std::vector<double> S(N1 * N1), D(N1 * N1), Dn(N1 * N1);
+    for (int q = 0; q < N1; ++q)
+        for (int a = 0; a < N1; ++a) {
+            S[q * N1 + a] = lagrange_value(gll, a, gq[q]);
+            D[q * N1 + a] = lagrange_deriv(gq, a, gq[q]);
+            Dn[q * N1 + a] = lagrange_deriv(gll, a, gq[q]);
+        }
+
+    // levels
+    const int L = d.n_levels;
+    h->lv.resize(L);
+    size_t coef_off = 0;
+    for (int l = 0; l < L; ++l) {
+        Level& lv = h->lv[l];
+        const int n = d.n_cells_1d >> l;
+        lv.g.n = n;
+        lv.g.n1 = n * k + 1;
+        lv.g.n_nodes = 1;
+        lv.g.n_cells = 1;
+        for (int i = 0; i < dim; ++i) {
+            lv.g.n_nodes *= lv.g.n1;
+            lv.g.n_cells *= n;
+        }
+        lv.h = (d.hi - d.lo) / n;
+        lv.len = (long long)h->n_xi * h->NT * lv.g.n_nodes;
+        fill_tables(&lv.tab64, S, D, gw, h->At, h->Bt, N1, h->NT, std::pow(lv.h, dim));
+        fill_tables(&lv.tab32, S, D, gw, h->At, h->Bt, N1, h->NT, std::pow(lv.h, dim));
+        // coefficients, pre-scaled by the Gauss weight and h^(d-2)
+        const size_t per_mode = (size_t)lv.g.n_cells * h->NP;
+        const int nm = (l == 0) ? h->n_mu : 1;
+        std::vector<double> c64((size_t)nm * per_mode);
+        const double hs = std::pow(lv.h, dim - 2);
+        for (int mi = 0; mi < nm; ++mi) {
+            const int mu = (l == 0) ? mi : h->cpl.mu0;
+            const double* src = d.coef_qp + coef_off + (size_t)mu * per_mode;
+            for (size_t c = 0; c < (size_t)lv.g.n_cells; ++c)
+                for (int q = 0; q < h->NP; ++q) {
+                    double wq = hs;
+                    for (int dd = 0, qq = q; dd < dim; ++dd, qq /= N1) wq *= gw[qq % N1];
+                    c64[mi * per_mode + c * h->NP + q] = src[c * h->NP + q] * wq;
+                }
+        }
+        coef_off += (size_t)h->n_mu * per_mode;
+        SG_TRY(lv.coef64.upload(c64.data(), c64.size(), "coefficients"));
+        if (h->mixed) {
+            std::vector<float> c32(c64.begin(), c64.end());
+            SG_TRY(lv.coef32.upload(c32.data(), c32.size(), "coefficients"));
+        }
+        // work vectors
+        SG_TRY(lv.b64.alloc(lv.len, "level vectors"));
+        SG_TRY(lv.x64.alloc(lv.len, "level vectors"));
+        SG_TRY(lv.r64.alloc(lv.len, "level vectors"));
+        if (h->mixed) {
+            SG_TRY(lv.b32.alloc(lv.len, "level vectors"));
+            SG_TRY(lv.x32.alloc(lv.len, "level vectors"));
+            SG_TRY(lv.r32.alloc(lv.len, "level vectors"));
+        }
+    }
+    h->N = h->lv[0].len;
+
+    // element mass matrix (identical on every cell of a level up to h^d)
+    std::vector<double> Me1((size_t)h->NP * h->NP);
+    for (int a = 0; a < h->NP; ++a)
+        for (int b = 0; b < h->NP; ++b) {
+            double s = 0.0;
+            for (int q = 0; q < h->NP; ++q) {
+                double v = 1.0;
+                for (int dd = 0, qq = q, aa = a, bb = b; dd < dim; ++dd, qq /= N1, aa /= N1, bb /= N1)
+                    v *= gw[qq % N1] * S[(qq % N1) * N1 + aa % N1] * S[(qq % N1) * N1 + bb % N1];
+                s += v;
+            }
+            Me1[(size_t)a * h->NP + b] = s;
+        }
+
+    // Vanka patch inverses on every level (device)
+    {
+        PatchTime pt{};
+        for (int i = 0; i < h->NT; ++i) {
+            pt.Bt[i] = h->Bt[i];
+            for (int j = 0; j < h->NT; ++j) pt.At[i * h->NT + j] = h->At[i * h->NT + j];
+        }
+        ElemTables et{};
+        for (int i = 0; i < N1 * N1; ++i) {
+            et.S[i] = S[i];
+            et.Dn[i] = Dn[i];
+        }
+        DevBuf<int> status;
+        int zero = 0;
+        SG_TRY(status.upload(&zero, 1, "status"));
+        for (int l = 0; l < L; ++l) {
+            Level& lv = h->lv[l];
+            DevBuf<double> E, Me;
+            SG_TRY(E.alloc((size_t)lv.g.n_cells * h->NP * h->NP, "element matrices"));
+            std::vector<double> Mel(Me1);
+            const double vol = std::pow(lv.h, dim);
+            for (double& v : Mel) v *= vol;
+            SG_TRY(Me.upload(Mel.data(), Mel.size(), "element matrices"));
+            const double* c0 = lv.coef64.p + (l == 0 ? (size_t)h->cpl.mu0 * lv.g.n_cells * h->NP : 0);
+            SG_HIP(launch_elem_stiffness(dim, k, lv.g, c0, et, E.p, nullptr));
+            const size_t ninv = (size_t)lv.g.n_cells * h->npp * h->npp;
+            const bool want32 = h->mixed && l < L - 1;
+            SG_TRY(lv.inv64.alloc(ninv, "patch inverses"));
+            if (want32) SG_TRY(lv.inv32.alloc(ninv, "patch inverses"));
+            SG_HIP(launch_patch_invert(dim, k, h->NT, lv.g, E.p, Me.p, pt, lv.inv64.p, want32 ? lv.inv32.p : nullptr,
+                                       status.p, nullptr));
+            SG_HIP(hipDeviceSynchronize());
+        }
+        int st = 0;
+        SG_HIP(hipMemcpy(&st, status.p, sizeof(int), hipMemcpyDeviceToHost));
+        if (st) return fail(SG_ESINGULAR, "a Vanka patch matrix is singular");
+    }
+
+    // coarsest level: dense A_0 on interior DoFs, inverted on the host
+    {
+        const Level& lc = h->lv[L - 1];
+        const int n = lc.g.n, n1 = lc.g.n1;
+        std::vector<int> interior_node(lc.g.n_nodes, -1);
+        std::vector<int> inodes;
+        for (long long node = 0; node < lc.g.n_nodes; ++node) {
+            bool bnd = false;
+            long long r = node;
+            for (int dd = 0; dd < dim; ++dd) {
+                const int id = r % n1;
+                r /= n1;
+                bnd |= (id == 0 || id == n1 - 1);
+            }
+            if (!bnd) {
+                interior_node[node] = (int)inodes.size();
+                inodes.push_back((int)node);
+            }
+        }
+        const int ni = (int)inodes.size();
+        h->nint = ni * h->NT;
+        if (h->nint > 12000) return fail(SG_EINVAL, "coarsest level too large for the dense solve; add levels");
+        std::vector<double> A((size_t)h->nint * h->nint, 0.0);
+        const double* c0 = d.coef_qp;
+        size_t off = 0;
+        for (int l = 0; l < L - 1; ++l) off += (size_t)h->n_mu * h->lv[l].g.n_cells * h->NP;
+        c0 += off + (size_t)h->cpl.mu0 * lc.g.n_cells * h->NP;
+        const double vol = std::pow(lc.h, dim), hs = std::pow(lc.h, dim - 2);
+        std::vector<double> Ke((size_t)h->NP * h->NP);
+        for (long long cell = 0; cell < lc.g.n_cells; ++cell) {
+            int cc[3] = {0, 0, 0};
+            long long r = cell;
+            for (int dd = 0; dd < dim; ++dd) { cc[dd] = r % n; r /= n; }
+            std::vector<int> nodes(h->NP);
+            for (int a = 0; a < h->NP; ++a) {
+                long long node = 0, mul = 1;
+                for (int dd = 0, aa = a; dd < dim; ++dd, aa /= N1) { node += (cc[dd] * k + aa % N1) * mul; mul *= n1; }
+                nodes[a] = interior_node[node];
+            }
+            for (int a = 0; a < h->NP; ++a)
+                for (int b = 0; b < h->NP; ++b) {
+                    double s = 0.0;
+                    for (int q = 0; q < h->NP; ++q) {
+                        double wq = hs, gsum = 0.0;
+                        for (int dd = 0, qq = q; dd < dim; ++dd, qq /= N1) wq *= gw[qq % N1];
+                        for (int e = 0; e < dim; ++e) {
+                            double va = 1.0, vb = 1.0;
+                            for (int dd = 0, qq = q, aa = a, bb = b; dd < dim; ++dd, qq /= N1, aa /= N1, bb /= N1) {
+                                va *= (dd == e ? Dn : S)[(qq % N1) * N1 + aa % N1];
+                                vb *= (dd == e ? Dn : S)[(qq % N1) * N1 + bb % N1];
+                            }
+                            gsum += va * vb;
+                        }
+                        s += c0[cell * h->NP + q] * wq * gsum;
+                    }
+                    Ke[(size_t)a * h->NP + b] = s;
+                }
+            for (int a = 0; a < h->NP; ++a) {
+                if (nodes[a] < 0) continue;
+                for (int b = 0; b < h->NP; ++b) {
+                    if (nodes[b] < 0) continue;
+                    const double m = Me1[(size_t)a * h->NP + b] * vol, kv = Ke[(size_t)a * h->NP + b];
+                    for (int i = 0; i < h->NT; ++i)
+                        for (int j = 0; j < h->NT; ++j) {
+                            const size_t row = (size_t)i * ni + nodes[a], col = (size_t)j * ni + nodes[b];
+                            A[row * h->nint + col] += h->At[i * h->NT + j] * m + (i == j ? h->Bt[i] * kv : 0.0);
+                        }
+                }
+            }
+        }
+        if (!invert_dense(A, h->nint)) return fail(SG_ESINGULAR, "coarsest-level matrix is singular");
+        std::vector<double> AT((size_t)h->nint * h->nint);
+        for (int i = 0; i < h->nint; ++i)
+            for (int j = 0; j < h->nint; ++j) AT[(size_t)j * h->nint + i] = A[(size_t)i * h->nint + j];
+        std::vector<int> dofs(h->nint);
+        for (int i = 0; i < h->NT; ++i)
+            for (int a = 0; a < ni; ++a) dofs[i * ni + a] = i * (int)lc.g.n_nodes + inodes[a];
+        SG_TRY(h->coarse_invT.upload(AT.data(), AT.size(), "coarse inverse"));
+        SG_TRY(h->coarse_dofs.upload(dofs.data(), dofs.size(), "coarse dofs"));
+    }
+
+    // transfer stencils and temporaries
+    size_t tmax = 0;
+    for (int l = 0; l + 1 < L; ++l) {
+        Level& lf = h->lv[l];
+        const int nc = h->lv[l + 1].g.n, nc1 = h->lv[l + 1].g.n1, nf1 = lf.g.n1;
+        std::vector<int> pidx;
+        std::vector<double> pw;
+        prolong_1d(nc, k, gll, &pidx, &pw);
+        lf.wp = k + 1;
+        // transpose: for each coarse node the fine nodes with a nonzero weight
+        std::vector<std::vector<std::pair<int, double>>> cols(nc1);
+        for (int f = 0; f < nf1; ++f)
+            for (int a = 0; a <= k; ++a) {
+                const double v = pw[f * (k + 1) + a];
+                if (v != 0.0) cols[pidx[f * (k + 1) + a]].push_back({f, v});
+            }
+        int wr = 1;
+        for (auto& c : cols) wr = std::max<int>(wr, (int)c.size());
+        lf.wr = wr;
+        std::vector<int> ridx((size_t)nc1 * wr, 0);
+        std::vector<double> rw((size_t)nc1 * wr, 0.0);
+        for (int c = 0; c < nc1; ++c)
+            for (size_t e = 0; e < cols[c].size(); ++e) {
+                ridx[c * wr + e] = cols[c][e].first;
+                rw[c * wr + e] = cols[c][e].second;
+            }
+        SG_TRY(lf.p_idx.upload(pidx.data(), pidx.size(), "transfer"));
+        SG_TRY(lf.p_w64.upload(pw.data(), pw.size(), "transfer"));
+        SG_TRY(lf.r_idx.upload(ridx.data(), ridx.size(), "transfer"));
+        SG_TRY(lf.r_w64.upload(rw.data(), rw.size(), "transfer"));
+        std::vector<float> pw32(pw.begin(), pw.end()), rw32(rw.begin(), rw.end());
+        SG_TRY(lf.p_w32.upload(pw32.data(), pw32.size(), "transfer"));
+        SG_TRY(lf.r_w32.upload(rw32.data(), rw32.size(), "transfer"));
+        size_t inter = (size_t)h->n_xi * h->NT * nf1 * (size_t)(dim == 3 ? (size_t)nf1 * nc1 : nc1);
+        tmax = std::max(tmax, inter);
+    }
+    if (tmax) {
+        SG_TRY(h->t64a.alloc(tmax, "transfer temporaries"));
+        SG_TRY(h->t64b.alloc(tmax, "transfer temporaries"));
+        if (h->mixed) {
+            SG_TRY(h->t32a.alloc(tmax, "transfer temporaries"));
+            SG_TRY(h->t32b.alloc(tmax, "transfer temporaries"));
+        }
+    }
+    // Krylov workspace
+    h->restart = d.fgmres_restart;
+    SG_TRY(h->V.alloc((size_t)(h->restart + 1) * h->N, "Krylov basis"));
+    SG_TRY(h->Z.alloc((size_t)h->restart * h->N, "Krylov basis"));
+    SG_TRY(h->w1.alloc(h->N, "Krylov work"));
+    SG_TRY(h->w2.alloc(h->N, "Krylov work"));
+    SG_TRY(h->partial.alloc((size_t)kDotBlocks * (h->restart + 2), "partials"));
+    SG_TRY(h->dscal.alloc(3 * 80, "scalars"));
+    SG_HIP(hipDeviceSynchronize());
+    return SG_OK;
+}
+
+// ---- operator helpers -------------------------------------------------------------------------------
+template <typename T>
+struct Prec;
+template <>
+struct Prec<double> {
+    static const Tables<double>* tab(const Level& l) { return &l.tab64; }
+    static const double* coef(const Level& l) { return l.coef64.p; }
+    static const double* cw(const sg_handle h) { return h->cw64.p; }
+    static const double* cwm(const sg_handle h) { return h->cw_m64.p; }
+    static const double* inv(const Level& l) { return l.inv64.p; }
+    static double* b(Level& l) { return l.b64.p; }
+    static double* x(Level& l) { return l.x64.p; }
+    static double* r(Level& l) { return l.r64.p; }
+    static double* ta(sg_handle h) { return h->t64a.p; }
+    static double* tb(sg_handle h) { return h->t64b.p; }
+    static const double* pw(const Level& l) { return l.p_w64.p; }
+    static const double* rw(const Level& l) { return l.r_w64.p; }
+};
+template <>
+struct Prec<float> {
+    static const Tables<float>* tab(const Level& l) { return &l.tab32; }
+    static const float* coef(const Level& l) { return l.coef32.p; }
+    static const float* cw(const sg_handle h) { return h->cw32.p; }
+    static const float* cwm(const sg_handle h) { return h->cw_m32.p; }
+    static const float* inv(const Level& l) { return l.inv32.p; }
+    static float* b(Level& l) { return l.b32.p; }
+    static float* x(Level& l) { return l.x32.p; }
+    static float* r(Level& l) { return l.r32.p; }
+    static float* ta(sg_handle h) { return h->t32a.p; }
+    static float* tb(sg_handle h) { return h->t32b.p; }
+    static const float* pw(const Level& l) { return l.p_w32.p; }
+    static const float* rw(const Level& l) { return l.r_w32.p; }
+};
+
+int pick_cpb(int nc, int n_mu, int np, size_t elem) {
+    // as many cells per workgroup as fit 512 threads and ~64 KiB of LDS
+    int cpb = std::max(1, 512 / nc);
+    while (cpb > 1 && (size_t)(nc + n_mu) * np * cpb * elem > 64 * 1024) --cpb;
+    return cpb;
+}
+
+template <typename T>
+ApplyOp<T> make_op(const sg_handle h, int level, bool full) {
+    const Level& lv = h->lv[level];
+    ApplyOp<T> op{};
+    op.dim = h->d.dim;
+    op.k = h->d.fe_degree;
+    op.nt = h->NT;
+    op.g = lv.g;
+    op.n_xi = h->n_xi;
+    op.coef_mode_stride = lv.g.n_cells * h->NP;
+    op.tables = Prec<T>::tab(lv);
+    if (full) {
+        op.n_mu = h->n_mu;
+        op.coef = Prec<T>::coef(lv);
+        op.cptr = h->cptr.p;
+        op.cbeta = h->cbeta.p;
+        op.cmu = h->cmu.p;
+        op.cw = Prec<T>::cw(h);
+    } else {
+        op.n_mu = 1;
+        op.coef = Prec<T>::coef(lv) + (level == 0 ? (size_t)h->cpl.mu0 * op.coef_mode_stride : 0);
+        op.cptr = h->cptr_m.p;
+        op.cbeta = h->cbeta_m.p;
+        op.cmu = h->cmu_m.p;
+        op.cw = Prec<T>::cwm(h);
+    }
+    op.cells_per_block = pick_cpb(h->n_xi * h->NT, op.n_mu, h->NP, sizeof(T));
+    return op;
+}
+
+template <typename T>
+sg_status smooth_level(sg_handle h, int l, const T* b, T* x, int sweeps, bool x_is_zero, hipStream_t s) {
+    Level& lv = h->lv[l];
+    const ApplyOp<T> op = make_op<T>(h, l, false);
+    const T* inv = Prec<T>::inv(lv);
+    for (int it = 0; it < sweeps; ++it) {
+        const T* r = b;   // with x = 0 the residual b - A_0 x is b itself
+        if (!(x_is_zero && it == 0)) {
+            SG_HIP(launch_apply<T>(op, x, Prec<T>::r(lv), b, s));
+            r = Prec<T>::r(lv);
+        }
+        SG_HIP(launch_vanka_apply<T>(h->d.dim, h->d.fe_degree, h->NT, lv.g, h->n_xi, inv, r, b, x,
+                                     (T)h->d.vanka_omega, s));
+    }
+    return SG_OK;
+}
+
+int dims_of(const Grid& g, int dim, int* out) {
+    for (int i = 0; i < 3; ++i) out[i] = i < dim ? g.n1 : 1;
+    return 0;
+}
+
+// b_c = R r_f (restriction), fine level l -> coarse level l+1
+template <typename T>
+sg_status restrict_to(sg_handle h, int l, const T* rf, T* bc, hipStream_t s) {
+    const int dim = h->d.dim, nc = h->n_xi * h->NT;
+    const Level& lf = h->lv[l];
+    const Level& lc = h->lv[l + 1];
+    int cur[3];
+    dims_of(lf.g, dim, cur);
+    const T* in = rf;
+    T* bufs[2] = {Prec<T>::ta(h), Prec<T>::tb(h)};
+    for (int dir = 0; dir < dim; ++dir) {
+        int out[3] = {cur[0], cur[1], cur[2]};
+        out[dir] = lc.g.n1;
+        T* o = (dir == dim - 1) ? bc : bufs[dir % 2];
+        SG_HIP(launch_transfer_1d<T>(dim, nc, cur, out, dir, lf.r_idx.p, Prec<T>::rw(lf), lf.wr, in, o, false, s));
+        in = o;
+        for (int i = 0; i < 3; ++i) cur[i] = out[i];
+    }
+    return SG_OK;
+}
+
+// x_f += P x_c (prolongation), coarse level l+1 -> fine level l
+template <typename T>
+sg_status prolong_add(sg_handle h, int l, const T* xc, T* xf, hipStream_t s) {
+    const int dim = h->d.dim, nc = h->n_xi * h->NT;
+    const Level& lf = h->lv[l];
+    const Level& lc = h->lv[l + 1];
+    int cur[3];
+    dims_of(lc.g, dim, cur);
+    const T* in = xc;
+    T* bufs[2] = {Prec<T>::ta(h), Prec<T>::tb(h)};
+    for (int dir = 0; dir < dim; ++dir) {
+        int out[3] = {cur[0], cur[1], cur[2]};
+        out[dir] = lf.g.n1;
+        const bool last = dir == dim - 1;
+        T* o = last ? xf : bufs[dir % 2];
+        SG_HIP(launch_transfer_1d<T>(dim, nc, cur, out, dir, lf.p_idx.p, Prec<T>::pw(lf), lf.wp, in, o, last, s));
+        in = o;
+        for (int i = 0; i < 3; ++i) cur[i] = out[i];
+    }
+    return SG_OK;
+}
+
+template <typename T>
+sg_status vcycle_level(sg_handle h, int l, const T* b, T* x, hipStream_t s) {
+    const int L = h->d.n_levels;
+    Level& lv = h->lv[l];
+    if (l == L - 1) {
+        SG_HIP(launch_coarse_solve<T>(h->coarse_invT.p, h->nint, h->coarse_dofs.p, h->n_xi, (long long)h->NT * lv.g.n_nodes,
+                                      b, x, s));
+        return SG_OK;
+    }
+    SG_HIP(launch_fill<T>(x, T(0), lv.len, s));
+    SG_TRY(smooth_level<T>(h, l, b, x, h->d.pre_smooth, true, s));
+    const ApplyOp<T> op = make_op<T>(h, l, false);
+    SG_HIP(launch_apply<T>(op, x, Prec<T>::r(lv), b, s));
+    Level& lc = h->lv[l + 1];
+    SG_TRY(restrict_to<T>(h, l, Prec<T>::r(lv), Prec<T>::b(lc), s));
+    SG_TRY(vcycle_level<T>(h, l + 1, Prec<T>::b(lc), Prec<T>::x(lc), s));
+    SG_TRY(prolong_add<T>(h, l, Prec<T>::x(lc), x, s));
+    SG_TRY(smooth_level<T>(h, l, b, x, h->d.post_smooth, false, s));
+    return SG_OK;
+}
+
+sg_status vcycle(sg_handle h, const double* r, double* z, hipStream_t s) {
+    if (!h->mixed) return vcycle_level<double>(h, 0, r, z, s);
+    Level& l0 = h->lv[0];
+    SG_HIP((launch_convert<double, float>(r, l0.b32.p, l0.len, s)));
+    SG_TRY(vcycle_level<float>(h, 0, l0.b32.p, l0.x32.p, s));
+    SG_HIP((launch_convert<float, double>(l0.x32.p, z, l0.len, s)));
+    return SG_OK;
+}
+
+bool overlap(const void* a, const void* b, size_t bytes) {
+    const char* pa = (const char*)a;
+    const char* pb = (const char*)b;
+    return pa < pb + bytes && pb < pa + bytes;
+}
+
+double dev_dot_sync(sg_handle h, const double* a, const double* b, long long n, hipStream_t s, sg_status* st) {
+    double out = 0.0;
+    *st = SG_OK;
+    if (launch_multidot(a, 0, 1, b, n, h->partial.p, kDotBlocks, s) != hipSuccess ||
+        launch_reduce_partials(h->partial.p, kDotBlocks, 1, h->dscal.p, s) != hipSuccess ||
+        hipMemcpyAsync(&out, h->dscal.p, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        *st = fail(SG_EHIP, "dot product failed");
+    }
+    return out;
+}
+
+}  // namespace
+
+extern "C" {
+
+sg_status sg_create(const sg_problem_desc* desc, sg_handle* out) {
+    if (!out) return fail(SG_EINVAL, "out is NULL");
+    *out = nullptr;
+    SG_TRY(validate(desc));
+    std::unique_ptr<sg_handle_s> h(new (std::nothrow) sg_handle_s());
+    if (!h) return fail(SG_ENOMEM, "host allocation failed");
+    h->d = *desc;
+    h->coef_mu.assign(desc->coef_mu, desc->coef_mu + (size_t)desc->n_coef_modes * desc->n_vars);
+    h->d.coef_mu = h->coef_mu.data();
+    try {
+        sg_status s = build(h.get());
+        h->d.coef_qp = nullptr;   // host array not retained
+        if (s != SG_OK) return s;
+    } catch (const std::bad_alloc&) {
+        return fail(SG_ENOMEM, "host allocation failed during set-up");
+    }
+    *out = h.release();
+    return SG_OK;
+}
+
+sg_status sg_destroy(sg_handle h) {
+    if (!h) return SG_OK;
+    (void)hipDeviceSynchronize();
+    delete h;
+    return SG_OK;
+}
+
+sg_status sg_vector_length(sg_handle h, int level, long long* n) {
+    if (!h || !n) return fail(SG_EINVAL, "null argument");
+    if (level < 0 || level >= h->d.n_levels) return fail(SG_EINVAL, "level out of range");
+    *n = h->lv[level].len;
+    return SG_OK;
+}
+
+sg_status sg_operator_apply(sg_handle h, const double* x, double* y, void* hip_stream) {
+    if (!h || !x || !y) return fail(SG_EINVAL, "null argument");
+    if (overlap(x, y, h->N * sizeof(double))) return fail(SG_EINVAL, "x and y overlap");
+    const ApplyOp<double> op = make_op<double>(h, 0, true);
+    SG_HIP(launch_apply<double>(op, x, y, nullptr, (hipStream_t)hip_stream));
+    return SG_OK;
+}
+
+sg_status sg_vanka_smooth(sg_handle h, int level, const double* b, double* x, int sweeps, void* hip_stream) {
+    if (!h || !b || !x) return fail(SG_EINVAL, "null argument");
+    if (level < 0 || level >= h->d.n_levels) return fail(SG_EINVAL, "level out of range");
+    if (sweeps < 0) return fail(SG_EINVAL, "sweeps must be >= 0");
+    Level& lv = h->lv[level];
+    if (overlap(b, x, lv.len * sizeof(double))) return fail(SG_EINVAL, "b and x overlap");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const bool use32 = h->mixed && level < h->d.n_levels - 1;
+    if (!use32) return smooth_level<double>(h, level, b, x, sweeps, false, s);
+    SG_HIP((launch_convert<double, float>(b, lv.b32.p, lv.len, s)));
+    SG_HIP((launch_convert<double, float>(x, lv.x32.p, lv.len, s)));
+    SG_TRY(smooth_level<float>(h, level, lv.b32.p, lv.x32.p, sweeps, false, s));
+    SG_HIP((launch_convert<float, double>(lv.x32.p, x, lv.len, s)));
+    return SG_OK;
+}
+
+sg_status gmg_vcycle(sg_handle h, const double* r, double* z, void* hip_stream) {
+    if (!h || !r || !z) return fail(SG_EINVAL, "null argument");
+    if (overlap(r, z, h->N * sizeof(double))) return fail(SG_EINVAL, "r and z overlap");
+    return vcycle(h, r, z, (hipStream_t)hip_stream);
+}
+
+sg_status fgmres_solve_slab(sg_handle h, const double* b, double* x, double rtol, int max_iter, sg_solve_info* info,
+                            void* hip_stream) {
+    if (!h || !b || !x) return fail(SG_EINVAL, "null argument");
+    if (!(rtol > 0.0) || max_iter < 1) return fail(SG_EINVAL, "rtol > 0 and max_iter >= 1 required");
+    if (overlap(b, x, h->N * sizeof(double))) return fail(SG_EINVAL, "b and x overlap");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const long long n = h->N;
+    const int m = h->restart;
+    sg_solve_info inf{};
+    std::vector<hipEvent_t> ev;
+    auto mark = [&](std::vector<hipEvent_t>& v) -> hipError_t {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        v.push_back(e);
+        return hipEventRecord(e, s);
+    };
+    std::vector<hipEvent_t> ev_apply, ev_prec, ev_total;
+    struct EvGuard {
+        std::vector<hipEvent_t>* v[3];
+        ~EvGuard() { for (auto* p : v) for (auto e : *p) (void)hipEventDestroy(e); }
+    } guard{{&ev_apply, &ev_prec, &ev_total}};
+    SG_HIP(mark(ev_total));
+    const ApplyOp<double> op = make_op<double>(h, 0, true);
+    double* V = h->V.p;
+    double* Z = h->Z.p;
+    sg_status st;
+    const double bnorm = std::sqrt(dev_dot_sync(h, b, b, n, s, &st));
+    if (st != SG_OK) return st;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    double hscal[3 * 80];
+    sg_status result = SG_NOT_CONVERGED;
+    if (bnorm == 0.0) {
+        SG_HIP(launch_fill<double>(x, 0.0, n, s));
+        inf.converged = 1;
+        result = SG_OK;
+    } else {
+        while (true) {
+            // true residual r = b - AA x into V[0]
+            SG_HIP(mark(ev_apply));
+            SG_HIP(launch_apply<double>(op, x, V, b, s));
+            SG_HIP(mark(ev_apply));
+            inf.applies++;
+            const double beta = std::sqrt(dev_dot_sync(h, V, V, n, s, &st));
+            if (st != SG_OK) return st;
+            inf.rel_residual_true = beta / bnorm;
+            if (beta / bnorm <= rtol) { inf.converged = 1; result = SG_OK; break; }
+            if (inf.iterations >= max_iter) break;
+            inf.restarts++;
+            SG_HIP(launch_axpby(1.0 / beta, V, 0.0, nullptr, V, n, s));
+            std::fill(H.begin(), H.end(), 0.0);
+            std::fill(g.begin(), g.end(), 0.0);
+            g[0] = beta;
+            int kdim = 0;
+            for (int j = 0; j < m; ++j) {
+                double* vj = V + (size_t)j * n;
+                double* zj = Z + (size_t)j * n;
+                SG_HIP(mark(ev_prec));
+                SG_TRY(vcycle(h, vj, zj, s));
+                SG_HIP(mark(ev_prec));
+                inf.vcycles++;
+                SG_HIP(mark(ev_apply));
+                SG_HIP(launch_apply<double>(op, zj, h->w1.p, nullptr, s));
+                SG_HIP(mark(ev_apply));
+                inf.applies++;
+                const int kk = j + 1;
+                double* d_h1 = h->dscal.p;
+                double* d_h2 = h->dscal.p + 80;
+                double* d_nr = h->dscal.p + 160;
+                double* vnext = V + (size_t)(j + 1) * n;
+                // CGS2: h1 = V^T w; w' = w - V h1, h2 = V^T w'; w'' = w' - V h2, |w''|^2
+                SG_HIP(launch_multidot(V, n, kk, h->w1.p, n, h->partial.p, kDotBlocks, s));
+                SG_HIP(launch_reduce_partials(h->partial.p, kDotBlocks, kk, d_h1, s));
+                SG_HIP(launch_update_dot(V, n, kk, d_h1, h->w1.p, h->w2.p, n, h->partial.p, kDotBlocks, true, s));
+                SG_HIP(launch_reduce_partials(h->partial.p, kDotBlocks, kk, d_h2, s));
+                SG_HIP(launch_update_dot(V, n, kk, d_h2, h->w2.p, vnext, n, h->partial.p, kDotBlocks, false, s));
+                SG_HIP(launch_reduce_partials(h->partial.p, kDotBlocks, 1, d_nr, s));
+                SG_HIP(hipMemcpyAsync(hscal, h->dscal.p, sizeof(double) * 240, hipMemcpyDeviceToHost, s));
+                SG_HIP(hipStreamSynchronize(s));
+                const double hn = std::sqrt(hscal[160]);
+                for (int i = 0; i < kk; ++i) H[(size_t)i * m + j] = hscal[i] + hscal[80 + i];
+                H[(size_t)(j + 1) * m + j] = hn;
+                for (int i = 0; i < j; ++i) {
+                    const double t = cs[i] * H[(size_t)i * m + j] + sn[i] * H[(size_t)(i + 1) * m + j];
+                    H[(size_t)(i + 1) * m + j] = -sn[i] * H[(size_t)i * m + j] + cs[i] * H[(size_t)(i + 1) * m + j];
+                    H[(size_t)i * m + j] = t;
+                }
+                const double den = std::hypot(H[(size_t)j * m + j], H[(size_t)(j + 1) * m + j]);
+                cs[j] = H[(size_t)j * m + j] / den;
+                sn[j] = H[(size_t)(j + 1) * m + j] / den;
+                H[(size_t)j * m + j] = den;
+                H[(size_t)(j + 1) * m + j] = 0.0;
+                g[j + 1] = -sn[j] * g[j];
+                g[j] = cs[j] * g[j];
+                inf.iterations++;
+                kdim = j + 1;
+                if (hn == 0.0 || std::fabs(g[j + 1]) / bnorm <= rtol || inf.iterations >= max_iter) break;
+                SG_HIP(launch_axpby(1.0 / hn, vnext, 0.0, nullptr, vnext, n, s));
+            }
+            for (int i = kdim - 1; i >= 0; --i) {
+                double acc = g[i];
+                for (int c = i + 1; c < kdim; ++c) acc -= H[(size_t)i * m + c] * y[c];
+                y[i] = acc / H[(size_t)i * m + i];
+            }
+            SG_HIP(hipMemcpyAsync(h->dscal.p, y.data(), sizeof(double) * kdim, hipMemcpyHostToDevice, s));
+            SG_HIP(launch_multi_axpy(Z, n, kdim, h->dscal.p, x, n, s));
+        }
+    }
+    SG_HIP(mark(ev_total));
+    SG_HIP(hipStreamSynchronize(s));
+    auto sum_pairs = [](const std::vector<hipEvent_t>& v) {
+        double t = 0.0;
+        for (size_t i = 0; i + 1 < v.size(); i += 2) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, v[i], v[i + 1]) == hipSuccess) t += ms;
+        }
+        return t;
+    };
+    inf.t_apply_ms = sum_pairs(ev_apply);
+    inf.t_prec_ms = sum_pairs(ev_prec);
+    inf.t_total_ms = sum_pairs(ev_total);
+    inf.work_proxy = (double)n * inf.vcycles;
+    if (info) *info = inf;
+    if (result == SG_NOT_CONVERGED) g_last_error = "FGMRES did not reach the tolerance within max_iter";
+    return result;
+}
+
+sg_status sg_quadrature_points(const sg_problem_desc* d, int level, double* xyz) {
+    if (!d || !xyz) return fail(SG_EINVAL, "null argument");
+    if (d->dim != 2 && d->dim != 3) return fail(SG_EINVAL, "dim must be 2 or 3");
+    if (d->fe_degree < 1 || d->fe_degree > 4 || d->n_cells_1d < 1) return fail(SG_EINVAL, "bad mesh");
+    if (level < 0 || (d->n_cells_1d >> level) < 1 || (d->n_cells_1d % (1 << level)) != 0)
+        return fail(SG_EINVAL, "level out of range");
+    const int n = d->n_cells_1d >> level, N1 = d->fe_degree + 1, dim = d->dim;
+    const double h = (d->hi - d->lo) / n;
+    std::vector<double> gw;
+    const std::vector<double> gq = gauss_points(N1, &gw);
+    const int NP = ipow_h(N1, dim);
+    long long ncell = 1;
+    for (int i = 0; i < dim; ++i) ncell *= n;
+    for (long long c = 0; c < ncell; ++c) {
+        int cc[3] = {0, 0, 0};
+        long long r = c;
+        for (int i = 0; i < dim; ++i) { cc[i] = r % n; r /= n; }
+        for (int q = 0; q < NP; ++q)
+            for (int i = 0, qq = q; i < dim; ++i, qq /= N1) xyz[(c * NP + q) * dim + i] = d->lo + h * (cc[i] + gq[qq % N1]);
+    }
+    return SG_OK;
+}
+
+const char* sg_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

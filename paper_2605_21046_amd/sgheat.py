@@ -1,0 +1,221 @@
+"""Python binding of libsgheat.so (include/sgheat.h): argument marshalling only.
+
+Every numerical step runs in the library's gfx950 kernels; PyTorch provides device memory and
+the current HIP stream.  Importing this module loads the library and fails loudly if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsgheat.so")
+
+SG_OK, SG_NOT_CONVERGED = 0, 1
+SG_FP64, SG_MIXED = 0, 1
+_STATUS = {0: "SG_OK", 1: "SG_NOT_CONVERGED", -1: "SG_EINVAL", -2: "SG_ENOMEM", -3: "SG_EHIP",
+           -4: "SG_ESINGULAR", -5: "SG_EUNSUPPORTED"}
+EXPORTS = ["sg_create", "sg_destroy", "sg_vector_length", "sg_operator_apply", "sg_vanka_smooth",
+           "gmg_vcycle", "fgmres_solve_slab", "sg_quadrature_points", "sg_last_error"]
+
+
+class SgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n_cells_1d", ctypes.c_int), ("lo", ctypes.c_double),
+                ("hi", ctypes.c_double), ("fe_degree", ctypes.c_int), ("time_degree", ctypes.c_int),
+                ("tau", ctypes.c_double), ("n_vars", ctypes.c_int), ("chaos_degree", ctypes.c_int),
+                ("n_coef_modes", ctypes.c_int), ("coef_mu", ctypes.POINTER(ctypes.c_int)),
+                ("coef_qp", ctypes.POINTER(ctypes.c_double)), ("n_levels", ctypes.c_int),
+                ("pre_smooth", ctypes.c_int), ("post_smooth", ctypes.c_int), ("vanka_omega", ctypes.c_double),
+                ("fgmres_restart", ctypes.c_int), ("precision", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("vcycles", ctypes.c_int),
+                ("applies", ctypes.c_int), ("converged", ctypes.c_int), ("rel_residual_true", ctypes.c_double),
+                ("t_apply_ms", ctypes.c_double), ("t_prec_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
+                ("work_proxy", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(path)
+    P, I, D, V = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+    lib.sg_create.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(P)]
+    lib.sg_destroy.argtypes = [P]
+    lib.sg_vector_length.argtypes = [P, I, ctypes.POINTER(ctypes.c_longlong)]
+    lib.sg_operator_apply.argtypes = [P, V, V, V]
+    lib.sg_vanka_smooth.argtypes = [P, I, V, V, I, V]
+    lib.gmg_vcycle.argtypes = [P, V, V, V]
+    lib.fgmres_solve_slab.argtypes = [P, V, V, D, I, ctypes.POINTER(SolveInfo), V]
+    lib.sg_quadrature_points.argtypes = [ctypes.POINTER(ProblemDesc), I, ctypes.POINTER(ctypes.c_double)]
+    lib.sg_last_error.restype = ctypes.c_char_p
+    for f in ["sg_create", "sg_destroy", "sg_vector_length", "sg_operator_apply", "sg_vanka_smooth", "gmg_vcycle",
+              "fgmres_solve_slab", "sg_quadrature_points"]:
+        getattr(lib, f).restype = ctypes.c_int
+    return lib
+
+
+_lib = load_library()
+
+
+def _check(status: int, allow_not_converged: bool = False) -> int:
+    if status == SG_OK or (allow_not_converged and status == SG_NOT_CONVERGED):
+        return status
+    raise SgError(status, _lib.sg_last_error().decode())
+
+
+@dataclass
+class Spec:
+    """Sizes of one slab problem (names as in the paper)."""
+    dim: int
+    n_cells_1d: int
+    fe_degree: int
+    time_degree: int
+    tau: float
+    n_vars: int
+    chaos_degree: int
+    n_levels: int
+    lo: float = 0.0
+    hi: float = 1.0
+    pre_smooth: int = 1
+    post_smooth: int = 1
+    vanka_omega: float = 1.0
+    fgmres_restart: int = 30
+
+
+def _desc(spec, precision=SG_FP64):
+    d = ProblemDesc()
+    for name in ["dim", "n_cells_1d", "fe_degree", "time_degree", "n_vars", "chaos_degree", "n_levels",
+                 "pre_smooth", "post_smooth", "fgmres_restart"]:
+        setattr(d, name, int(getattr(spec, name)))
+    for name in ["lo", "hi", "tau", "vanka_omega"]:
+        setattr(d, name, float(getattr(spec, name)))
+    d.precision = int(precision)
+    return d
+
+
+def quadrature_points(spec, level: int) -> np.ndarray:
+    """Physical Gauss points of a level, [n_cells, (k+1)^d, d] (where coef_qp is sampled)."""
+    d = _desc(spec)
+    n = spec.n_cells_1d >> level
+    npts = (spec.fe_degree + 1) ** spec.dim
+    out = np.zeros((n ** spec.dim, npts, spec.dim))
+    _check(_lib.sg_quadrature_points(ctypes.byref(d), level, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
+
+
+def _ptr(t, n, name):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Problem:
+    """One slab problem on the GPU (a handle of libsgheat.so)."""
+
+    def __init__(self, spec, coef_mu, coef_qp_levels, precision=SG_FP64):
+        self.spec = spec
+        mus = np.ascontiguousarray(np.asarray(coef_mu, dtype=np.int32).reshape(-1, spec.n_vars))
+        coef = np.ascontiguousarray(np.concatenate([np.asarray(c, np.float64).reshape(-1) for c in coef_qp_levels]))
+        d = _desc(spec, precision)
+        d.n_coef_modes = mus.shape[0]
+        d.coef_mu = mus.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        d.coef_qp = coef.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        h = ctypes.c_void_p()
+        _check(_lib.sg_create(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self.precision = precision
+        self.shape = (math_comb(spec.n_vars + spec.chaos_degree, spec.chaos_degree), spec.time_degree + 1,
+                      (spec.n_cells_1d * spec.fe_degree + 1) ** spec.dim)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.sg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def n(self, level: int = 0) -> int:
+        v = ctypes.c_longlong()
+        _check(_lib.sg_vector_length(self._h, level, ctypes.byref(v)))
+        return v.value
+
+    def apply(self, x, y=None, stream=None):
+        import torch
+        if y is None:
+            y = torch.empty_like(x)
+        n = self.n(0)
+        _check(_lib.sg_operator_apply(self._h, _ptr(x, n, "x"), _ptr(y, n, "y"), _stream(stream)))
+        return y
+
+    def vanka_smooth(self, level, b, x, sweeps=1, stream=None):
+        n = self.n(level)
+        _check(_lib.sg_vanka_smooth(self._h, level, _ptr(b, n, "b"), _ptr(x, n, "x"), sweeps, _stream(stream)))
+        return x
+
+    def vcycle(self, r, z=None, stream=None):
+        import torch
+        if z is None:
+            z = torch.empty_like(r)
+        n = self.n(0)
+        _check(_lib.gmg_vcycle(self._h, _ptr(r, n, "r"), _ptr(z, n, "z"), _stream(stream)))
+        return z
+
+    def solve(self, b, x=None, rtol=1e-8, max_iter=1000, stream=None):
+        import torch
+        if x is None:
+            x = torch.zeros_like(b)
+        n = self.n(0)
+        info = SolveInfo()
+        st = _lib.fgmres_solve_slab(self._h, _ptr(b, n, "b"), _ptr(x, n, "x"), float(rtol), int(max_iter),
+                                    ctypes.byref(info), _stream(stream))
+        _check(st, allow_not_converged=True)
+        return x, info.as_dict()
+
+
+def math_comb(a, b):
+    import math
+    return math.comb(a, b)
+
+
+def problem_from_workload(w, precision=SG_FP64, **overrides):
+    """Problem for an sg_inputs.Workload, with coefficients sampled at this library's Gauss points."""
+    import sg_inputs
+    spec = Spec(w.dim, w.n_cells_1d, w.fe_degree, w.time_degree, w.tau, w.n_vars, w.chaos_degree, w.n_levels,
+                w.lo, w.hi, w.pre_smooth, w.post_smooth, w.vanka_omega, w.fgmres_restart)
+    for k, v in overrides.items():
+        setattr(spec, k, v)
+    mus, coef = sg_inputs.coef_qp_levels(w, lambda lvl: quadrature_points(spec, lvl))
+    return Problem(spec, mus, coef, precision)

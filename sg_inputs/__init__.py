@@ -124,3 +124,19 @@ def coefficient_modes(w: Workload, x: np.ndarray):
 def uniform_vector(n: int, seed: int) -> np.ndarray:
     """FP64 vector of ``n`` entries drawn from U[-1, 1] with numpy's PCG64 generator."""
     return np.random.Generator(np.random.PCG64(seed)).uniform(-1.0, 1.0, size=n)
+
+
+def coef_qp_levels(w: Workload, points_fn):
+    """Coefficient values for every multigrid level, in the layout the slab library takes.
+
+    ``points_fn(level)`` returns the physical quadrature points of that level as an array
+    [n_cells, n_points, d]; each side (oracle or HIP library) supplies its own.
+    Returns (mu_list, coef) with coef[level] of shape [n_mu, n_cells, n_points].
+    """
+    mus, out = None, []
+    for level in range(w.n_levels):
+        pts = np.asarray(points_fn(level))
+        m, vals = coefficient_modes(w, pts)
+        mus = m
+        out.append(np.ascontiguousarray(vals, dtype=np.float64))
+    return mus, out

@@ -1,0 +1,215 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle, on an MI355X.
+
+Tolerances:
+  * operator apply, FP64: ||y_gpu - y_oracle||_inf <= 1e-12 ||y_oracle||_inf (summation order only);
+  * Vanka sweep and V-cycle, FP64: 1e-11 relative (the patch inverse is applied as a product instead
+    of two triangular solves; the patch condition numbers here stay below 1e4);
+  * FGMRES: true relative residual <= rtol, recomputed by the oracle, and the solution within
+    1e-6 of the direct sparse solve (condition number times the tolerance);
+  * mixed precision: same residual bar (checked in FP64); the error against the FP64 solution is
+    printed, not asserted.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import sg_inputs
+from oracle.krylov import fgmres
+from oracle.multigrid import hierarchy_from_workload
+from oracle.rows import RowOracle
+from oracle.slab import from_workload
+
+pytestmark = pytest.mark.gpu
+
+SMALL = ["c1", "t2q1", "t2q2", "t2q3", "t3q1", "t3q2", "t3q3", "t3q4"]
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _gpu(w, precision=0, **kw):
+    from paper_2605_21046_amd import sgheat
+    return sgheat.problem_from_workload(w, precision, **kw)
+
+
+def _to_gpu(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _rel_inf(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_apply_matches_oracle(torch_cuda, name):
+    torch = torch_cuda
+    w = sg_inputs.WORKLOADS[name]
+    print(f"apply parity {name}", flush=True)
+    P = from_workload(w)
+    G = _gpu(w)
+    assert G.n(0) == P.n
+    x = sg_inputs.uniform_vector(P.n, sg_inputs.SEED_APPLY_INPUT)
+    y = G.apply(_to_gpu(torch, x))
+    torch.cuda.synchronize()
+    assert _rel_inf(y.cpu().numpy(), P.apply_route2(x)) <= 1e-12
+
+
+def test_apply_twice_is_deterministic(torch_cuda):
+    torch = torch_cuda
+    w = sg_inputs.WORKLOADS["t3q2"]
+    G = _gpu(w)
+    x = _to_gpu(torch, sg_inputs.uniform_vector(G.n(0), 3))
+    y1 = G.apply(x).clone()
+    y2 = G.apply(x)
+    assert torch.equal(y1, y2)
+
+
+@pytest.mark.parametrize("name", ["c2", "c3"])
+def test_apply_full_size_sampled_rows(torch_cuda, name):
+    """Full benchmark sizes: GPU apply vs the oracle's row-by-row definition on sampled rows,
+    including Dirichlet rows, corners of the mode/time ranges and ragged positions."""
+    torch = torch_cuda
+    w = sg_inputs.WORKLOADS[name]
+    print(f"full-size apply {name}", flush=True)
+    G = _gpu(w)
+    n = G.n(0)
+    assert n == w.n_dofs(0)
+    x = sg_inputs.uniform_vector(n, sg_inputs.SEED_APPLY_INPUT)
+    xg = _to_gpu(torch, x)
+    y = G.apply(xg).cpu().numpy()
+    mus, _ = sg_inputs.coefficient_modes(w, np.zeros((1, w.dim)))
+    R = RowOracle(w.dim, w.n_cells_1d, w.fe_degree, w.time_degree, w.tau, w.n_vars, w.chaos_degree, mus,
+                  lambda p: sg_inputs.coefficient_modes(w, p)[1])
+    nxi, nt, nx = w.n_chaos, w.n_time, w.n_nodes(0)
+    rng = np.random.default_rng(11)
+    picks = [(int(rng.integers(nxi)), int(rng.integers(nt)), int(rng.integers(nx))) for _ in range(60)]
+    n1 = w.n_nodes_1d(0)
+    picks += [(0, 0, 0), (nxi - 1, nt - 1, nx - 1), (nxi - 1, 0, n1 + 1), (1, nt - 1, nx // 2),
+              (nxi // 2, 0, (n1 * n1 if w.dim == 3 else 0) + 2 * n1 + 2)]
+    ref = R.rows(x, picks)
+    got = np.array([y[(a * nt + i) * nx + m] for a, i, m in picks])
+    scale = np.abs(ref).max()
+    assert np.abs(got - ref).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("name", ["c1", "t2q1", "t2q3", "t3q2", "t3q3"])
+def test_vanka_matches_oracle(torch_cuda, name):
+    torch = torch_cuda
+    w = sg_inputs.WORKLOADS[name]
+    print(f"vanka parity {name}", flush=True)
+    H = hierarchy_from_workload(w)
+    G = _gpu(w)
+    for level in range(w.n_levels):
+        n = G.n(level)
+        b = sg_inputs.uniform_vector(n, 21 + level)
+        x0 = sg_inputs.uniform_vector(n, 31 + level)
+        xg = _to_gpu(torch, x0)
+        G.vanka_smooth(level, _to_gpu(torch, b), xg, sweeps=2)
+        ref = H.smooth(level, b, x0, 2, w.n_chaos)
+        assert _rel_inf(xg.cpu().numpy(), ref) <= 1e-11, level
+
+
+@pytest.mark.parametrize("name", ["c1", "t2q2", "t2q3", "t3q1", "t3q2"])
+def test_vcycle_matches_oracle(torch_cuda, name):
+    torch = torch_cuda
+    w = sg_inputs.WORKLOADS[name]
+    print(f"vcycle parity {name}", flush=True)
+    H = hierarchy_from_workload(w)
+    G = _gpu(w)
+    r = sg_inputs.uniform_vector(G.n(0), 41)
+    z = G.vcycle(_to_gpu(torch, r)).cpu().numpy()
+    assert _rel_inf(z, H.vcycle(r, w.n_chaos)) <= 1e-11
+
+
+@pytest.mark.parametrize("name", ["c1", "t3q2", "t2q3"])
+def test_fgmres_solves_to_tolerance(torch_cuda, name):
+    torch = torch_cuda
+    import scipy.sparse.linalg as spla
+    w = sg_inputs.WORKLOADS[name]
+    print(f"fgmres {name}", flush=True)
+    P = from_workload(w)
+    G = _gpu(w)
+    xs = sg_inputs.uniform_vector(P.n, sg_inputs.SEED_SOLVE_TARGET)
+    xs[P.full_boundary_mask()] = 0.0
+    b = P.apply_route2(xs)
+    x, info = G.solve(_to_gpu(torch, b), rtol=1e-8, max_iter=200)
+    x = x.cpu().numpy()
+    assert info["converged"] == 1 and info["rel_residual_true"] <= 1e-8
+    rel = np.linalg.norm(b - P.apply_route2(x)) / np.linalg.norm(b)
+    assert rel <= 1.0001e-8
+    xd = spla.spsolve(P.assemble_full().tocsc(), b)
+    assert np.linalg.norm(x - xd) <= 1e-6 * np.linalg.norm(xd)
+    # same iteration count as the oracle's FGMRES with the oracle's V-cycle (same arithmetic up to rounding)
+    H = hierarchy_from_workload(w)
+    _, st = fgmres(P.apply_route2, lambda r: H.vcycle(r, P.n_xi), b, rtol=1e-8)
+    assert abs(st["iterations"] - info["iterations"]) <= 1
+    print(name, info)
+
+
+@pytest.mark.parametrize("name", ["c1", "t3q2"])
+def test_mixed_precision_solve(torch_cuda, name):
+    torch = torch_cuda
+    w = sg_inputs.WORKLOADS[name]
+    print(f"mixed fgmres {name}", flush=True)
+    P = from_workload(w)
+    xs = sg_inputs.uniform_vector(P.n, sg_inputs.SEED_SOLVE_TARGET)
+    xs[P.full_boundary_mask()] = 0.0
+    b = P.apply_route2(xs)
+    G64 = _gpu(w, 0)
+    G32 = _gpu(w, 1)
+    bg = _to_gpu(torch, b)
+    x64, i64 = G64.solve(bg, rtol=1e-8)
+    x32, i32 = G32.solve(bg, rtol=1e-8)
+    x32n = x32.cpu().numpy()
+    assert i32["converged"] == 1
+    rel = np.linalg.norm(b - P.apply_route2(x32n)) / np.linalg.norm(b)
+    assert rel <= 1.0001e-8
+    err = np.linalg.norm(x32n - x64.cpu().numpy()) / np.linalg.norm(x64.cpu().numpy())
+    print(f"{name}: mixed vs fp64 solution rel. difference {err:.3e}; iterations {i32['iterations']} vs {i64['iterations']}")
+
+
+def test_degenerate_cases(torch_cuda):
+    """One Q1 cell (every node Dirichlet: AA = I), p_xi = 0 (N_xi = 1), dG(0), one level."""
+    torch = torch_cuda
+    w = sg_inputs.WORKLOADS["t2q1"].with_(n_cells_1d=1, n_levels=1)
+    G = _gpu(w)
+    x = _to_gpu(torch, sg_inputs.uniform_vector(G.n(0), 5))
+    assert torch.equal(G.apply(x), x)
+    for w in [sg_inputs.WORKLOADS["t2q2"].with_(chaos_degree=0), sg_inputs.WORKLOADS["t3q1"].with_(time_degree=0),
+              sg_inputs.WORKLOADS["t2q2"].with_(n_levels=1)]:
+        P = from_workload(w)
+        G = _gpu(w)
+        x = sg_inputs.uniform_vector(P.n, 6)
+        assert _rel_inf(G.apply(_to_gpu(torch, x)).cpu().numpy(), P.apply_route2(x)) <= 1e-12
+        H = hierarchy_from_workload(w)
+        z = G.vcycle(_to_gpu(torch, x)).cpu().numpy()
+        assert _rel_inf(z, H.vcycle(x, P.n_xi)) <= 1e-11
+
+
+def test_argument_errors(torch_cuda):
+    torch = torch_cuda
+    from paper_2605_21046_amd import sgheat
+    G = _gpu(sg_inputs.WORKLOADS["c1"])
+    x = torch.zeros(G.n(0), dtype=torch.float64, device="cuda")
+    with pytest.raises(sgheat.SgError):
+        sgheat._check(sgheat._lib.sg_operator_apply(G._h, sgheat.ctypes.c_void_p(x.data_ptr()),
+                                                    sgheat.ctypes.c_void_p(x.data_ptr()), None))
+    with pytest.raises(ValueError):
+        G.apply(torch.zeros(5, dtype=torch.float64, device="cuda"))
+    with pytest.raises(TypeError):
+        G.apply(x.float())
+    with pytest.raises(sgheat.SgError):
+        G.vanka_smooth(7, x, x.clone())
+    # non-affine coefficient: the operator is fine, the preconditioner is not available
+    w = sg_inputs.WORKLOADS["t2q2"]
+    spec = sgheat.Spec(w.dim, w.n_cells_1d, w.fe_degree, w.time_degree, w.tau, w.n_vars, w.chaos_degree, w.n_levels)
+    nq = (w.fe_degree + 1) ** w.dim
+    coef = [np.ones((2, (w.n_cells_1d >> l) ** w.dim, nq)) for l in range(w.n_levels)]
+    with pytest.raises(sgheat.SgError):
+        sgheat.Problem(spec, [[0, 0], [2, 0]], coef)
