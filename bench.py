@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--only-apply", action="store_true", help="skip the solves (for profiling the apply)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 512 MiB device copy 5 times (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -95,8 +97,16 @@ def main():
     import sg_inputs
     from paper_2605_21046_amd import sgheat
 
-    w = sg_inputs.WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        a = torch.rand(64 * 1024 * 1024, dtype=torch.float64, device=dev)
+        c = torch.empty_like(a)
+        for _ in range(5):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": a.numel() * 8, "copy_calibration_bytes_written": c.numel() * 8}))
+        return
+    w = sg_inputs.WORKLOADS[args.workload]
     stream = torch.cuda.current_stream()
     t_setup = time.perf_counter()
     G = sgheat.problem_from_workload(w, sgheat.SG_FP64)

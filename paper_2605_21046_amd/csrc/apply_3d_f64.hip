@@ -1,0 +1,6 @@
+// Instances of the slab-operator kernels for d = 3 in double (see apply_impl.hpp).
+#include "apply_impl.hpp"
+
+namespace sg {
+template hipError_t apply_dim<3, double>(const ApplyOp<double>&, const double*, double*, const double*, hipStream_t);
+}  // namespace sg

@@ -9,7 +9,8 @@
 namespace sg {
 
 // ---- slab operator ------------------------------------------------------------------------------
-// y = AA x, or y = b - AA x when b != nullptr, restricted to the coupling list given.
+// y = AA x, or y = b - AA x when b != nullptr, restricted to the coupling list given;
+// with `mean` set (and b given) y = b - (I (x) A_0) x.
 // coef: [n_mu][n_cells][(k+1)^d] values a_mu(x_q) * w_q * h^(d-2).
 // Coupling CSR: row alpha * n_mu + mu lists (beta, [G_mu]_{alpha beta}).
 template <typename T>
@@ -25,6 +26,7 @@ struct ApplyOp {
     const T* cw;
     const Tables<T>* tables;      // host copy, passed by value to the kernel
     int cells_per_block;          // cells handled by one workgroup
+    bool mean;                    // coupling is the identity with the mean coefficient (residuals only)
 };
 template <typename T>
 hipError_t launch_apply(const ApplyOp<T>& op, const T* x, T* y, const T* b, hipStream_t s);

@@ -596,6 +596,7 @@ ApplyOp<T> make_op(const sg_handle h, int level, bool full) {
         op.cmu = h->cmu_m.p;
         op.cw = Prec<T>::cwm(h);
     }
+    op.mean = !full;
     op.cells_per_block = pick_cpb(h->n_xi * h->NT, op.n_mu, h->NP, sizeof(T));
     return op;
 }
