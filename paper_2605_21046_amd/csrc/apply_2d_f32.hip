@@ -2,5 +2,5 @@
 #include "apply_impl.hpp"
 
 namespace sg {
-template hipError_t apply_dim<2, float>(const ApplyOp<float>&, const float*, float*, const float*, hipStream_t);
+template hipError_t apply_dim<2, float>(const ApplyOp<float>&, const float*, float*, hipStream_t);
 }  // namespace sg

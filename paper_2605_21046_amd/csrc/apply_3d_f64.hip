@@ -2,5 +2,5 @@
 #include "apply_impl.hpp"
 
 namespace sg {
-template hipError_t apply_dim<3, double>(const ApplyOp<double>&, const double*, double*, const double*, hipStream_t);
+template hipError_t apply_dim<3, double>(const ApplyOp<double>&, const double*, double*, hipStream_t);
 }  // namespace sg

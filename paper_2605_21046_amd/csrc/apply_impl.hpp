@@ -4,19 +4,24 @@
 // action of AA is formed).
 //
 // Work decomposition (gfx950, wave64):
-//   * one workgroup = `cpb` cells of one colour x all N_xi * N_t components; one thread owns one
-//     (cell, component) pair and keeps its (k+1)^d point values in registers;
+//   * one launch over every cell; one workgroup = `cpb` consecutive cells x all N_xi * N_t
+//     components; one thread owns one (cell, component) pair and keeps its (k+1)^d point values
+//     in registers; workgroups are remapped so that each XCD (and its L2) works on one contiguous
+//     range of cells;
 //   * per thread: gather the cell's nodal values (Dirichlet columns dropped), interpolate to the
 //     Gauss points (d 1D sweeps with the GLL-basis table), take reference derivatives by Gauss
 //     collocation (d sweeps), and integrate back with the transposed sweeps;
 //   * the two couplings that cross components go through LDS:
 //       - time: the mass term needs sum_j A_t[i][j] u_j at each point,
 //       - chaos: the stiffness flux of mode alpha is sum_mu a_mu(x_q) sum_beta [G_mu]_{alpha beta}
-//         grad u_beta, read from the neighbours listed in the coupling CSR;
-//   * continuous-FE scatter without atomics: cells are split into 2^d colours by coordinate
-//     parity, one launch per colour; cells of one colour share no node.  A node's first writer
-//     (lowest colour) stores, later colours read-modify-write, so the result is deterministic.
+//         grad u_beta, read from the neighbours listed in the coupling CSR
+//     (with the mean coefficient alone the chaos coupling is the identity and stays in registers);
+//   * no scatter: each cell writes its local result to a "broken" node array (every cell owns its
+//     (k+1)^d nodes, shared nodes are duplicated); k_node_gather then sums the copies of each node
+//     in a fixed order, so the result is deterministic and no atomics or colouring are needed.
 #pragma once
+
+#include <algorithm>
 
 #include "kernels.hpp"
 
@@ -27,8 +32,7 @@ namespace {
 template <typename T>
 struct ApplyArgs {
     const T* x;
-    T* y;
-    const T* b;
+    T* s;                 // broken-layout output [comp][b_z][b_y][b_x], b = c (k+1) + a
     const T* coef;
     long long coef_mode_stride;
     const int* cptr;
@@ -36,11 +40,10 @@ struct ApplyArgs {
     const int* cmu;
     const T* cw;
     int n_xi, n_mu;
+    int n_ent;            // coupling entries (length of cbeta / cw / cmu)
     Grid g;
-    int par[3];
-    int cnt[3];
-    int cells_in_colour;
     int cpb;
+    int nblocks;
 };
 
 // out[.., o, ..] (+)= sum_i M(o, i) in[.., i, ..] along direction DIR of an N1^DIM point block;
@@ -67,73 +70,49 @@ __device__ __forceinline__ void sweep(const T (&in)[ipow(N1, DIM)], T (&out)[ipo
 // would otherwise blow the register budget and spill.
 #define SG_FENCE() __builtin_amdgcn_sched_barrier(0)
 
-__device__ __forceinline__ long long colour_cell(const int* par, const int* cnt, int n, int dim, int ci,
-                                                 int* cc) {
-    int r = ci;
-    long long cell = 0, mul = 1;
-    for (int d = 0; d < 3; ++d) {
-        if (d < dim) {
-            cc[d] = 2 * (r % cnt[d]) + par[d];
-            r /= cnt[d];
-            cell += (long long)cc[d] * mul;
-            mul *= n;
-        } else {
-            cc[d] = 0;
-        }
-    }
-    return cell;
+// Workgroups are dispatched round-robin over the 8 XCDs; give XCD x the contiguous block range
+// [start_x, start_x + count_x) so neighbouring cells share one L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int q = nb / 8, r = nb % 8;
+    const int x = b % 8;
+    return x * q + min(x, r) + b / 8;
 }
 
-// Coloured scatter of one (cell, component) block: the lowest colour touching a node stores, the
-// others read-modify-write; Dirichlet rows get the identity (y = x, or b - x for a residual).
-template <int DIM, int K, typename T, bool RESID>
-__device__ __forceinline__ void scatter(const ApplyArgs<T>& a, const T (&Y)[ipow(K + 1, DIM)], T bt,
-                                        const int* cc, long long cbase) {
-    constexpr int N1 = K + 1;
-    constexpr int NP = ipow(N1, DIM);
-    const int n = a.g.n, n1 = a.g.n1;
+template <int NT, typename T>
+__device__ __forceinline__ T bt_of(const Tables<T>& tb, int ti) {
+    T v = tb.Bt[0];
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-        long long node = 0, mul = 1;
-        bool bnd = false, first = true;
+    for (int i = 1; i < NT; ++i) v = (ti == i) ? tb.Bt[i] : v;
+    return v;
+}
+
+// Store the (k+1)^d results of one (cell, component) into the broken layout.
+template <int DIM, int K, typename T>
+__device__ __forceinline__ void store_broken(T* __restrict__ s, const T (&Y)[ipow(K + 1, DIM)], T scale,
+                                             const int* cc, int n, int comp) {
+    constexpr int N1 = K + 1;
+    const long long nb1 = (long long)n * N1;
+    long long base = comp;
+#pragma unroll
+    for (int d = DIM - 1; d >= 0; --d) base = base * nb1 + (long long)cc[d] * N1;
+#pragma unroll
+    for (int p = 0; p < ipow(N1, DIM); ++p) {
+        long long off = 0, mul = 1;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-            const int ad = (p / ipow(N1, d)) % N1;
-            const int id = cc[d] * K + ad;
-            bnd |= (id == 0) | (id == n1 - 1);
-            const bool shared = (ad == 0 && cc[d] > 0) || (ad == K && cc[d] < n - 1);
-            if (shared && a.par[d]) first = false;
-            node += id * mul;
-            mul *= n1;
+            off += ((p / ipow(N1, d)) % N1) * mul;
+            mul *= nb1;
         }
-        const long long gi = cbase + node;
-        if (bnd) {
-            if (first) a.y[gi] = RESID ? a.b[gi] - a.x[gi] : a.x[gi];
-        } else {
-            const T v = Y[p] * bt;
-            if (RESID) a.y[gi] = first ? a.b[gi] - v : a.y[gi] - v;
-            else a.y[gi] = first ? v : a.y[gi] + v;
-        }
-        if (p % 9 == 8) SG_FENCE();
+        s[base + off] = Y[p] * scale;
     }
 }
 
 // Points u_q of one (cell, component) at the Gauss points are in U; W accumulates the integrand.
-// Slice s of direction DIR = the N1^(DIM-1) points with q_DIR = s.
-template <int DIM, int N1, int DIR>
-__device__ __forceinline__ constexpr int slice_point(int s, int j) {
-    // j enumerates the other directions (x fastest), s is the index along DIR
-    constexpr int st = ipow(N1, DIR);
-    return (j / st) * st * N1 + s * st + (j % st);
-}
-
-// MODE 0: y = AA x;  MODE 1: y = b - AA x;  MODE 2: y = b - (I (x) A_0) x with the mean coefficient
-// only (no chaos coupling, so the stiffness flux never leaves the thread).
-template <int DIM, int K, int NT, typename T, int MODE>
+template <int DIM, int K, int NT, typename T, bool MEAN>
 __device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const Tables<T>& tb, T (&U)[ipow(K + 1, DIM)],
                                            T (&W)[ipow(K + 1, DIM)], T* slot_rows, const T* slot_coef,
-                                           int comp, int alpha, int ti, bool active, const int* cc,
-                                           long long cbase) {
+                                           const int* ent_g, const int* ent_c, const T* ent_w, int e0, int e1,
+                                           int comp, int alpha, int ti, bool active, const int* cc) {
     constexpr int N1 = K + 1;
     constexpr int NP = ipow(N1, DIM);
     constexpr int NS = NP / N1;   // points per slice
@@ -147,7 +126,10 @@ __device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const Tables<T
     for (int q = 0; q < NP; ++q) W[q] = T(0);
 #pragma unroll 1
     for (int j = 0; j < NT; ++j) {
-        const T as = tb.As[ti * NT + j];
+        // row ti of A_t / B_t picked with selects (ti varies per lane; the table is uniform)
+        T as = tb.As[j];
+#pragma unroll
+        for (int i = 1; i < NT; ++i) as = (ti == i) ? tb.As[i * NT + j] : as;
         const T* row = slot_rows + (alpha * NT + j) * NP;
 #pragma unroll
         for (int q = 0; q < NP; ++q) W[q] += as * row[q];
@@ -159,9 +141,8 @@ __device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const Tables<T
         for (int d = 0; d < DIM; ++d) wq *= tb.w[(q / ipow(N1, d)) % N1];
         W[q] *= wq;
     }
-    __syncthreads();
 
-    if constexpr (MODE == 2) {
+    if constexpr (MEAN) {
         // mean block: flux = a_0(x_q) * d u / d x_dir, all in registers
 #pragma unroll
         for (int dir = 0; dir < DIM; ++dir) {
@@ -188,103 +169,136 @@ __device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const Tables<T
             }
         }
     } else {
-    const int e0 = a.cptr[alpha * a.n_mu];
-        const int e1 = a.cptr[(alpha + 1) * a.n_mu];
+        __syncthreads();
         // stiffness term, one reference direction at a time
-    #pragma unroll
+#pragma unroll
         for (int dir = 0; dir < DIM; ++dir) {
             const int st = ipow(N1, dir);
             // reference derivative along dir by Gauss collocation, written straight to LDS
-    #pragma unroll
+#pragma unroll
             for (int q = 0; q < NP; ++q) {
                 const int qd = (q / st) % N1;
                 const int base = q - qd * st;
                 T g = T(0);
-    #pragma unroll
+#pragma unroll
                 for (int i = 0; i < N1; ++i) g += tb.D[qd * N1 + i] * U[base + i * st];
                 my_row[q] = g;
             }
             __syncthreads();
             // flux of mode alpha on one slice at a time, then W += D^T flux along dir
-    #pragma unroll
+#pragma unroll
             for (int s = 0; s < N1; ++s) {
                 T F[NS];
-    #pragma unroll
+#pragma unroll
                 for (int j = 0; j < NS; ++j) F[j] = T(0);
-    #pragma unroll 1
+#pragma unroll 1
                 for (int e = e0; e < e1; ++e) {
-                    const int beta = a.cbeta[e];
-                    const T w = a.cw[e];
-                    const T* cp = slot_coef + a.cmu[e] * NP;
-                    const T* gp = slot_rows + (beta * NT + ti) * NP;
-    #pragma unroll
+                    const T w = ent_w[e];
+                    const T* cp = slot_coef + ent_c[e];
+                    const T* gp = slot_rows + ent_g[e] + ti * NP;
+#pragma unroll
                     for (int j = 0; j < NS; ++j) {
                         const int q = (j / st) * st * N1 + s * st + (j % st);
                         F[j] += (w * cp[q]) * gp[q];
                     }
                 }
-    #pragma unroll
+#pragma unroll
                 for (int j = 0; j < NS; ++j) {
                     const int q = (j / st) * st * N1 + s * st + (j % st);
                     const int base = q - s * st;
-    #pragma unroll
+#pragma unroll
                     for (int o = 0; o < N1; ++o) W[base + o * st] += tb.D[s * N1 + o] * F[j];
                 }
             }
             __syncthreads();
         }
-    
     }
 
-    // integrate back to the nodes and scatter
+    // integrate back to the nodes and store the cell-local result
     if constexpr (DIM == 2) {
         sweep<DIM, N1, 0, false, true>(W, U, tb.S);
         sweep<DIM, N1, 1, false, true>(U, W, tb.S);
-        if (active) scatter<DIM, K, T, MODE != 0>(a, W, tb.Bt[ti], cc, cbase);
+        if (active) store_broken<DIM, K, T>(a.s, W, bt_of<NT>(tb, ti), cc, a.g.n, comp);
     } else {
         sweep<DIM, N1, 0, false, true>(W, U, tb.S);
         sweep<DIM, N1, 1, false, true>(U, W, tb.S);
         sweep<DIM, N1, 2, false, true>(W, U, tb.S);
-        if (active) scatter<DIM, K, T, MODE != 0>(a, U, tb.Bt[ti], cc, cbase);
+        if (active) store_broken<DIM, K, T>(a.s, U, bt_of<NT>(tb, ti), cc, a.g.n, comp);
     }
 }
 
-template <int DIM, int K, int NT, typename T, int MODE>
-__global__ void __launch_bounds__(ipow(K + 1, DIM) > 27 ? 256 : 512) k_apply(ApplyArgs<T> a, Tables<T> tb) {
+// Minimum resident waves per SIMD the register allocator must allow (more waves hide the LDS and
+// barrier latency of the exchange phases).
+template <int NP, typename T>
+constexpr int apply_waves_per_eu() {
+    return NP > 27 ? 1 : (sizeof(T) == 8 ? 2 : 3);
+}
+
+// Per-slot LDS strides padded so consecutive slots start on different banks.
+template <typename T>
+__host__ __device__ constexpr int padded_stride(int n) {
+    constexpr int nb = sizeof(T) == 8 ? 16 : 32;   // 32 four-byte banks
+    return n + ((1 - n) % nb + nb) % nb;
+}
+
+template <int DIM, int K, int NT, typename T, bool MEAN>
+__global__ void __launch_bounds__(ipow(K + 1, DIM) > 27 ? 256 : 512)
+    __attribute__((amdgpu_waves_per_eu(apply_waves_per_eu<ipow(K + 1, DIM), T>())))
+    k_apply(ApplyArgs<T> a, Tables<T> tb) {
     constexpr int N1 = K + 1;
     constexpr int NP = ipow(N1, DIM);
     extern __shared__ unsigned char smem_raw[];
     const int cpb = a.cpb;
     const int NC = a.n_xi * NT;
-    T* exch = reinterpret_cast<T*>(smem_raw);               // [cpb][NC][NP]
-    T* cl = exch + (size_t)NC * NP * cpb;                    // [cpb][n_mu][NP]
+    const int SS = padded_stride<T>(NC * NP);                // slot stride of the exchange rows
+    const int CS = padded_stride<T>(a.n_mu * NP);            // slot stride of the coefficient rows
+    T* exch = reinterpret_cast<T*>(smem_raw);               // [cpb][SS]: rows [NC][NP]
+    T* cl = exch + (size_t)SS * cpb;                         // [cpb][CS]: rows [n_mu][NP]
+    T* ent_w = cl + (size_t)CS * cpb;                        // [n_ent] G_mu[alpha][beta]
+    int* ent_g = reinterpret_cast<int*>(ent_w + a.n_ent);    // [n_ent] LDS row offset of beta
+    int* ent_c = ent_g + a.n_ent;                            // [n_ent] LDS row offset of mu
 
     const int t = threadIdx.x;
     const int slot = t % cpb;
     const int comp = t / cpb;
     const int alpha = comp / NT;
     const int ti = comp % NT;
-    const int ci = blockIdx.x * cpb + slot;
-    const bool active = ci < a.cells_in_colour;
+    const int lb = xcd_block(blockIdx.x, a.nblocks);
+    const long long cell0 = (long long)lb * cpb;
+    const long long ci = cell0 + slot;
+    const bool active = ci < a.g.n_cells;
     const int n = a.g.n, n1 = a.g.n1;
     const long long nn = a.g.n_nodes;
 
-    int cc[3];
-    colour_cell(a.par, a.cnt, n, DIM, active ? ci : 0, cc);
+    int cc[3] = {0, 0, 0};
+    {
+        long long r = active ? ci : 0;
+        for (int d = 0; d < DIM; ++d) {
+            cc[d] = (int)(r % n);
+            r /= n;
+        }
+    }
 
-    // stage the coefficient values of this block's cells
+    // stage the coefficient values of this block's cells (contiguous in memory)
     for (int idx = t; idx < a.n_mu * NP * cpb; idx += blockDim.x) {
         const int q = idx % NP;
         const int mu = (idx / NP) % a.n_mu;
         const int s = idx / (NP * a.n_mu);
-        const int c2 = blockIdx.x * cpb + s;
-        T v = T(0);
-        if (c2 < a.cells_in_colour) {
-            int cq[3];
-            const long long cell = colour_cell(a.par, a.cnt, n, DIM, c2, cq);
-            v = a.coef[mu * a.coef_mode_stride + cell * NP + q];
+        const long long c2 = cell0 + s;
+        cl[s * CS + mu * NP + q] = (c2 < a.g.n_cells) ? a.coef[mu * a.coef_mode_stride + c2 * NP + q] : T(0);
+    }
+    // stage the coupling entries (beta, mu, w) as LDS offsets
+    if constexpr (!MEAN) {
+        for (int e = t; e < a.n_ent; e += blockDim.x) {
+            ent_w[e] = a.cw[e];
+            ent_g[e] = a.cbeta[e] * NT * NP;
+            ent_c[e] = a.cmu[e] * NP;
         }
-        cl[idx] = v;
+    }
+    int e0 = 0, e1 = 0;
+    if constexpr (!MEAN) {
+        e0 = a.cptr[alpha * a.n_mu];
+        e1 = a.cptr[(alpha + 1) * a.n_mu];
     }
 
     T A[NP], B[NP];
@@ -307,30 +321,61 @@ __global__ void __launch_bounds__(ipow(K + 1, DIM) > 27 ? 256 : 512) k_apply(App
         if (p % 9 == 8) SG_FENCE();
     }
 
-    T* const slot_rows = exch + (size_t)slot * NC * NP;
-    const T* const slot_coef = cl + (size_t)slot * a.n_mu * NP;
+    T* const slot_rows = exch + (size_t)slot * SS;
+    const T* const slot_coef = cl + (size_t)slot * CS;
     // values at the Gauss points, then the rest of the cell work
     if constexpr (DIM == 2) {
         sweep<DIM, N1, 0, false, false>(A, B, tb.S);
         sweep<DIM, N1, 1, false, false>(B, A, tb.S);
-        apply_body<DIM, K, NT, T, MODE>(a, tb, A, B, slot_rows, slot_coef, comp, alpha, ti, active, cc, cbase);
+        apply_body<DIM, K, NT, T, MEAN>(a, tb, A, B, slot_rows, slot_coef, ent_g, ent_c, ent_w, e0, e1, comp, alpha,
+                                        ti, active, cc);
     } else {
         sweep<DIM, N1, 0, false, false>(A, B, tb.S);
         sweep<DIM, N1, 1, false, false>(B, A, tb.S);
         sweep<DIM, N1, 2, false, false>(A, B, tb.S);
-        apply_body<DIM, K, NT, T, MODE>(a, tb, B, A, slot_rows, slot_coef, comp, alpha, ti, active, cc, cbase);
+        apply_body<DIM, K, NT, T, MEAN>(a, tb, B, A, slot_rows, slot_coef, ent_g, ent_c, ent_w, e0, e1, comp, alpha,
+                                        ti, active, cc);
     }
 }
 
+// Cells per workgroup: the largest number of busy lanes per CU allowed by the kernel's register use
+// (queried from the code object), the launch bound and 160 KiB of LDS.
+inline int choose_cpb(const void* kern, int nc, size_t lds_fixed, size_t lds_per_cell, int max_threads) {
+    hipFuncAttributes attr{};
+    int vgpr = 256;
+    if (hipFuncGetAttributes(&attr, kern) == hipSuccess && attr.numRegs > 0) vgpr = attr.numRegs;
+    else (void)hipGetLastError();
+    const int alloc = ((vgpr + 7) / 8) * 8;
+    const int waves_simd = std::max(1, std::min(8, 512 / alloc));
+    const int waves_cu = 4 * waves_simd;
+    int best = 1;
+    long best_score = -1;
+    for (int cpb = 1; nc * cpb <= max_threads; ++cpb) {
+        const int threads = nc * cpb;
+        const int waves = (threads + 63) / 64;
+        const int by_w = waves_cu / waves;
+        const size_t lds = lds_fixed + lds_per_cell * cpb;
+        const int by_l = lds > 160 * 1024 ? 0 : (int)((160 * 1024) / lds);
+        const int blocks = std::min(by_w, by_l);
+        if (blocks == 0) continue;
+        const long score = (long)blocks * threads;
+        if (score > best_score) {
+            best_score = score;
+            best = cpb;
+        }
+    }
+    return best;
+}
+
 template <int DIM, int K, int NT, typename T>
-hipError_t run_apply(const ApplyOp<T>& op, const T* x, T* y, const T* b, hipStream_t s) {
+hipError_t run_apply(const ApplyOp<T>& op, const T* x, T* s_out, hipStream_t s) {
     constexpr int N1 = K + 1;
     constexpr int NP = ipow(N1, DIM);
-    const int cpb = op.cells_per_block;
+    constexpr int MAXT = NP > 27 ? 256 : 512;
+    auto kern = op.mean ? k_apply<DIM, K, NT, T, true> : k_apply<DIM, K, NT, T, false>;
     ApplyArgs<T> a{};
     a.x = x;
-    a.y = y;
-    a.b = b;
+    a.s = s_out;
     a.coef = op.coef;
     a.coef_mode_stride = op.coef_mode_stride;
     a.cptr = op.cptr;
@@ -339,43 +384,31 @@ hipError_t run_apply(const ApplyOp<T>& op, const T* x, T* y, const T* b, hipStre
     a.cw = op.cw;
     a.n_xi = op.n_xi;
     a.n_mu = op.n_mu;
+    a.n_ent = op.n_ent;
     a.g = op.g;
+    const int nc = op.n_xi * NT;
+    const size_t per_cell = (size_t)(padded_stride<T>(nc * NP) + padded_stride<T>(op.n_mu * NP)) * sizeof(T);
+    const size_t fixed = (size_t)op.n_ent * (sizeof(T) + 2 * sizeof(int)) + 16;
+    const int cpb = op.cells_per_block > 0 ? op.cells_per_block : choose_cpb((const void*)kern, nc, fixed, per_cell, MAXT);
     a.cpb = cpb;
-    const int threads = op.n_xi * NT * cpb;
-    const size_t lds = (size_t)(op.n_xi * NT + op.n_mu) * NP * cpb * sizeof(T);
-    for (int colour = 0; colour < (1 << DIM); ++colour) {
-        int cells = 1;
-        for (int d = 0; d < 3; ++d) {
-            if (d < DIM) {
-                a.par[d] = (colour >> d) & 1;
-                a.cnt[d] = (op.g.n - a.par[d] + 1) / 2;
-            } else {
-                a.par[d] = 0;
-                a.cnt[d] = 1;
-            }
-            cells *= a.cnt[d];
-        }
-        a.cells_in_colour = cells;
-        if (cells == 0) continue;
-        const int blocks = (cells + cpb - 1) / cpb;
-        const int mode = b ? (op.mean ? 2 : 1) : 0;
-        auto kern = mode == 0 ? k_apply<DIM, K, NT, T, 0> : (mode == 1 ? k_apply<DIM, K, NT, T, 1> : k_apply<DIM, K, NT, T, 2>);
-        if (lds > 64 * 1024)
-            (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds, s, a, *op.tables);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    const int threads = nc * cpb;
+    const size_t lds = fixed + per_cell * cpb;
+    if (threads > MAXT || lds > 160 * 1024) return hipErrorInvalidConfiguration;
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const long long blocks = (op.g.n_cells + cpb - 1) / cpb;
+    a.nblocks = (int)blocks;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(threads), lds, s, a, *op.tables);
+    return hipGetLastError();
 }
 
 template <int DIM, int K, typename T>
-hipError_t dispatch_nt(const ApplyOp<T>& op, const T* x, T* y, const T* b, hipStream_t s) {
+hipError_t dispatch_nt(const ApplyOp<T>& op, const T* x, T* s_out, hipStream_t s) {
     switch (op.nt) {
-        case 1: return run_apply<DIM, K, 1, T>(op, x, y, b, s);
-        case 2: return run_apply<DIM, K, 2, T>(op, x, y, b, s);
-        case 3: return run_apply<DIM, K, 3, T>(op, x, y, b, s);
-        case 4: return run_apply<DIM, K, 4, T>(op, x, y, b, s);
+        case 1: return run_apply<DIM, K, 1, T>(op, x, s_out, s);
+        case 2: return run_apply<DIM, K, 2, T>(op, x, s_out, s);
+        case 3: return run_apply<DIM, K, 3, T>(op, x, s_out, s);
+        case 4: return run_apply<DIM, K, 4, T>(op, x, s_out, s);
     }
     return hipErrorInvalidValue;
 }
@@ -384,15 +417,14 @@ hipError_t dispatch_nt(const ApplyOp<T>& op, const T* x, T* y, const T* b, hipSt
 
 // All (k, N_t) instances of one dimension and precision; instantiated in apply_<d>d_<type>.hip.
 template <int DIM, typename T>
-hipError_t apply_dim(const ApplyOp<T>& op, const T* x, T* y, const T* b, hipStream_t s) {
+hipError_t apply_dim(const ApplyOp<T>& op, const T* x, T* s_out, hipStream_t s) {
     switch (op.k) {
-        case 1: return dispatch_nt<DIM, 1, T>(op, x, y, b, s);
-        case 2: return dispatch_nt<DIM, 2, T>(op, x, y, b, s);
-        case 3: return dispatch_nt<DIM, 3, T>(op, x, y, b, s);
-        case 4: return dispatch_nt<DIM, 4, T>(op, x, y, b, s);
+        case 1: return dispatch_nt<DIM, 1, T>(op, x, s_out, s);
+        case 2: return dispatch_nt<DIM, 2, T>(op, x, s_out, s);
+        case 3: return dispatch_nt<DIM, 3, T>(op, x, s_out, s);
+        case 4: return dispatch_nt<DIM, 4, T>(op, x, s_out, s);
     }
     return hipErrorInvalidValue;
 }
-
 
 }  // namespace sg

@@ -9,8 +9,10 @@
 namespace sg {
 
 // ---- slab operator ------------------------------------------------------------------------------
-// y = AA x, or y = b - AA x when b != nullptr, restricted to the coupling list given;
-// with `mean` set (and b given) y = b - (I (x) A_0) x.
+// Cell-local part of y = AA x (or of (I (x) A_0) x when `mean` is set): every cell writes its
+// (k+1)^d nodal results per component to s_out in the broken layout
+//     s_out[comp][b_z][b_y][b_x],  b_d = c_d (k+1) + a_d  (cell c, local node a),
+// which k_node_gather (launch_node_gather) sums per node.
 // coef: [n_mu][n_cells][(k+1)^d] values a_mu(x_q) * w_q * h^(d-2).
 // Coupling CSR: row alpha * n_mu + mu lists (beta, [G_mu]_{alpha beta}).
 template <typename T>
@@ -25,13 +27,21 @@ struct ApplyOp {
     const int* cmu;               // mu index of every entry
     const T* cw;
     const Tables<T>* tables;      // host copy, passed by value to the kernel
-    int cells_per_block;          // cells handled by one workgroup
-    bool mean;                    // coupling is the identity with the mean coefficient (residuals only)
+    int n_ent;                    // number of coupling entries
+    int cells_per_block;          // cells handled by one workgroup (0 = chosen from occupancy)
+    bool mean;                    // mean block only: identity coupling with the mean coefficient
 };
 template <typename T>
-hipError_t launch_apply(const ApplyOp<T>& op, const T* x, T* y, const T* b, hipStream_t s);
+hipError_t launch_apply(const ApplyOp<T>& op, const T* x, T* s_out, hipStream_t s);
+
+// Sum of the broken copies of every node, then one of
+//   GATHER_SET:      out = sum                 (Dirichlet rows: out = x)
+//   GATHER_RESIDUAL: out = b - sum             (Dirichlet rows: out = b - x)
+//   GATHER_VANKA:    out += omega sum / mult   (Dirichlet rows: out = b); mult = cells sharing the node
+enum GatherOp { GATHER_SET = 0, GATHER_RESIDUAL = 1, GATHER_VANKA = 2 };
 template <typename T>
-size_t apply_lds_bytes(const ApplyOp<T>& op, int cells_per_block);
+hipError_t launch_node_gather(GatherOp op, int dim, int k, Grid g, int ncomp, const T* s_in, const T* x, const T* b,
+                              T* out, T omega, hipStream_t s);
 
 // ---- Vanka -----------------------------------------------------------------------------------------
 // Element stiffness of the mean coefficient: E[cell][a][b] = sum_q c0(cell,q) sum_d dphi_a dphi_b.
@@ -53,10 +63,12 @@ hipError_t launch_patch_invert(int dim, int k, int nt, Grid g, const double* E, 
                                const PatchTime& pt, double* inv64, float* inv32, int* status,
                                hipStream_t s);
 
-// x <- x + omega sum_K R_K^T W_K inv_K R_K r over the cells; x_D = b_D on Dirichlet nodes.
+// Patch corrections c_K = A_{0,K}^{-1} R_K r of every cell (inverses stored transposed), written to
+// s_out in the broken layout; launch_node_gather(GATHER_VANKA) then forms
+// x <- x + omega sum_K R_K^T W_K c_K.
 template <typename T>
-hipError_t launch_vanka_apply(int dim, int k, int nt, Grid g, int n_xi, const T* inv, const T* r,
-                              const T* b, T* x, T omega, hipStream_t s);
+hipError_t launch_vanka_cells(int dim, int k, int nt, Grid g, int n_xi, const T* invT, const T* r, T* s_out,
+                              hipStream_t s);
 
 // ---- transfers ---------------------------------------------------------------------------------------
 // One 1D pass along `dir`: out[c][.., o, ..] (+)= sum_w tw[o*width + w] in[c][.., tidx[o*width + w], ..]

@@ -13,33 +13,22 @@
 //       - time: the mass term needs sum_j A_t[i][j] u_j at each point,
 //       - chaos: the stiffness flux of mode alpha is sum_mu a_mu(x_q) sum_beta [G_mu]_{alpha beta}
 //         grad u_beta, read from the neighbours listed in the coupling CSR;
-//   * continuous-FE scatter without atomics: cells are split into 2^d colours by coordinate
-//     parity, one launch per colour; cells of one colour share no node.  A node's first writer
-//     (lowest colour) stores, later colours read-modify-write, so the result is deterministic.
+//   * no scatter: cell-local results go to a broken node array that k_node_gather sums per node.
 #include "kernels.hpp"
 
 namespace sg {
 
 template <int DIM, typename T>
-hipError_t apply_dim(const ApplyOp<T>& op, const T* x, T* y, const T* b, hipStream_t s);
+hipError_t apply_dim(const ApplyOp<T>& op, const T* x, T* s_out, hipStream_t s);
 
 template <typename T>
-hipError_t launch_apply(const ApplyOp<T>& op, const T* x, T* y, const T* b, hipStream_t s) {
-    if (op.dim == 2) return apply_dim<2, T>(op, x, y, b, s);
-    if (op.dim == 3) return apply_dim<3, T>(op, x, y, b, s);
+hipError_t launch_apply(const ApplyOp<T>& op, const T* x, T* s_out, hipStream_t s) {
+    if (op.dim == 2) return apply_dim<2, T>(op, x, s_out, s);
+    if (op.dim == 3) return apply_dim<3, T>(op, x, s_out, s);
     return hipErrorInvalidValue;
 }
 
-template <typename T>
-size_t apply_lds_bytes(const ApplyOp<T>& op, int cpb) {
-    size_t np = 1;
-    for (int d = 0; d < op.dim; ++d) np *= (size_t)(op.k + 1);
-    return (size_t)(op.n_xi * op.nt + op.n_mu) * np * cpb * sizeof(T);
-}
-
-template hipError_t launch_apply<double>(const ApplyOp<double>&, const double*, double*, const double*, hipStream_t);
-template hipError_t launch_apply<float>(const ApplyOp<float>&, const float*, float*, const float*, hipStream_t);
-template size_t apply_lds_bytes<double>(const ApplyOp<double>&, int);
-template size_t apply_lds_bytes<float>(const ApplyOp<float>&, int);
+template hipError_t launch_apply<double>(const ApplyOp<double>&, const double*, double*, hipStream_t);
+template hipError_t launch_apply<float>(const ApplyOp<float>&, const float*, float*, hipStream_t);
 
 }  // namespace sg

@@ -43,6 +43,58 @@ __global__ void k_transfer_1d(int dim, long long total, int i0, int i1, int o0, 
     }
 }
 
+// Sum of the broken copies of each node (fixed order: lower cell first in every direction), then the
+// requested update; one thread per (component, node), consecutive threads on consecutive x nodes.
+template <typename T, int OP, int DIM>
+__global__ void k_node_gather(int k, Grid g, long long total, const T* __restrict__ s_in, const T* __restrict__ x,
+                              const T* __restrict__ b, T* __restrict__ out, T omega) {
+    const int N1 = k + 1;
+    const long long nb1 = (long long)g.n * N1;
+    long long nbn = 1;
+    for (int d = 0; d < DIM; ++d) nbn *= nb1;
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const long long comp = idx / g.n_nodes;
+        long long r = idx - comp * g.n_nodes;
+        int cnt[3] = {1, 1, 1};
+        long long bi[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+        bool bnd = false;
+        for (int d = 0; d < DIM; ++d) {
+            const int i = (int)(r % g.n1);
+            r /= g.n1;
+            bnd |= (i == 0) | (i == g.n1 - 1);
+            if (i % k == 0 && i > 0 && i < g.n1 - 1) {
+                const int c = i / k;
+                bi[d][0] = (long long)(c - 1) * N1 + k;
+                bi[d][1] = (long long)c * N1;
+                cnt[d] = 2;
+            } else {
+                const int c = min(i / k, g.n - 1);
+                bi[d][0] = (long long)c * N1 + (i - c * k);
+            }
+        }
+        if (bnd) {
+            if (OP == GATHER_SET) out[idx] = x[idx];
+            else if (OP == GATHER_RESIDUAL) out[idx] = b[idx] - x[idx];
+            else out[idx] = b[idx];
+            continue;
+        }
+        const T* sc = s_in + comp * nbn;
+        T sum = T(0);
+        for (int z = 0; z < cnt[2]; ++z)
+            for (int y = 0; y < cnt[1]; ++y)
+                for (int xx = 0; xx < cnt[0]; ++xx) {
+                    long long o = bi[0][xx];
+                    if (DIM >= 2) o += bi[1][y] * nb1;
+                    if (DIM == 3) o += bi[2][z] * nb1 * nb1;
+                    sum += sc[o];
+                }
+        if (OP == GATHER_SET) out[idx] = sum;
+        else if (OP == GATHER_RESIDUAL) out[idx] = b[idx] - sum;
+        else out[idx] = out[idx] + omega * sum / T(cnt[0] * cnt[1] * cnt[2]);
+    }
+}
+
 template <typename T>
 __global__ void k_coarse_solve(const double* __restrict__ AinvT, int nint, const int* __restrict__ dofs, int n_xi,
                                long long mode_len, const T* __restrict__ b, T* __restrict__ x) {
@@ -216,6 +268,25 @@ hipError_t launch_transfer_1d(int dim, int ncomp, const int* in_dims, const int*
 }
 
 template <typename T>
+hipError_t launch_node_gather(GatherOp op, int dim, int k, Grid g, int ncomp, const T* s_in, const T* x, const T* b,
+                              T* out, T omega, hipStream_t s) {
+    const long long total = g.n_nodes * ncomp;
+    const dim3 grid(grid_for(total, 256, 65536)), block(256);
+#define SG_NG(OP_, D_) hipLaunchKernelGGL((k_node_gather<T, OP_, D_>), grid, block, 0, s, k, g, total, s_in, x, b, out, omega)
+    if (dim == 2) {
+        if (op == GATHER_SET) SG_NG(GATHER_SET, 2);
+        else if (op == GATHER_RESIDUAL) SG_NG(GATHER_RESIDUAL, 2);
+        else SG_NG(GATHER_VANKA, 2);
+    } else {
+        if (op == GATHER_SET) SG_NG(GATHER_SET, 3);
+        else if (op == GATHER_RESIDUAL) SG_NG(GATHER_RESIDUAL, 3);
+        else SG_NG(GATHER_VANKA, 3);
+    }
+#undef SG_NG
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_coarse_solve(const double* AinvT, int nint, const int* dofs, int n_xi, long long mode_len,
                                const T* b, T* x, hipStream_t s) {
     const long long n = mode_len * n_xi;
@@ -288,6 +359,10 @@ template hipError_t launch_transfer_1d<double>(int, int, const int*, const int*,
                                                const double*, double*, bool, hipStream_t);
 template hipError_t launch_transfer_1d<float>(int, int, const int*, const int*, int, const int*, const float*, int,
                                               const float*, float*, bool, hipStream_t);
+template hipError_t launch_node_gather<double>(GatherOp, int, int, Grid, int, const double*, const double*,
+                                               const double*, double*, double, hipStream_t);
+template hipError_t launch_node_gather<float>(GatherOp, int, int, Grid, int, const float*, const float*, const float*,
+                                              float*, float, hipStream_t);
 template hipError_t launch_coarse_solve<double>(const double*, int, const int*, int, long long, const double*, double*,
                                                 hipStream_t);
 template hipError_t launch_coarse_solve<float>(const double*, int, const int*, int, long long, const float*, float*,

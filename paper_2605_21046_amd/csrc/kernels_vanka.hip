@@ -7,7 +7,8 @@
 //   k_patch_invert   : forms A_{0,K} from the element matrices of every cell sharing the node pair,
 //                      inverts it by Gauss-Jordan elimination with partial pivoting, FP64, with the
 //                      matrix distributed over a TG x TG thread grid (R x R entries per thread)
-//   k_vanka_apply    : x <- x + omega sum_K R_K^T W_K A_{0,K}^{-1} R_K r for one colour of cells
+//   k_vanka_cells    : c_K = A_{0,K}^{-1} R_K r for every cell, into the broken node array; the
+//                      node gather then forms x <- x + omega sum_K R_K^T W_K c_K
 #include "kernels.hpp"
 
 namespace sg {
@@ -257,7 +258,7 @@ __global__ void __launch_bounds__(TG * TG)
             const int I = ty + TG * r, J = tx + TG * c;
             const int Jd = sigma_inv[J];
             if (I < npp && J < npp && Jd < npp) {
-                const long long o = (cell * npp + I) * npp + Jd;
+                const long long o = (cell * npp + Jd) * npp + I;   // stored transposed: [cell][col][row]
                 if (inv64) inv64[o] = Am[r][c];
                 if (inv32) inv32[o] = (float)Am[r][c];
             }
@@ -265,152 +266,136 @@ __global__ void __launch_bounds__(TG * TG)
 }
 
 // ------------------------------------------------------------------------------------------------
-template <int DIM, int K, int NT, typename T>
-__global__ void __launch_bounds__(256)
-    k_vanka_apply(Grid g, int n_xi, int par0, int par1, int par2, int cnt0, int cnt1, int cells_in_colour,
-                  const T* __restrict__ inv, const T* __restrict__ r, const T* __restrict__ b, T* __restrict__ x,
-                  T omega) {
+// One workgroup per cell, one wave per strip of SW chaos modes.  Lane l owns patch rows l, l + 64,
+// ...; the patch inverse is stored transposed so that, for a fixed column m, the 64 lanes read 64
+// consecutive entries; the residual patch rk[m][strip] is an LDS broadcast.  The correction of the
+// cell goes to the broken node array (summed per node by k_node_gather).
+template <int DIM, int K, int NT, typename T, int SW>
+__global__ void __launch_bounds__(512)
+    k_vanka_cells(Grid g, int n_xi, int nblocks, const T* __restrict__ invT, const T* __restrict__ r,
+                  T* __restrict__ s_out) {
     constexpr int N1 = K + 1;
     constexpr int NP = ipow(N1, DIM);
     constexpr int NPP = NT * NP;
+    constexpr int RCH = (NPP + 63) / 64;
     extern __shared__ unsigned char smem_raw[];
-    const int ldr = (n_xi + 3) & ~3;
+    const int nstrip = blockDim.x / 64;
+    const int ldr = nstrip * SW;
     T* rk = reinterpret_cast<T*>(smem_raw);   // [NPP][ldr]
-    T* ck = rk + NPP * ldr;                   // [NPP][ldr]
 
-    const int ci = blockIdx.x;
-    if (ci >= cells_in_colour) return;
-    const int par[3] = {par0, par1, par2};
+    // contiguous cell ranges per XCD (blocks are dispatched round-robin over the 8 XCDs)
+    const int b = blockIdx.x;
+    const long long cell = (long long)((b % 8) * (nblocks / 8) + min(b % 8, nblocks % 8) + b / 8);
     int cc[3] = {0, 0, 0};
     {
-        int rr = ci;
-        cc[0] = 2 * (rr % cnt0) + par0;
-        rr /= cnt0;
-        if (DIM >= 2) { cc[1] = 2 * (rr % cnt1) + par1; rr /= cnt1; }
-        if (DIM == 3) cc[2] = 2 * rr + par2;
+        long long rr = cell;
+        for (int d = 0; d < DIM; ++d) { cc[d] = (int)(rr % g.n); rr /= g.n; }
     }
-    long long cell = 0, mul = 1;
-    for (int d = 0; d < DIM; ++d) { cell += cc[d] * mul; mul *= g.n; }
     const long long nn = g.n_nodes;
 
-    auto node_of = [&](int p, bool* bnd, bool* first, int* mult) {
-        long long node = 0, m = 1;
-        *bnd = false;
-        *first = true;
-        *mult = 1;
+    // gather r_K: rk[l][alpha], l = i*NP + p; Dirichlet rows and padding modes are zero
+    for (int idx = threadIdx.x; idx < NPP * ldr; idx += blockDim.x) {
+        const int p = idx % NP;
+        const int i = (idx / NP) % NT;
+        const int al = idx / NPP;
+        T v = T(0);
+        if (al < n_xi) {
+            long long node = 0, m = 1;
+            bool bnd = false;
+            for (int d = 0; d < DIM; ++d) {
+                const int id = cc[d] * K + (p / ipow(N1, d)) % N1;
+                bnd |= (id == 0) | (id == g.n1 - 1);
+                node += id * m;
+                m *= g.n1;
+            }
+            if (!bnd) v = r[((long long)al * NT + i) * nn + node];
+        }
+        rk[(i * NP + p) * ldr + al] = v;
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x % 64;
+    const int strip = threadIdx.x / 64;
+    T acc[RCH][SW];
+#pragma unroll
+    for (int c = 0; c < RCH; ++c)
+#pragma unroll
+        for (int u = 0; u < SW; ++u) acc[c][u] = T(0);
+    const T* A = invT + cell * NPP * NPP;
+    const T* rs = rk + strip * SW;
+#pragma unroll 2
+    for (int m = 0; m < NPP; ++m) {
+        T av[RCH];
+#pragma unroll
+        for (int c = 0; c < RCH; ++c) {
+            const int l = lane + 64 * c;
+            av[c] = (l < NPP) ? A[(long long)m * NPP + l] : T(0);
+        }
+        const T* rr = rs + m * ldr;
+#pragma unroll
+        for (int u = 0; u < SW; ++u) {
+            const T rv = rr[u];
+#pragma unroll
+            for (int c = 0; c < RCH; ++c) acc[c][u] += av[c] * rv;
+        }
+    }
+
+    // cell-local correction into the broken layout [comp][b_z][b_y][b_x]
+    const long long nb1 = (long long)g.n * N1;
+    long long nbn = 1;
+    for (int d = 0; d < DIM; ++d) nbn *= nb1;
+#pragma unroll
+    for (int c = 0; c < RCH; ++c) {
+        const int l = lane + 64 * c;
+        if (l >= NPP) continue;
+        const int p = l % NP, i = l / NP;
+        long long off = 0, mul = 1;
         for (int d = 0; d < DIM; ++d) {
-            const int ad = (p / ipow(N1, d)) % N1;
-            const int id = cc[d] * K + ad;
-            *bnd |= (id == 0) | (id == g.n1 - 1);
-            const bool shared = (ad == 0 && cc[d] > 0) || (ad == K && cc[d] < g.n - 1);
-            if (shared) { *mult *= 2; if (par[d]) *first = false; }
-            node += id * m;
-            m *= g.n1;
+            off += ((long long)cc[d] * N1 + (p / ipow(N1, d)) % N1) * mul;
+            mul *= nb1;
         }
-        return node;
-    };
-
-    // gather r_K: rk[l][alpha], l = i*NP + p
-    for (int idx = threadIdx.x; idx < NPP * n_xi; idx += blockDim.x) {
-        const int p = idx % NP;
-        const int i = (idx / NP) % NT;
-        const int al = idx / NPP;
-        bool bnd, first;
-        int mult;
-        const long long node = node_of(p, &bnd, &first, &mult);
-        rk[(i * NP + p) * ldr + al] = bnd ? T(0) : r[((long long)al * NT + i) * nn + node];
-    }
-    for (int idx = threadIdx.x; idx < NPP * (ldr - n_xi); idx += blockDim.x) {
-        const int l = idx / (ldr - n_xi), al = n_xi + idx % (ldr - n_xi);
-        rk[l * ldr + al] = T(0);
-    }
-    __syncthreads();
-
-    // ck = inv_K rk, a 4-wide strip of modes per task
-    const T* A = inv + cell * NPP * NPP;
-    const int nab = ldr / 4;
-    for (int task = threadIdx.x; task < NPP * nab; task += blockDim.x) {
-        const int l = task / nab;
-        const int a0 = (task % nab) * 4;
-        T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
-        const T* arow = A + (long long)l * NPP;
-        for (int m = 0; m < NPP; ++m) {
-            const T av = arow[m];
-            const T* rr = rk + m * ldr + a0;
-            acc0 += av * rr[0];
-            acc1 += av * rr[1];
-            acc2 += av * rr[2];
-            acc3 += av * rr[3];
-        }
-        T* cw = ck + l * ldr + a0;
-        cw[0] = acc0;
-        cw[1] = acc1;
-        cw[2] = acc2;
-        cw[3] = acc3;
-    }
-    __syncthreads();
-
-    // weighted scatter-add (coloured: no other cell of this colour touches these nodes)
-    for (int idx = threadIdx.x; idx < NPP * n_xi; idx += blockDim.x) {
-        const int p = idx % NP;
-        const int i = (idx / NP) % NT;
-        const int al = idx / NPP;
-        bool bnd, first;
-        int mult;
-        const long long node = node_of(p, &bnd, &first, &mult);
-        const long long gi = ((long long)al * NT + i) * nn + node;
-        if (bnd) {
-            if (first) x[gi] = b[gi];
-        } else {
-            x[gi] += omega * ck[(i * NP + p) * ldr + al] / T(mult);
+#pragma unroll
+        for (int u = 0; u < SW; ++u) {
+            const int al = strip * SW + u;
+            if (al >= n_xi) break;
+            s_out[((long long)al * NT + i) * nbn + off] = acc[c][u];
         }
     }
 }
 
 template <int DIM, int K, int NT, typename T>
-hipError_t run_vanka(Grid g, int n_xi, const T* inv, const T* r, const T* b, T* x, T omega, hipStream_t s) {
+hipError_t run_vanka(Grid g, int n_xi, const T* invT, const T* r, T* s_out, hipStream_t s) {
     constexpr int NPP = NT * ipow(K + 1, DIM);
-    const int ldr = (n_xi + 3) & ~3;
-    const size_t lds = 2 * (size_t)NPP * ldr * sizeof(T);
-    for (int colour = 0; colour < (1 << DIM); ++colour) {
-        int par[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
-        int cells = 1;
-        for (int d = 0; d < DIM; ++d) {
-            par[d] = (colour >> d) & 1;
-            cnt[d] = (g.n - par[d] + 1) / 2;
-            cells *= cnt[d];
-        }
-        if (cells == 0) continue;
-        if (lds > 64 * 1024)
-            (void)hipFuncSetAttribute((const void*)k_vanka_apply<DIM, K, NT, T>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_vanka_apply<DIM, K, NT, T>), dim3(cells), dim3(256), lds, s, g, n_xi, par[0], par[1],
-                           par[2], cnt[0], cnt[1], cells, inv, r, b, x, omega);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    constexpr int SW = 12;
+    const int nstrip = (n_xi + SW - 1) / SW;
+    if (nstrip > 8) return hipErrorInvalidConfiguration;
+    const size_t lds = (size_t)NPP * nstrip * SW * sizeof(T);
+    auto kern = k_vanka_cells<DIM, K, NT, T, SW>;
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const int blocks = (int)g.n_cells;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * nstrip), lds, s, g, n_xi, blocks, invT, r, s_out);
+    return hipGetLastError();
 }
 
 template <int DIM, int K, typename T>
-hipError_t vanka_nt(int nt, Grid g, int n_xi, const T* inv, const T* r, const T* b, T* x, T omega, hipStream_t s) {
+hipError_t vanka_nt(int nt, Grid g, int n_xi, const T* invT, const T* r, T* s_out, hipStream_t s) {
     switch (nt) {
-        case 1: return run_vanka<DIM, K, 1, T>(g, n_xi, inv, r, b, x, omega, s);
-        case 2: return run_vanka<DIM, K, 2, T>(g, n_xi, inv, r, b, x, omega, s);
-        case 3: return run_vanka<DIM, K, 3, T>(g, n_xi, inv, r, b, x, omega, s);
-        case 4: return run_vanka<DIM, K, 4, T>(g, n_xi, inv, r, b, x, omega, s);
+        case 1: return run_vanka<DIM, K, 1, T>(g, n_xi, invT, r, s_out, s);
+        case 2: return run_vanka<DIM, K, 2, T>(g, n_xi, invT, r, s_out, s);
+        case 3: return run_vanka<DIM, K, 3, T>(g, n_xi, invT, r, s_out, s);
+        case 4: return run_vanka<DIM, K, 4, T>(g, n_xi, invT, r, s_out, s);
     }
     return hipErrorInvalidValue;
 }
 
 template <int DIM, typename T>
-hipError_t vanka_k(int k, int nt, Grid g, int n_xi, const T* inv, const T* r, const T* b, T* x, T omega,
-                   hipStream_t s) {
+hipError_t vanka_k(int k, int nt, Grid g, int n_xi, const T* invT, const T* r, T* s_out, hipStream_t s) {
     switch (k) {
-        case 1: return vanka_nt<DIM, 1, T>(nt, g, n_xi, inv, r, b, x, omega, s);
-        case 2: return vanka_nt<DIM, 2, T>(nt, g, n_xi, inv, r, b, x, omega, s);
-        case 3: return vanka_nt<DIM, 3, T>(nt, g, n_xi, inv, r, b, x, omega, s);
-        case 4: return vanka_nt<DIM, 4, T>(nt, g, n_xi, inv, r, b, x, omega, s);
+        case 1: return vanka_nt<DIM, 1, T>(nt, g, n_xi, invT, r, s_out, s);
+        case 2: return vanka_nt<DIM, 2, T>(nt, g, n_xi, invT, r, s_out, s);
+        case 3: return vanka_nt<DIM, 3, T>(nt, g, n_xi, invT, r, s_out, s);
+        case 4: return vanka_nt<DIM, 4, T>(nt, g, n_xi, invT, r, s_out, s);
     }
     return hipErrorInvalidValue;
 }
@@ -456,16 +441,16 @@ hipError_t launch_patch_invert(int dim, int k, int nt, Grid g, const double* E, 
 }
 
 template <typename T>
-hipError_t launch_vanka_apply(int dim, int k, int nt, Grid g, int n_xi, const T* inv, const T* r, const T* b,
-                              T* x, T omega, hipStream_t s) {
-    if (dim == 2) return vanka_k<2, T>(k, nt, g, n_xi, inv, r, b, x, omega, s);
-    if (dim == 3) return vanka_k<3, T>(k, nt, g, n_xi, inv, r, b, x, omega, s);
+hipError_t launch_vanka_cells(int dim, int k, int nt, Grid g, int n_xi, const T* invT, const T* r, T* s_out,
+                              hipStream_t s) {
+    if (dim == 2) return vanka_k<2, T>(k, nt, g, n_xi, invT, r, s_out, s);
+    if (dim == 3) return vanka_k<3, T>(k, nt, g, n_xi, invT, r, s_out, s);
     return hipErrorInvalidValue;
 }
 
-template hipError_t launch_vanka_apply<double>(int, int, int, Grid, int, const double*, const double*,
-                                               const double*, double*, double, hipStream_t);
-template hipError_t launch_vanka_apply<float>(int, int, int, Grid, int, const float*, const float*, const float*,
-                                              float*, float, hipStream_t);
+template hipError_t launch_vanka_cells<double>(int, int, int, Grid, int, const double*, const double*, double*,
+                                               hipStream_t);
+template hipError_t launch_vanka_cells<float>(int, int, int, Grid, int, const float*, const float*, float*,
+                                              hipStream_t);
 
 }  // namespace sg

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -111,6 +112,8 @@ struct sg_handle_s {
     // Krylov workspace
     int restart = 30;
     DevBuf<double> V, Z, w1, w2, partial, dscal;
+    // cell-local results in the broken node layout (shared by every operator call; FP32 calls reuse it)
+    DevBuf<double> sbuf;
     std::vector<double> hbuf;
     long long N = 0;
 };
@@ -245,8 +248,10 @@ sg_status build(sg_handle h) {
         return fail(SG_EUNSUPPORTED, "the block-Jacobi preconditioner needs an affine coefficient (mu in {0, e_m})");
     if (h->npp > 256) return fail(SG_EUNSUPPORTED, "Vanka patches larger than 256 DoFs are not supported");
     {
-        const size_t lds_apply = (size_t)(h->n_xi * h->NT + h->n_mu) * h->NP * sizeof(double);
-        const size_t lds_vanka = 2 * (size_t)h->npp * ((h->n_xi + 3) & ~3) * sizeof(double);
+        const size_t n_ent_max = (size_t)h->n_xi * (2 * d.n_vars + 1) * 4;
+        const size_t lds_apply = (size_t)(h->n_xi * h->NT + h->n_mu) * h->NP * sizeof(double) + n_ent_max * 16;
+        const size_t lds_vanka = (size_t)h->npp * ((h->n_xi + 11) / 12) * 12 * sizeof(double);
+        if ((h->n_xi + 11) / 12 > 8) return fail(SG_EUNSUPPORTED, "N_xi must be <= 96 for the Vanka kernel");
         if (lds_apply > 160 * 1024 || lds_vanka > 160 * 1024)
             return fail(SG_EUNSUPPORTED, "problem too large for one workgroup's LDS (N_xi * N_t * (k+1)^d)");
     }
@@ -525,6 +530,7 @@ sg_status build(sg_handle h) {
     SG_TRY(h->w2.alloc(h->N, "Krylov work"));
     SG_TRY(h->partial.alloc((size_t)kDotBlocks * (h->restart + 2), "partials"));
     SG_TRY(h->dscal.alloc(3 * 80, "scalars"));
+    SG_TRY(h->sbuf.alloc((size_t)h->n_xi * h->NT * h->lv[0].g.n_cells * h->NP, "cell-local results"));
     SG_HIP(hipDeviceSynchronize());
     return SG_OK;
 }
@@ -563,11 +569,15 @@ struct Prec<float> {
     static const float* rw(const Level& l) { return l.r_w32.p; }
 };
 
-int pick_cpb(int nc, int n_mu, int np, size_t elem) {
-    // as many cells per workgroup as fit 512 threads and ~64 KiB of LDS
-    int cpb = std::max(1, 512 / nc);
-    while (cpb > 1 && (size_t)(nc + n_mu) * np * cpb * elem > 64 * 1024) --cpb;
-    return cpb;
+// Cells per workgroup of the apply kernel: chosen from the kernel's occupancy unless the
+// SGHEAT_APPLY_CPB environment variable fixes it (a tuning override).
+int apply_cpb_override() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = std::getenv("SGHEAT_APPLY_CPB");
+        v = e ? std::max(0, std::atoi(e)) : 0;
+    }
+    return v;
 }
 
 template <typename T>
@@ -597,8 +607,23 @@ ApplyOp<T> make_op(const sg_handle h, int level, bool full) {
         op.cw = Prec<T>::cwm(h);
     }
     op.mean = !full;
-    op.cells_per_block = pick_cpb(h->n_xi * h->NT, op.n_mu, h->NP, sizeof(T));
+    op.n_ent = full ? (int)h->cpl.beta.size() : h->n_xi;
+    op.cells_per_block = apply_cpb_override();
     return op;
+}
+
+template <typename T>
+T* sbuf_as(sg_handle h) {
+    return reinterpret_cast<T*>(h->sbuf.p);
+}
+
+// y = A x (b == nullptr) or y = b - A x, for the operator described by op
+template <typename T>
+sg_status op_apply(sg_handle h, const ApplyOp<T>& op, const T* x, T* y, const T* b, hipStream_t s) {
+    SG_HIP(launch_apply<T>(op, x, sbuf_as<T>(h), s));
+    SG_HIP(launch_node_gather<T>(b ? GATHER_RESIDUAL : GATHER_SET, op.dim, op.k, op.g, h->n_xi * h->NT, sbuf_as<T>(h), x,
+                                 b, y, T(0), s));
+    return SG_OK;
 }
 
 template <typename T>
@@ -609,11 +634,12 @@ sg_status smooth_level(sg_handle h, int l, const T* b, T* x, int sweeps, bool x_
     for (int it = 0; it < sweeps; ++it) {
         const T* r = b;   // with x = 0 the residual b - A_0 x is b itself
         if (!(x_is_zero && it == 0)) {
-            SG_HIP(launch_apply<T>(op, x, Prec<T>::r(lv), b, s));
+            SG_TRY(op_apply<T>(h, op, x, Prec<T>::r(lv), b, s));
             r = Prec<T>::r(lv);
         }
-        SG_HIP(launch_vanka_apply<T>(h->d.dim, h->d.fe_degree, h->NT, lv.g, h->n_xi, inv, r, b, x,
-                                     (T)h->d.vanka_omega, s));
+        SG_HIP(launch_vanka_cells<T>(h->d.dim, h->d.fe_degree, h->NT, lv.g, h->n_xi, inv, r, sbuf_as<T>(h), s));
+        SG_HIP(launch_node_gather<T>(GATHER_VANKA, h->d.dim, h->d.fe_degree, lv.g, h->n_xi * h->NT, sbuf_as<T>(h),
+                                     nullptr, b, x, (T)h->d.vanka_omega, s));
     }
     return SG_OK;
 }
@@ -678,7 +704,7 @@ sg_status vcycle_level(sg_handle h, int l, const T* b, T* x, hipStream_t s) {
     SG_HIP(launch_fill<T>(x, T(0), lv.len, s));
     SG_TRY(smooth_level<T>(h, l, b, x, h->d.pre_smooth, true, s));
     const ApplyOp<T> op = make_op<T>(h, l, false);
-    SG_HIP(launch_apply<T>(op, x, Prec<T>::r(lv), b, s));
+    SG_TRY(op_apply<T>(h, op, x, Prec<T>::r(lv), b, s));
     Level& lc = h->lv[l + 1];
     SG_TRY(restrict_to<T>(h, l, Prec<T>::r(lv), Prec<T>::b(lc), s));
     SG_TRY(vcycle_level<T>(h, l + 1, Prec<T>::b(lc), Prec<T>::x(lc), s));
@@ -756,7 +782,7 @@ sg_status sg_operator_apply(sg_handle h, const double* x, double* y, void* hip_s
     if (!h || !x || !y) return fail(SG_EINVAL, "null argument");
     if (overlap(x, y, h->N * sizeof(double))) return fail(SG_EINVAL, "x and y overlap");
     const ApplyOp<double> op = make_op<double>(h, 0, true);
-    SG_HIP(launch_apply<double>(op, x, y, nullptr, (hipStream_t)hip_stream));
+    SG_TRY(op_apply<double>(h, op, x, y, nullptr, (hipStream_t)hip_stream));
     return SG_OK;
 }
 
@@ -822,7 +848,7 @@ sg_status fgmres_solve_slab(sg_handle h, const double* b, double* x, double rtol
         while (true) {
             // true residual r = b - AA x into V[0]
             SG_HIP(mark(ev_apply));
-            SG_HIP(launch_apply<double>(op, x, V, b, s));
+            SG_TRY(op_apply<double>(h, op, x, V, b, s));
             SG_HIP(mark(ev_apply));
             inf.applies++;
             const double beta = std::sqrt(dev_dot_sync(h, V, V, n, s, &st));
@@ -844,7 +870,7 @@ sg_status fgmres_solve_slab(sg_handle h, const double* b, double* x, double rtol
                 SG_HIP(mark(ev_prec));
                 inf.vcycles++;
                 SG_HIP(mark(ev_apply));
-                SG_HIP(launch_apply<double>(op, zj, h->w1.p, nullptr, s));
+                SG_TRY(op_apply<double>(h, op, zj, h->w1.p, nullptr, s));
                 SG_HIP(mark(ev_apply));
                 inf.applies++;
                 const int kk = j + 1;

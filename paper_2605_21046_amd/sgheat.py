@@ -12,7 +12,7 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsgheat.so")
+LIB_PATH = os.environ.get("SGHEAT_LIB", os.path.join(_HERE, "libsgheat.so"))
 
 SG_OK, SG_NOT_CONVERGED = 0, 1
 SG_FP64, SG_MIXED = 0, 1
