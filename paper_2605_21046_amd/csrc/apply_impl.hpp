@@ -44,6 +44,8 @@ struct ApplyArgs {
     Grid g;
     int cpb;
     int nblocks;
+    int mu0;              // position of mu = 0 in the coefficient list
+    int mum[8];           // position of mu = e_m (m = 1..M) in the coefficient list, -1 if absent
 };
 
 // out[.., o, ..] (+)= sum_i M(o, i) in[.., i, ..] along direction DIR of an N1^DIM point block;
@@ -64,6 +66,34 @@ __device__ __forceinline__ void sweep(const T (&in)[ipow(N1, DIM)], T (&out)[ipo
             out[base + o * st] = acc;
         }
     }
+}
+
+// In-place variant: one line of N1 values is staged in registers at a time.
+template <int DIM, int N1, int DIR, bool TR, typename T>
+__device__ __forceinline__ void sweep_ip(T (&v)[ipow(N1, DIM)], const T* __restrict__ M) {
+    constexpr int NP = ipow(N1, DIM);
+    constexpr int st = ipow(N1, DIR);
+#pragma unroll
+    for (int base = 0; base < NP; ++base) {
+        if ((base / st) % N1 != 0) continue;
+        T tmp[N1];
+#pragma unroll
+        for (int i = 0; i < N1; ++i) tmp[i] = v[base + i * st];
+#pragma unroll
+        for (int o = 0; o < N1; ++o) {
+            T acc = T(0);
+#pragma unroll
+            for (int i = 0; i < N1; ++i) acc += (TR ? M[i * N1 + o] : M[o * N1 + i]) * tmp[i];
+            v[base + o * st] = acc;
+        }
+    }
+}
+
+template <int DIM, int N1, bool TR, typename T>
+__device__ __forceinline__ void sweeps_ip(T (&v)[ipow(N1, DIM)], const T* __restrict__ M) {
+    sweep_ip<DIM, N1, 0, TR>(v, M);
+    sweep_ip<DIM, N1, 1, TR>(v, M);
+    if constexpr (DIM == 3) sweep_ip<DIM, N1, 2, TR>(v, M);
 }
 
 // Keeps the scheduler from hoisting every unrolled load of a long loop ahead of its uses, which
@@ -107,12 +137,99 @@ __device__ __forceinline__ void store_broken(T* __restrict__ s, const T (&Y)[ipo
     }
 }
 
+// ---- compile-time chaos structure for affine coefficients ------------------------------------------
+// Total-degree index set Lambda_p in graded, lexicographically descending order, and for every
+// alpha the positions of alpha - e_m and alpha + e_m (or -1).  For mu = e_m the Galerkin tensor is
+// [G_{e_m}]_{alpha beta} = sqrt(max(alpha_m, beta_m)) when beta = alpha +- e_m, zero otherwise.
+constexpr int binom_c(int n, int k) {
+    long long r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return (int)r;
+}
+
+template <int M, int P>
+struct ChaosTab {
+    static constexpr int N = binom_c(M + P, P);
+    int idx[N][M];
+    int nbm[N][M];
+    int nbp[N][M];
+    constexpr ChaosTab() : idx{}, nbm{}, nbp{} {
+        int pos = 0;
+        for (int deg = 0; deg <= P; ++deg) {
+            int a[M] = {};
+            a[0] = deg;
+            while (true) {
+                for (int m = 0; m < M; ++m) idx[pos][m] = a[m];
+                ++pos;
+                int j = -1;
+                for (int m = M - 2; m >= 0; --m)
+                    if (a[m] > 0) { j = m; break; }
+                if (j < 0) break;
+                int tail = 0;
+                for (int m = j + 1; m < M; ++m) { tail += a[m]; a[m] = 0; }
+                a[j] -= 1;
+                a[j + 1] = tail + 1;
+            }
+        }
+        for (int al = 0; al < N; ++al)
+            for (int m = 0; m < M; ++m) {
+                nbm[al][m] = -1;
+                nbp[al][m] = -1;
+                for (int be = 0; be < N; ++be) {
+                    bool minus = true, plus = true;
+                    for (int k = 0; k < M; ++k) {
+                        const int dm = idx[al][k] - (k == m ? 1 : 0);
+                        const int dp = idx[al][k] + (k == m ? 1 : 0);
+                        minus = minus && idx[be][k] == dm;
+                        plus = plus && idx[be][k] == dp;
+                    }
+                    if (minus) nbm[al][m] = be;
+                    if (plus) nbp[al][m] = be;
+                }
+            }
+    }
+};
+
+// sqrt(k) for the Hermite weights (k <= 8)
+__device__ constexpr double kSqrtTab[9] = {0.0, 1.0, 1.4142135623730951, 1.7320508075688772, 2.0,
+                                           2.2360679774997896, 2.4494897427831781, 2.6457513110645907,
+                                           2.8284271247461903};
+
+// Chaos coupling at one (cell, point, time index) for all modes, in registers: g[alpha] -> flux.
+template <int M, int P, int NT, int NP, typename T>
+__device__ __forceinline__ void couple_point(T* rows, const T* crow, int q, int ti, int mu0, const int* mum) {
+    constexpr ChaosTab<M, P> tab{};
+    constexpr int N = ChaosTab<M, P>::N;
+    T g[N];
+#pragma unroll
+    for (int al = 0; al < N; ++al) g[al] = rows[(al * NT + ti) * NP + q];
+    const T c0 = crow[mu0 * NP + q];
+    T cm[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) cm[m] = mum[m] >= 0 ? crow[mum[m] * NP + q] : T(0);
+#pragma unroll
+    for (int al = 0; al < N; ++al) {
+        T f = c0 * g[al];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int bm = tab.nbm[al][m], bp = tab.nbp[al][m];
+            if (bm < 0 && bp < 0) continue;
+            T t = T(0);
+            if (bm >= 0) t += T(kSqrtTab[tab.idx[al][m]]) * g[bm];
+            if (bp >= 0) t += T(kSqrtTab[tab.idx[al][m] + 1]) * g[bp];
+            f += cm[m] * t;
+        }
+        rows[(al * NT + ti) * NP + q] = f;
+    }
+}
+
 // Points u_q of one (cell, component) at the Gauss points are in U; W accumulates the integrand.
-template <int DIM, int K, int NT, typename T, bool MEAN>
+template <int DIM, int K, int NT, typename T, bool MEAN, int CM, int CP>
 __device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const Tables<T>& tb, T (&U)[ipow(K + 1, DIM)],
                                            T (&W)[ipow(K + 1, DIM)], T* slot_rows, const T* slot_coef,
                                            const int* ent_g, const int* ent_c, const T* ent_w, int e0, int e1,
-                                           int comp, int alpha, int ti, bool active, const int* cc) {
+                                           int comp, int alpha, int ti, bool active, const int* cc,
+                                           T* exch_all, const T* cl_all, int SS, int CS, long long cell_id) {
     constexpr int N1 = K + 1;
     constexpr int NP = ipow(N1, DIM);
     constexpr int NS = NP / N1;   // points per slice
@@ -168,6 +285,46 @@ __device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const Tables<T
                 }
             }
         }
+    } else if constexpr (CM > 0) {
+        // affine chaos coupling transposed: (cell, component) threads write d u / d x_dir, then
+        // (cell, point, time) threads couple all modes in registers in place, then each
+        // (cell, component) thread integrates its own flux row
+        __syncthreads();
+        const int cpb = a.cpb;
+        const int ntask = cpb * NP * NT;
+#pragma unroll
+        for (int dir = 0; dir < DIM; ++dir) {
+            const int st = ipow(N1, dir);
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                const int qd = (q / st) % N1;
+                const int base = q - qd * st;
+                T g = T(0);
+#pragma unroll
+                for (int i = 0; i < N1; ++i) g += tb.D[qd * N1 + i] * U[base + i * st];
+                my_row[q] = g;
+            }
+            __syncthreads();
+            for (int task = threadIdx.x; task < ntask; task += blockDim.x) {
+                const int q = task % NP;
+                const int tb_i = (task / NP) % NT;
+                const int sl = task / (NP * NT);
+                couple_point<CM, CP, NT, NP, T>(exch_all + (size_t)sl * SS, cl_all + (size_t)sl * CS, q, tb_i, a.mu0,
+                                                a.mum);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < N1; ++s) {
+#pragma unroll
+                for (int j = 0; j < NS; ++j) {
+                    const int q = (j / st) * st * N1 + s * st + (j % st);
+                    const int base = q - s * st;
+                    const T f = my_row[q];
+#pragma unroll
+                    for (int o = 0; o < N1; ++o) W[base + o * st] += tb.D[s * N1 + o] * f;
+                }
+            }
+        }
     } else {
         __syncthreads();
         // stiffness term, one reference direction at a time
@@ -215,16 +372,8 @@ __device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const Tables<T
     }
 
     // integrate back to the nodes and store the cell-local result
-    if constexpr (DIM == 2) {
-        sweep<DIM, N1, 0, false, true>(W, U, tb.S);
-        sweep<DIM, N1, 1, false, true>(U, W, tb.S);
-        if (active) store_broken<DIM, K, T>(a.s, W, bt_of<NT>(tb, ti), cc, a.g.n, comp);
-    } else {
-        sweep<DIM, N1, 0, false, true>(W, U, tb.S);
-        sweep<DIM, N1, 1, false, true>(U, W, tb.S);
-        sweep<DIM, N1, 2, false, true>(W, U, tb.S);
-        if (active) store_broken<DIM, K, T>(a.s, U, bt_of<NT>(tb, ti), cc, a.g.n, comp);
-    }
+    sweeps_ip<DIM, N1, true>(W, tb.S);
+    if (active) store_broken<DIM, K, T>(a.s, W, bt_of<NT>(tb, ti), cc, a.g.n, comp);
 }
 
 // Minimum resident waves per SIMD the register allocator must allow (more waves hide the LDS and
@@ -241,7 +390,7 @@ __host__ __device__ constexpr int padded_stride(int n) {
     return n + ((1 - n) % nb + nb) % nb;
 }
 
-template <int DIM, int K, int NT, typename T, bool MEAN>
+template <int DIM, int K, int NT, typename T, bool MEAN, int CM = 0, int CP = 0>
 __global__ void __launch_bounds__(ipow(K + 1, DIM) > 27 ? 256 : 512)
     __attribute__((amdgpu_waves_per_eu(apply_waves_per_eu<ipow(K + 1, DIM), T>())))
     k_apply(ApplyArgs<T> a, Tables<T> tb) {
@@ -288,7 +437,7 @@ __global__ void __launch_bounds__(ipow(K + 1, DIM) > 27 ? 256 : 512)
         cl[s * CS + mu * NP + q] = (c2 < a.g.n_cells) ? a.coef[mu * a.coef_mode_stride + c2 * NP + q] : T(0);
     }
     // stage the coupling entries (beta, mu, w) as LDS offsets
-    if constexpr (!MEAN) {
+    if constexpr (!MEAN && CM == 0) {
         for (int e = t; e < a.n_ent; e += blockDim.x) {
             ent_w[e] = a.cw[e];
             ent_g[e] = a.cbeta[e] * NT * NP;
@@ -296,14 +445,13 @@ __global__ void __launch_bounds__(ipow(K + 1, DIM) > 27 ? 256 : 512)
         }
     }
     int e0 = 0, e1 = 0;
-    if constexpr (!MEAN) {
+    if constexpr (!MEAN && CM == 0) {
         e0 = a.cptr[alpha * a.n_mu];
         e1 = a.cptr[(alpha + 1) * a.n_mu];
     }
 
     T A[NP], B[NP];
     const long long cbase = ((long long)alpha * NT + ti) * nn;
-
     // gather (Dirichlet columns dropped)
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
@@ -324,18 +472,9 @@ __global__ void __launch_bounds__(ipow(K + 1, DIM) > 27 ? 256 : 512)
     T* const slot_rows = exch + (size_t)slot * SS;
     const T* const slot_coef = cl + (size_t)slot * CS;
     // values at the Gauss points, then the rest of the cell work
-    if constexpr (DIM == 2) {
-        sweep<DIM, N1, 0, false, false>(A, B, tb.S);
-        sweep<DIM, N1, 1, false, false>(B, A, tb.S);
-        apply_body<DIM, K, NT, T, MEAN>(a, tb, A, B, slot_rows, slot_coef, ent_g, ent_c, ent_w, e0, e1, comp, alpha,
-                                        ti, active, cc);
-    } else {
-        sweep<DIM, N1, 0, false, false>(A, B, tb.S);
-        sweep<DIM, N1, 1, false, false>(B, A, tb.S);
-        sweep<DIM, N1, 2, false, false>(A, B, tb.S);
-        apply_body<DIM, K, NT, T, MEAN>(a, tb, B, A, slot_rows, slot_coef, ent_g, ent_c, ent_w, e0, e1, comp, alpha,
-                                        ti, active, cc);
-    }
+    sweeps_ip<DIM, N1, false>(A, tb.S);
+    apply_body<DIM, K, NT, T, MEAN, CM, CP>(a, tb, A, B, slot_rows, slot_coef, ent_g, ent_c, ent_w, e0, e1, comp, alpha,
+                                            ti, active, cc, exch, cl, SS, CS, active ? ci : 0);
 }
 
 // Cells per workgroup: the largest number of busy lanes per CU allowed by the kernel's register use
@@ -355,7 +494,7 @@ inline int choose_cpb(const void* kern, int nc, size_t lds_fixed, size_t lds_per
         const int waves = (threads + 63) / 64;
         const int by_w = waves_cu / waves;
         const size_t lds = lds_fixed + lds_per_cell * cpb;
-        const int by_l = lds > 160 * 1024 ? 0 : (int)((160 * 1024) / lds);
+        const int by_l = lds > 160 * 1024 ? 0 : (lds == 0 ? 64 : (int)((160 * 1024) / lds));
         const int blocks = std::min(by_w, by_l);
         if (blocks == 0) continue;
         const long score = (long)blocks * threads;
@@ -373,6 +512,21 @@ hipError_t run_apply(const ApplyOp<T>& op, const T* x, T* s_out, hipStream_t s) 
     constexpr int NP = ipow(N1, DIM);
     constexpr int MAXT = NP > 27 ? 256 : 512;
     auto kern = op.mean ? k_apply<DIM, K, NT, T, true> : k_apply<DIM, K, NT, T, false>;
+    // register-resident chaos coupling for the affine index sets of the benchmark workloads
+    if (!op.mean && op.affine) {
+        if constexpr (DIM == 3 && K == 2 && NT == 2) {
+            if (op.chaos_m == 4 && op.chaos_p == 3) kern = k_apply<DIM, K, NT, T, false, 4, 3>;
+        }
+        if constexpr (DIM == 3 && K == 3 && NT == 3) {
+            if (op.chaos_m == 3 && op.chaos_p == 4) kern = k_apply<DIM, K, NT, T, false, 3, 4>;
+        }
+        if constexpr (DIM == 2 && K == 2 && NT == 2) {
+            if (op.chaos_m == 2 && op.chaos_p == 2) kern = k_apply<DIM, K, NT, T, false, 2, 2>;
+        }
+        if constexpr (DIM == 3 && K == 2 && NT == 2) {
+            if (op.chaos_m == 3 && op.chaos_p == 2) kern = k_apply<DIM, K, NT, T, false, 3, 2>;
+        }
+    }
     ApplyArgs<T> a{};
     a.x = x;
     a.s = s_out;
@@ -386,9 +540,11 @@ hipError_t run_apply(const ApplyOp<T>& op, const T* x, T* s_out, hipStream_t s) 
     a.n_mu = op.n_mu;
     a.n_ent = op.n_ent;
     a.g = op.g;
+    a.mu0 = op.mu0;
+    for (int m = 0; m < 8; ++m) a.mum[m] = op.mum[m];
     const int nc = op.n_xi * NT;
     const size_t per_cell = (size_t)(padded_stride<T>(nc * NP) + padded_stride<T>(op.n_mu * NP)) * sizeof(T);
-    const size_t fixed = (size_t)op.n_ent * (sizeof(T) + 2 * sizeof(int)) + 16;
+    const size_t fixed = op.mean ? 16 : (size_t)op.n_ent * (sizeof(T) + 2 * sizeof(int)) + 16;
     const int cpb = op.cells_per_block > 0 ? op.cells_per_block : choose_cpb((const void*)kern, nc, fixed, per_cell, MAXT);
     a.cpb = cpb;
     const int threads = nc * cpb;

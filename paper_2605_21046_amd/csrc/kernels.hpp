@@ -30,6 +30,10 @@ struct ApplyOp {
     int n_ent;                    // number of coupling entries
     int cells_per_block;          // cells handled by one workgroup (0 = chosen from occupancy)
     bool mean;                    // mean block only: identity coupling with the mean coefficient
+    bool affine;                  // coefficient modes are mu = 0 and mu = e_m only
+    int chaos_m, chaos_p;         // M and p_xi of the total-degree index set
+    int mu0;                      // position of mu = 0 in the coefficient list
+    int mum[8];                   // position of mu = e_m in the coefficient list (-1 if absent)
 };
 template <typename T>
 hipError_t launch_apply(const ApplyOp<T>& op, const T* x, T* s_out, hipStream_t s);

@@ -6,6 +6,8 @@
 //
 // Reductions are deterministic: a fixed number of blocks writes partial sums, and one block adds
 // them in a fixed order.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace sg {
@@ -44,70 +46,97 @@ __global__ void k_transfer_1d(int dim, long long total, int i0, int i1, int o0, 
 }
 
 // Sum of the broken copies of each node (fixed order: lower cell first in every direction), then the
-// requested update; one thread per (component, node), consecutive threads on consecutive x nodes.
-template <typename T, int OP, int DIM>
-__global__ void k_node_gather(int k, Grid g, long long total, const T* __restrict__ s_in, const T* __restrict__ x,
-                              const T* __restrict__ b, T* __restrict__ out, T omega) {
-    const int N1 = k + 1;
-    const long long nb1 = (long long)g.n * N1;
-    long long nbn = 1;
-    for (int d = 0; d < DIM; ++d) nbn *= nb1;
-    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
-         idx += (long long)gridDim.x * blockDim.x) {
-        const long long comp = idx / g.n_nodes;
-        long long r = idx - comp * g.n_nodes;
-        int cnt[3] = {1, 1, 1};
-        long long bi[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+// requested update; one thread per node of one component (component = blockIdx.y), consecutive
+// threads on consecutive x nodes.
+template <typename T, int OP, int DIM, int K>
+__global__ void __launch_bounds__(256)
+    k_node_gather(Grid g, const T* __restrict__ s_in, const T* __restrict__ x, const T* __restrict__ b,
+                  T* __restrict__ out, T omega) {
+    constexpr int N1 = K + 1;
+    const unsigned n1 = g.n1, nc = g.n;
+    const unsigned nb1 = nc * N1;
+    unsigned nbn = nb1;
+    if (DIM >= 2) nbn *= nb1;
+    if (DIM == 3) nbn *= nb1;
+    const unsigned nn = (unsigned)g.n_nodes;
+    const long long comp = blockIdx.y;
+    const T* sc = s_in + comp * (long long)nbn;
+    const long long vbase = comp * (long long)nn;
+    for (unsigned node = blockIdx.x * 256u + threadIdx.x; node < nn; node += gridDim.x * 256u) {
+        unsigned r = node;
+        // per direction: the broken index of this node in the lower and the upper cell (equal, with
+        // weight 0 for the upper one, when the node lies inside a cell along that direction)
+        unsigned lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        T whi[3] = {T(0), T(0), T(0)};
         bool bnd = false;
+#pragma unroll
         for (int d = 0; d < DIM; ++d) {
-            const int i = (int)(r % g.n1);
-            r /= g.n1;
-            bnd |= (i == 0) | (i == g.n1 - 1);
-            if (i % k == 0 && i > 0 && i < g.n1 - 1) {
-                const int c = i / k;
-                bi[d][0] = (long long)(c - 1) * N1 + k;
-                bi[d][1] = (long long)c * N1;
-                cnt[d] = 2;
+            const unsigned i = (d == DIM - 1) ? r : r % n1;
+            r /= n1;
+            bnd |= (i == 0) | (i == n1 - 1);
+            const unsigned c = i / K;
+            if (i % K == 0 && i > 0 && i < n1 - 1) {
+                lo[d] = (c - 1) * N1 + K;
+                hi[d] = c * N1;
+                whi[d] = T(1);
             } else {
-                const int c = min(i / k, g.n - 1);
-                bi[d][0] = (long long)c * N1 + (i - c * k);
+                const unsigned cl = c < nc ? c : nc - 1;
+                lo[d] = cl * N1 + (i - cl * K);
+                hi[d] = lo[d];
             }
         }
+        const long long gi = vbase + node;
         if (bnd) {
-            if (OP == GATHER_SET) out[idx] = x[idx];
-            else if (OP == GATHER_RESIDUAL) out[idx] = b[idx] - x[idx];
-            else out[idx] = b[idx];
+            if (OP == GATHER_SET) out[gi] = x[gi];
+            else if (OP == GATHER_RESIDUAL) out[gi] = b[gi] - x[gi];
+            else out[gi] = b[gi];
             continue;
         }
-        const T* sc = s_in + comp * nbn;
+        // fixed summation order: lower before upper in x, then y, then z
         T sum = T(0);
-        for (int z = 0; z < cnt[2]; ++z)
-            for (int y = 0; y < cnt[1]; ++y)
-                for (int xx = 0; xx < cnt[0]; ++xx) {
-                    long long o = bi[0][xx];
-                    if (DIM >= 2) o += bi[1][y] * nb1;
-                    if (DIM == 3) o += bi[2][z] * nb1 * nb1;
-                    sum += sc[o];
-                }
-        if (OP == GATHER_SET) out[idx] = sum;
-        else if (OP == GATHER_RESIDUAL) out[idx] = b[idx] - sum;
-        else out[idx] = out[idx] + omega * sum / T(cnt[0] * cnt[1] * cnt[2]);
+        T cnt = T(1);
+        if (DIM == 2) {
+            const unsigned y0 = lo[1] * nb1, y1 = hi[1] * nb1;
+            sum = (sc[y0 + lo[0]] + whi[0] * sc[y0 + hi[0]]) + whi[1] * (sc[y1 + lo[0]] + whi[0] * sc[y1 + hi[0]]);
+            cnt = (T(1) + whi[0]) * (T(1) + whi[1]);
+        } else {
+            const unsigned z0 = lo[2] * nb1 * nb1, z1 = hi[2] * nb1 * nb1;
+            const unsigned y0 = lo[1] * nb1, y1 = hi[1] * nb1;
+            const T s00 = sc[z0 + y0 + lo[0]] + whi[0] * sc[z0 + y0 + hi[0]];
+            const T s01 = sc[z0 + y1 + lo[0]] + whi[0] * sc[z0 + y1 + hi[0]];
+            const T s10 = sc[z1 + y0 + lo[0]] + whi[0] * sc[z1 + y0 + hi[0]];
+            const T s11 = sc[z1 + y1 + lo[0]] + whi[0] * sc[z1 + y1 + hi[0]];
+            sum = (s00 + whi[1] * s01) + whi[2] * (s10 + whi[1] * s11);
+            cnt = (T(1) + whi[0]) * (T(1) + whi[1]) * (T(1) + whi[2]);
+        }
+        if (OP == GATHER_SET) out[gi] = sum;
+        else if (OP == GATHER_RESIDUAL) out[gi] = b[gi] - sum;
+        else out[gi] = out[gi] + omega * sum / cnt;
     }
 }
 
 template <typename T>
-__global__ void k_coarse_solve(const double* __restrict__ AinvT, int nint, const int* __restrict__ dofs, int n_xi,
-                               long long mode_len, const T* __restrict__ b, T* __restrict__ x) {
-    const long long total = (long long)nint * n_xi;
-    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
-         idx += (long long)gridDim.x * blockDim.x) {
-        const int row = idx % nint;
-        const int al = idx / nint;
-        const T* bm = b + al * mode_len;
-        double acc = 0.0;
-        for (int l = 0; l < nint; ++l) acc += AinvT[(long long)l * nint + row] * (double)bm[dofs[l]];
-        x[al * mode_len + dofs[row]] = (T)acc;
+__global__ void __launch_bounds__(256)
+    k_coarse_solve(const double* __restrict__ AinvT, int nint, const int* __restrict__ dofs, long long mode_len,
+                   const T* __restrict__ b, T* __restrict__ x) {
+    extern __shared__ unsigned char smem_raw[];
+    double* bl = reinterpret_cast<double*>(smem_raw);   // [nint]
+    const int al = blockIdx.y;
+    const T* bm = b + al * mode_len;
+    for (int l = threadIdx.x; l < nint; l += blockDim.x) bl[l] = (double)bm[dofs[l]];
+    __syncthreads();
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= nint) return;
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    int l = 0;
+    for (; l + 3 < nint; l += 4) {
+        acc0 += AinvT[(long long)l * nint + row] * bl[l];
+        acc1 += AinvT[(long long)(l + 1) * nint + row] * bl[l + 1];
+        acc2 += AinvT[(long long)(l + 2) * nint + row] * bl[l + 2];
+        acc3 += AinvT[(long long)(l + 3) * nint + row] * bl[l + 3];
     }
+    for (; l < nint; ++l) acc0 += AinvT[(long long)l * nint + row] * bl[l];
+    x[al * mode_len + dofs[row]] = (T)((acc0 + acc1) + (acc2 + acc3));
 }
 
 template <typename T>
@@ -270,18 +299,27 @@ hipError_t launch_transfer_1d(int dim, int ncomp, const int* in_dims, const int*
 template <typename T>
 hipError_t launch_node_gather(GatherOp op, int dim, int k, Grid g, int ncomp, const T* s_in, const T* x, const T* b,
                               T* out, T omega, hipStream_t s) {
-    const long long total = g.n_nodes * ncomp;
-    const dim3 grid(grid_for(total, 256, 65536)), block(256);
-#define SG_NG(OP_, D_) hipLaunchKernelGGL((k_node_gather<T, OP_, D_>), grid, block, 0, s, k, g, total, s_in, x, b, out, omega)
-    if (dim == 2) {
-        if (op == GATHER_SET) SG_NG(GATHER_SET, 2);
-        else if (op == GATHER_RESIDUAL) SG_NG(GATHER_RESIDUAL, 2);
-        else SG_NG(GATHER_VANKA, 2);
-    } else {
-        if (op == GATHER_SET) SG_NG(GATHER_SET, 3);
-        else if (op == GATHER_RESIDUAL) SG_NG(GATHER_RESIDUAL, 3);
-        else SG_NG(GATHER_VANKA, 3);
+    if (ncomp > 65535 || g.n_nodes > 0x7fffffffLL || k < 1 || k > 4) return hipErrorInvalidConfiguration;
+    const unsigned bx = std::min<long long>((g.n_nodes + 255) / 256, 4096);
+    const dim3 grid(bx, ncomp), block(256);
+#define SG_NG(OP_, D_, K_) hipLaunchKernelGGL((k_node_gather<T, OP_, D_, K_>), grid, block, 0, s, g, s_in, x, b, out, omega)
+#define SG_NG_K(OP_, D_)                          \
+    switch (k) {                                  \
+        case 1: SG_NG(OP_, D_, 1); break;         \
+        case 2: SG_NG(OP_, D_, 2); break;         \
+        case 3: SG_NG(OP_, D_, 3); break;         \
+        default: SG_NG(OP_, D_, 4); break;        \
     }
+    if (dim == 2) {
+        if (op == GATHER_SET) { SG_NG_K(GATHER_SET, 2) }
+        else if (op == GATHER_RESIDUAL) { SG_NG_K(GATHER_RESIDUAL, 2) }
+        else { SG_NG_K(GATHER_VANKA, 2) }
+    } else {
+        if (op == GATHER_SET) { SG_NG_K(GATHER_SET, 3) }
+        else if (op == GATHER_RESIDUAL) { SG_NG_K(GATHER_RESIDUAL, 3) }
+        else { SG_NG_K(GATHER_VANKA, 3) }
+    }
+#undef SG_NG_K
 #undef SG_NG
     return hipGetLastError();
 }
@@ -291,9 +329,12 @@ hipError_t launch_coarse_solve(const double* AinvT, int nint, const int* dofs, i
                                const T* b, T* x, hipStream_t s) {
     const long long n = mode_len * n_xi;
     hipLaunchKernelGGL(k_copy<T>, dim3(grid_for(n, 256)), dim3(256), 0, s, b, x, n);
-    const long long total = (long long)nint * n_xi;
-    hipLaunchKernelGGL(k_coarse_solve<T>, dim3(grid_for(total, 64, 65536)), dim3(64), 0, s, AinvT, nint, dofs, n_xi,
-                       mode_len, b, x);
+    const size_t lds = (size_t)nint * sizeof(double);
+    if (lds > 160 * 1024 || n_xi > 65535) return hipErrorInvalidConfiguration;
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute((const void*)k_coarse_solve<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_coarse_solve<T>, dim3((nint + 255) / 256, n_xi), dim3(256), lds, s, AinvT, nint, dofs, mode_len,
+                       b, x);
     return hipGetLastError();
 }
 

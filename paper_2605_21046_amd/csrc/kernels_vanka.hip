@@ -266,20 +266,20 @@ __global__ void __launch_bounds__(TG * TG)
 }
 
 // ------------------------------------------------------------------------------------------------
-// One workgroup per cell, one wave per strip of SW chaos modes.  Lane l owns patch rows l, l + 64,
-// ...; the patch inverse is stored transposed so that, for a fixed column m, the 64 lanes read 64
-// consecutive entries; the residual patch rk[m][strip] is an LDS broadcast.  The correction of the
-// cell goes to the broken node array (summed per node by k_node_gather).
+// One workgroup per cell, one wave per chunk of 64 patch rows.  Lane l owns row l of its chunk and
+// keeps SW chaos modes in registers (all of them when N_xi <= SW, else strips in turn); the patch
+// inverse is stored transposed so that, for a fixed column m, the 64 lanes read 64 consecutive
+// entries, and every entry is read once; the residual patch rk[m][mode] is an LDS broadcast.  The
+// correction of the cell goes to the broken node array (summed per node by k_node_gather).
 template <int DIM, int K, int NT, typename T, int SW>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(256)
     k_vanka_cells(Grid g, int n_xi, int nblocks, const T* __restrict__ invT, const T* __restrict__ r,
                   T* __restrict__ s_out) {
     constexpr int N1 = K + 1;
     constexpr int NP = ipow(N1, DIM);
     constexpr int NPP = NT * NP;
-    constexpr int RCH = (NPP + 63) / 64;
     extern __shared__ unsigned char smem_raw[];
-    const int nstrip = blockDim.x / 64;
+    const int nstrip = (n_xi + SW - 1) / SW;
     const int ldr = nstrip * SW;
     T* rk = reinterpret_cast<T*>(smem_raw);   // [NPP][ldr]
 
@@ -314,51 +314,47 @@ __global__ void __launch_bounds__(512)
     }
     __syncthreads();
 
-    const int lane = threadIdx.x % 64;
-    const int strip = threadIdx.x / 64;
-    T acc[RCH][SW];
-#pragma unroll
-    for (int c = 0; c < RCH; ++c)
-#pragma unroll
-        for (int u = 0; u < SW; ++u) acc[c][u] = T(0);
-    const T* A = invT + cell * NPP * NPP;
-    const T* rs = rk + strip * SW;
-#pragma unroll 2
-    for (int m = 0; m < NPP; ++m) {
-        T av[RCH];
-#pragma unroll
-        for (int c = 0; c < RCH; ++c) {
-            const int l = lane + 64 * c;
-            av[c] = (l < NPP) ? A[(long long)m * NPP + l] : T(0);
-        }
-        const T* rr = rs + m * ldr;
-#pragma unroll
-        for (int u = 0; u < SW; ++u) {
-            const T rv = rr[u];
-#pragma unroll
-            for (int c = 0; c < RCH; ++c) acc[c][u] += av[c] * rv;
-        }
-    }
-
-    // cell-local correction into the broken layout [comp][b_z][b_y][b_x]
+    const int l = threadIdx.x;            // patch row of this lane
+    if (l >= NPP) return;
+    const T* A = invT + cell * NPP * NPP + l;
     const long long nb1 = (long long)g.n * N1;
     long long nbn = 1;
     for (int d = 0; d < DIM; ++d) nbn *= nb1;
+    const int p = l % NP, i = l / NP;
+    long long off = 0, mul = 1;
+    for (int d = 0; d < DIM; ++d) {
+        off += ((long long)cc[d] * N1 + (p / ipow(N1, d)) % N1) * mul;
+        mul *= nb1;
+    }
+    constexpr int U = 8;                  // columns of the inverse in flight per lane
+    for (int strip = 0; strip < nstrip; ++strip) {
+        T acc[SW];
 #pragma unroll
-    for (int c = 0; c < RCH; ++c) {
-        const int l = lane + 64 * c;
-        if (l >= NPP) continue;
-        const int p = l % NP, i = l / NP;
-        long long off = 0, mul = 1;
-        for (int d = 0; d < DIM; ++d) {
-            off += ((long long)cc[d] * N1 + (p / ipow(N1, d)) % N1) * mul;
-            mul *= nb1;
+        for (int u = 0; u < SW; ++u) acc[u] = T(0);
+        const T* rs = rk + strip * SW;
+        T nxt[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) nxt[u] = (u < NPP) ? A[(long long)u * NPP] : T(0);
+        for (int m0 = 0; m0 < NPP; m0 += U) {
+            T cur[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+            // prefetch the next U columns while this chunk is multiplied
+#pragma unroll
+            for (int u = 0; u < U; ++u) nxt[u] = (m0 + U + u < NPP) ? A[(long long)(m0 + U + u) * NPP] : T(0);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (m0 + u >= NPP) break;
+                const T* rr = rs + (m0 + u) * ldr;
+#pragma unroll
+                for (int k2 = 0; k2 < SW; ++k2) acc[k2] += cur[u] * rr[k2];
+            }
         }
+        // cell-local correction into the broken layout [comp][b_z][b_y][b_x]
 #pragma unroll
         for (int u = 0; u < SW; ++u) {
             const int al = strip * SW + u;
-            if (al >= n_xi) break;
-            s_out[((long long)al * NT + i) * nbn + off] = acc[c][u];
+            if (al < n_xi) s_out[((long long)al * NT + i) * nbn + off] = acc[u];
         }
     }
 }
@@ -366,15 +362,16 @@ __global__ void __launch_bounds__(512)
 template <int DIM, int K, int NT, typename T>
 hipError_t run_vanka(Grid g, int n_xi, const T* invT, const T* r, T* s_out, hipStream_t s) {
     constexpr int NPP = NT * ipow(K + 1, DIM);
-    constexpr int SW = 12;
+    constexpr int SW = 36;
     const int nstrip = (n_xi + SW - 1) / SW;
-    if (nstrip > 8) return hipErrorInvalidConfiguration;
     const size_t lds = (size_t)NPP * nstrip * SW * sizeof(T);
+    if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
     auto kern = k_vanka_cells<DIM, K, NT, T, SW>;
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     const int blocks = (int)g.n_cells;
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * nstrip), lds, s, g, n_xi, blocks, invT, r, s_out);
+    const int threads = ((NPP + 63) / 64) * 64;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds, s, g, n_xi, blocks, invT, r, s_out);
     return hipGetLastError();
 }
 

@@ -250,8 +250,7 @@ sg_status build(sg_handle h) {
     {
         const size_t n_ent_max = (size_t)h->n_xi * (2 * d.n_vars + 1) * 4;
         const size_t lds_apply = (size_t)(h->n_xi * h->NT + h->n_mu) * h->NP * sizeof(double) + n_ent_max * 16;
-        const size_t lds_vanka = (size_t)h->npp * ((h->n_xi + 11) / 12) * 12 * sizeof(double);
-        if ((h->n_xi + 11) / 12 > 8) return fail(SG_EUNSUPPORTED, "N_xi must be <= 96 for the Vanka kernel");
+        const size_t lds_vanka = (size_t)h->npp * ((h->n_xi + 35) / 36) * 36 * sizeof(double);
         if (lds_apply > 160 * 1024 || lds_vanka > 160 * 1024)
             return fail(SG_EUNSUPPORTED, "problem too large for one workgroup's LDS (N_xi * N_t * (k+1)^d)");
     }
@@ -608,6 +607,17 @@ ApplyOp<T> make_op(const sg_handle h, int level, bool full) {
     }
     op.mean = !full;
     op.n_ent = full ? (int)h->cpl.beta.size() : h->n_xi;
+    op.affine = h->cpl.affine && h->d.n_vars <= 8;
+    op.chaos_m = h->d.n_vars;
+    op.chaos_p = h->d.chaos_degree;
+    op.mu0 = h->cpl.mu0;
+    for (int m = 0; m < 8; ++m) op.mum[m] = -1;
+    for (int k = 0; k < h->n_mu; ++k) {
+        int nz = -1, cnt = 0;
+        for (int m = 0; m < h->d.n_vars; ++m)
+            if (h->coef_mu[k * h->d.n_vars + m] != 0) { nz = m; ++cnt; }
+        if (cnt == 1 && nz < 8 && h->coef_mu[k * h->d.n_vars + nz] == 1) op.mum[nz] = k;
+    }
     op.cells_per_block = apply_cpb_override();
     return op;
 }
