@@ -1,13 +1,16 @@
 #!/usr/bin/env python3
 """Benchmark of the stochastic-Galerkin slab hot path on one MI355X.
 
-Metric (one JSON line on stdout):
-  * value = SG operator apply throughput in GDoF/s (N_DoF per apply / apply time) on the 3D
-    workload "Q2 on 32^3 cells, dG(1), M = 4, p_xi = 3" (19,223,750 DoFs), with % of HBM peak;
-  * solve = FGMRES-GMG slab solve time to a true relative residual of 1e-8, FP64 and mixed.
-A step is one FP64 slab solve (FGMRES + V-cycles + Vanka + applies: the whole path); the apply
-rate is timed separately over rotating input/output pairs so the 256 MB Infinity Cache cannot hold
-them.  All inputs are synthetic and seeded.
+One JSON line on stdout:
+  * value = SG operator apply throughput in GDoF/s (N_DoF / median apply time) on the 3D workload
+    "Q2 on 32^3 cells, dG(1), M = 4, p_xi = 3" (19,223,750 DoFs), timed over rotating input/output
+    pairs so the 256 MB Infinity Cache cannot hold them;
+  * roofline = the apply against the FP64 peak (its arithmetic intensity is above the ridge), with
+    roofline_hbm against 8 TB/s and the HBM traffic measured by rocprofv3 counters;
+  * solve = FGMRES-GMG slab solve time to a true relative residual of 1e-8, FP64 and mixed; a step is
+    one FP64 slab solve (FGMRES + V-cycles + Vanka + applies: the whole path);
+  * cpu_baseline = the FP64 CPU oracle's apply on a reduced mesh of the same discretisation.
+All inputs are synthetic and seeded.
 """
 from __future__ import annotations
 
@@ -22,6 +25,29 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 (vector and matrix)
+
+_CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2605_21046_amd", "csrc")
+# sources of the two kernels of one operator apply (k_apply, then k_node_gather)
+APPLY_SOURCES = ["device_common.hpp", "kernels.hpp", "apply_impl.hpp", "apply_3d_f64.hip", "apply_2d_f64.hip",
+                 "kernels_apply.hip", "kernels_misc.hip"]
+
+# HBM bytes per operator apply from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (k_apply + k_node_gather),
+# each scaled by what the same counter reads for a plain device copy of known size.  Keyed by workload
+# and by the hash of the kernel sources the counters were taken on: after any change to those
+# sources the entry no longer matches and the traffic is reported as null until it is measured again.
+MEASURED_TRAFFIC = {
+    # profiles/sg_apply_c2_hbm_traffic.md
+    ("c2", "d77f722ece2a278d"): {"fetch_bytes": 1144437137, "write_bytes": 1010230169},
+}
+
+
+def apply_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in APPLY_SOURCES:
+        with open(os.path.join(_CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def apply_model(w):
@@ -50,10 +76,35 @@ def apply_model(w):
     return n_dof, bytes_, flops
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _time_oracle_apply(P, x, seconds_target, max_reps=50):
+    P.apply_route2(x)
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        P.apply_route2(x)
+        reps += 1
+        if time.perf_counter() - t0 > seconds_target or reps >= max_reps:
+            break
+    return (time.perf_counter() - t0) / reps, reps
+
+
 def cpu_baseline(w, seconds_target=15.0):
     """The oracle's route-2 apply (scipy sparse x dense blocks), single thread, on a reduced mesh of
-    the same discretisation; assembly is not timed (as on the GPU)."""
+    the same discretisation; assembly is not timed (as on the GPU).  Also times the oracle on the
+    small 2D workload c1 at full size: its apply and a direct sparse solve of the slab system."""
     from threadpoolctl import threadpool_limits
+    import scipy.sparse.linalg as spla
     import sg_inputs
     from oracle.slab import from_workload
     n_small = 12 if w.dim == 3 else 64
@@ -61,18 +112,39 @@ def cpu_baseline(w, seconds_target=15.0):
     with threadpool_limits(limits=1):
         P = from_workload(ws)
         x = sg_inputs.uniform_vector(P.n, sg_inputs.SEED_APPLY_INPUT)
-        P.apply_route2(x)
+        dt, reps = _time_oracle_apply(P, x, seconds_target)
+        c1 = sg_inputs.WORKLOADS["c1"]
+        P1 = from_workload(c1)
+        x1 = sg_inputs.uniform_vector(P1.n, sg_inputs.SEED_APPLY_INPUT)
+        dt1, _ = _time_oracle_apply(P1, x1, 1.0, 200)
+        A1 = P1.assemble_full().tocsc()
+        b1 = A1 @ sg_inputs.interior_target(c1)
         t0 = time.perf_counter()
-        reps = 0
-        while True:
-            P.apply_route2(x)
-            reps += 1
-            if time.perf_counter() - t0 > seconds_target or reps >= 50:
-                break
-        dt = (time.perf_counter() - t0) / reps
+        spla.spsolve(A1, b1)
+        t_sp = time.perf_counter() - t0
     return {"value": P.n / dt / 1e9, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
             "sample": f"route-2 Kronecker apply (scipy CSR x dense), same k/r/M/p_xi on {n_small}^{w.dim} cells "
-                      f"({P.n} DoFs), {reps} applies, assembly excluded, 1 thread"}
+                      f"({P.n} DoFs), {reps} applies, assembly excluded, 1 thread of {os.cpu_count()} "
+                      f"({_cpu_model()})",
+            "c1_apply_gdofs": round(P1.n / dt1 / 1e9, 5), "c1_spsolve_s": round(t_sp, 4)}
+
+
+def copy_bandwidth(torch, dev, reps=20):
+    """Achievable HBM bandwidth of a plain device copy over two disjoint 1 GiB buffer pairs."""
+    n = 1 << 27
+    src = [torch.ones(n, dtype=torch.float64, device=dev) for _ in range(2)]
+    dst = [torch.empty_like(s) for s in src]
+    for i in range(4):
+        dst[i % 2].copy_(src[i % 2])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(reps):
+        dst[i % 2].copy_(src[i % 2])
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    return 2 * 8 * n / t / 1e9
 
 
 def main():
@@ -124,19 +196,25 @@ def main():
     for i in range(5):
         G.apply(xs[i % pairs], ys[i % pairs])
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.apply_reps + 1)]
+    evs[0].record(stream)
     for i in range(args.apply_reps):
         G.apply(xs[i % pairs], ys[i % pairs])
-    ev1.record(stream)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
-    t_apply = ev0.elapsed_time(ev1) / 1e3 / args.apply_reps
+    per_apply = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.apply_reps)]) / 1e3
+    t_apply = float(np.median(per_apply))
     gdofs = n_dof / t_apply / 1e9
     achieved_gbs = abytes / t_apply / 1e9
     achieved_tf = aflops / t_apply / 1e12
     print(f"[bench] apply {t_apply * 1e6:.1f} us  {gdofs:.1f} GDoF/s  {achieved_gbs:.0f} GB/s  "
           f"{achieved_tf:.1f} TFLOP/s", file=sys.stderr, flush=True)
     del xs, ys
+    copy_gbs = copy_bandwidth(torch, dev)
+    src_hash = apply_source_hash()
+    meas = MEASURED_TRAFFIC.get((args.workload, src_hash))
+    traffic = meas["fetch_bytes"] + meas["write_bytes"] if meas else None
+    print(f"[bench] device copy {copy_gbs:.0f} GB/s; apply sources {src_hash}", file=sys.stderr, flush=True)
 
     out = {"metric": "SG operator apply GDoF/s + % HBM peak; FGMRES-GMG slab solve time, FP64 vs mixed",
            "value": round(gdofs, 3), "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -146,20 +224,22 @@ def main():
                                   f"dG({w.time_degree}), M={w.n_vars}, p_xi={w.chaos_degree} ({w.n_chaos} modes), "
                                   f"{n_dof} DoFs, {w.n_levels}-level GMG", "n_dofs": n_dof},
            "apply_us": round(t_apply * 1e6, 2),
-           "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                        "kernel": "sg_operator_apply (2^d colour launches of k_apply)",
-                        "algorithmic_bytes_per_apply": abytes},
-           "roofline_fp64": {"bound": "alu", "achieved": round(achieved_tf, 2), "peak": FP64_PEAK_TFLOPS,
-                             "unit": "TFLOP/s", "frac": round(achieved_tf / FP64_PEAK_TFLOPS, 4),
-                             "algorithmic_flops_per_apply": aflops},
+           "roofline": {"bound": "alu", "achieved": round(achieved_tf, 2), "peak": FP64_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(achieved_tf / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
+                        "kernel": "operator apply: k_apply then k_node_gather, one stream, median of "
+                                  f"{args.apply_reps} HIP-event-timed applies",
+                        "algorithmic_flops_per_apply": aflops, "source_hash": src_hash},
+           "roofline_hbm": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                            "algorithmic_bytes_per_apply": abytes,
+                            "measured_frac": (round(traffic / t_apply / 1e9 / HBM_PEAK_GBS, 4) if traffic else None)},
+           "copy_gbs": round(copy_gbs, 1),
            "setup_s": round(setup_s, 2)}
 
     # ---- slab solves -------------------------------------------------------------------------------
     if not args.only_apply:
-        xstar = sg_inputs.uniform_vector(n, sg_inputs.SEED_SOLVE_TARGET)
-        xg = torch.from_numpy(xstar).to(dev)
-        # right-hand side b = AA x* for a seeded x*; the identity rows carry x* on Dirichlet DoFs
+        # right-hand side b = AA x* for a seeded x* that vanishes on the Dirichlet boundary (so b does too)
+        xg = torch.from_numpy(sg_inputs.interior_target(w)).to(dev)
         b = G.apply(xg)
         torch.cuda.synchronize()
         x = torch.zeros_like(b)
@@ -184,7 +264,9 @@ def main():
         res = {"fp64_ms": round(float(np.mean(t64)), 2), "fp64_iterations": i64[-1]["iterations"],
                "fp64_rel_residual_true": i64[-1]["rel_residual_true"],
                "fp64_t_apply_ms": round(i64[-1]["t_apply_ms"], 2), "fp64_t_prec_ms": round(i64[-1]["t_prec_ms"], 2),
-               "fp64_applies": i64[-1]["applies"], "work_proxy": i64[-1]["work_proxy"]}
+               "fp64_applies": i64[-1]["applies"], "fp64_vcycles": i64[-1]["vcycles"],
+               "fp64_err_vs_xstar": float(torch.linalg.norm(x - xg) / torch.linalg.norm(xg)),
+               "work_proxy": i64[-1]["work_proxy"]}
         out["ms_per_step"] = res["fp64_ms"]
         print(f"[bench] fp64 solve {res['fp64_ms']} ms, {res['fp64_iterations']} it", file=sys.stderr, flush=True)
         if not args.no_mixed:
@@ -194,6 +276,7 @@ def main():
             err = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
             res.update({"mixed_ms": round(float(np.mean(t32)), 2), "mixed_iterations": i32[-1]["iterations"],
                         "mixed_rel_residual_true": i32[-1]["rel_residual_true"],
+                        "mixed_err_vs_xstar": float(torch.linalg.norm(x - xg) / torch.linalg.norm(xg)),
                         "mixed_vs_fp64_solution_rel_diff": err,
                         "mixed_speedup": round(float(np.mean(t64)) / float(np.mean(t32)), 3)})
             print(f"[bench] mixed solve {res['mixed_ms']} ms, {res['mixed_iterations']} it", file=sys.stderr,

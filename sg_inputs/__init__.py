@@ -142,3 +142,19 @@ def coef_qp_levels(w: Workload, points_fn):
         mus = m
         out.append(np.ascontiguousarray(vals, dtype=np.float64))
     return mus, out
+
+
+def interior_target(w: Workload, seed: int = SEED_SOLVE_TARGET) -> np.ndarray:
+    """Solve target x* for the benchmark: U[-1, 1] on interior nodes, 0 on the Dirichlet boundary.
+
+    Layout [N_xi][N_t][n_nodes] with nodes lexicographic, x fastest, on (n_cells_1d k + 1)^d nodes.
+    """
+    n1 = w.n_nodes_1d(0)
+    idx = np.arange(n1)
+    inner1 = (idx > 0) & (idx < n1 - 1)
+    inner = inner1
+    for _ in range(w.dim - 1):
+        inner = np.outer(inner1, inner).reshape(-1)
+    x = uniform_vector(w.n_dofs(0), seed).reshape(w.n_chaos * w.n_time, -1)
+    x[:, ~inner] = 0.0
+    return x.reshape(-1)
