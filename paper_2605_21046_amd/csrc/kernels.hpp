@@ -69,7 +69,9 @@ hipError_t launch_patch_invert(int dim, int k, int nt, Grid g, const double* E, 
 
 // Patch corrections c_K = A_{0,K}^{-1} R_K r of every cell (inverses stored transposed), written to
 // s_out in the broken layout; launch_node_gather(GATHER_VANKA) then forms
-// x <- x + omega sum_K R_K^T W_K c_K.
+// x <- x + omega sum_K R_K^T W_K c_K.  The residual patch of a cell (48 modes at a time) takes
+// ceil(n_p / 4) * 4 * 49 * sizeof(T) bytes of LDS.
+inline size_t vanka_lds_bytes(int npp, size_t elem) { return (size_t)((npp + 3) / 4 * 4) * 49 * elem; }
 template <typename T>
 hipError_t launch_vanka_cells(int dim, int k, int nt, Grid g, int n_xi, const T* invT, const T* r, T* s_out,
                               hipStream_t s);

@@ -11,6 +11,7 @@
 //                      node gather then forms x <- x + omega sum_K R_K^T W_K c_K
 #include "kernels.hpp"
 
+
 namespace sg {
 
 namespace {
@@ -266,95 +267,179 @@ __global__ void __launch_bounds__(TG * TG)
 }
 
 // ------------------------------------------------------------------------------------------------
-// One workgroup per cell, one wave per chunk of 64 patch rows.  Lane l owns row l of its chunk and
-// keeps SW chaos modes in registers (all of them when N_xi <= SW, else strips in turn); the patch
-// inverse is stored transposed so that, for a fixed column m, the 64 lanes read 64 consecutive
-// entries, and every entry is read once; the residual patch rk[m][mode] is an LDS broadcast.  The
-// correction of the cell goes to the broken node array (summed per node by k_node_gather).
-template <int DIM, int K, int NT, typename T, int SW>
-__global__ void __launch_bounds__(256)
-    k_vanka_cells(Grid g, int n_xi, int nblocks, const T* __restrict__ invT, const T* __restrict__ r,
+// Vanka patch products on the matrix cores.  For one cell, C = A_K^{-1} R with A_K^{-1} of size
+// n_p x n_p and R = [n_p][N_xi] (one column per chaos mode) is a small dense GEMM.  It runs
+// transposed, C^T = R^T A_K^{-T}, as 16x16x4 MFMA tiles (FP64 MFMA for FP64, FP32 MFMA for the mixed
+// V-cycle): one workgroup per cell, wave w owns the 16 patch rows 16w..16w+15 (the N dimension) and
+// the chaos modes are the M dimension, so every lane ends up holding results of one patch row and
+// stores them straight to the broken node array (summed per node by k_node_gather).
+// 16x16x4 lane layout: lane l supplies A[m l%16][k l/16] and B[k l/16][n l%16] and receives
+// D[out_row(l/16, v)][l%16], v = 0..3, with out_row = l/16 + 4v for the FP64 instruction and
+// 4(l/16) + v for the FP32 one (both checked on gfx950 with known operands).
+//  * B = A_K^{-T} streams from HBM: the inverse is stored transposed ([col][row]), so a fragment is
+//    four 128-byte runs and every entry is read once.  The first PF fragments (all of them for
+//    n_p <= 64) are requested at entry, together with the residual values, so one memory latency
+//    covers both; later fragments are refilled PF k-steps ahead.
+//  * A = R^T comes from LDS: the residual patch gathered from the node vector.
+template <typename T>
+struct Mfma16;
+template <>
+struct Mfma16<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 run(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int out_row(int kk, int v) { return kk + 4 * v; }
+};
+template <>
+struct Mfma16<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 run(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int out_row(int kk, int v) { return 4 * kk + v; }
+};
+
+constexpr int kVankaTiles = 3;                       // 16-mode tiles per pass (35 modes: one pass)
+constexpr int kVankaModesPerPass = kVankaTiles * 16;
+constexpr int kVankaLdr = kVankaModesPerPass + 1;    // LDS row stride, odd: rows in different banks
+static_assert(kVankaLdr == 49, "vanka_lds_bytes assumes 49");
+
+constexpr int vanka_threads(int dim, int k, int nt) { return 64 * ((nt * ipow(k + 1, dim) + 15) / 16); }
+
+// Offsets inside r, the broken array and one cell's inverse are 32-bit (the launcher checks the
+// sizes); only the per-cell base of the inverse is 64-bit.
+template <int DIM, int K, int NT, typename T>
+__global__ void __launch_bounds__(vanka_threads(DIM, K, NT))
+    k_vanka_cells(Grid g, int n_xi, int n_cells, const T* __restrict__ invT, const T* __restrict__ r,
                   T* __restrict__ s_out) {
     constexpr int N1 = K + 1;
     constexpr int NP = ipow(N1, DIM);
     constexpr int NPP = NT * NP;
+    constexpr int KS = (NPP + 3) / 4;     // k-steps
+    constexpr int KP = KS * 4;            // rows of the LDS tile (zero beyond n_p)
+    constexpr int LR = (KP + 63) / 64 * 64;
+    constexpr int PF = KS < 16 ? KS : 16; // B fragments in flight
+    constexpr int NG = vanka_threads(DIM, K, NT) / LR;   // gather groups
+    constexpr int LDR = kVankaLdr;
+    constexpr int GB = (LDR + NG - 1) / NG;               // gathered values per thread and pass
+    using M = Mfma16<T>;
+    using v4 = typename M::v4;
     extern __shared__ unsigned char smem_raw[];
-    const int nstrip = (n_xi + SW - 1) / SW;
-    const int ldr = nstrip * SW;
-    T* rk = reinterpret_cast<T*>(smem_raw);   // [NPP][ldr]
+    T* const rk = reinterpret_cast<T*>(smem_raw);   // [KP][LDR]
 
-    // contiguous cell ranges per XCD (blocks are dispatched round-robin over the 8 XCDs)
+    const int lane = threadIdx.x & 63;
+    const int kk = lane >> 4;
+    const int I = (threadIdx.x >> 6) * 16 + (lane & 15);  // patch row of this lane (B column, output)
+
+    // contiguous cell ranges per XCD (workgroups are dispatched round-robin over the 8 XCDs)
     const int b = blockIdx.x;
-    const long long cell = (long long)((b % 8) * (nblocks / 8) + min(b % 8, nblocks % 8) + b / 8);
+    const int cell = (b % 8) * (n_cells / 8) + min(b % 8, n_cells % 8) + b / 8;
     int cc[3] = {0, 0, 0};
     {
-        long long rr = cell;
-        for (int d = 0; d < DIM; ++d) { cc[d] = (int)(rr % g.n); rr /= g.n; }
+        int rr = cell;
+        for (int d = 0; d < DIM; ++d) { cc[d] = rr % g.n; rr /= g.n; }
     }
-    const long long nn = g.n_nodes;
 
-    // gather r_K: rk[l][alpha], l = i*NP + p; Dirichlet rows and padding modes are zero
-    for (int idx = threadIdx.x; idx < NPP * ldr; idx += blockDim.x) {
-        const int p = idx % NP;
-        const int i = (idx / NP) % NT;
-        const int al = idx / NPP;
-        T v = T(0);
-        if (al < n_xi) {
-            long long node = 0, m = 1;
-            bool bnd = false;
-            for (int d = 0; d < DIM; ++d) {
-                const int id = cc[d] * K + (p / ipow(N1, d)) % N1;
-                bnd |= (id == 0) | (id == g.n1 - 1);
-                node += id * m;
-                m *= g.n1;
-            }
-            if (!bnd) v = r[((long long)al * NT + i) * nn + node];
+    // B fragments: rows I, columns 4 step + kk of the inverse.  Every load is unconditional, from a
+    // clamped (valid) address: columns beyond n_p meet zero rows of A, and lanes with I >= n_p own
+    // output columns that are never stored, so the clamped values never reach a result.  (Loads
+    // under a branch would make the compiler wait for each refill at once.)
+    const T* const bc = invT + (long long)cell * (NPP * NPP) + min(I, NPP - 1);
+    const int last_col = min(4 * (KS - 1) + kk, NPP - 1);
+    auto load_b = [&](int step) -> T {   // step is a compile-time constant at every call
+        return step < KS - 1 ? bc[(4 * step + kk) * NPP] : bc[last_col * NPP];
+    };
+    T ring[PF];
+#pragma unroll
+    for (int u = 0; u < PF; ++u) ring[u] = load_b(u);
+
+    // gather role: patch row lrow (node fastest: neighbouring lanes read neighbouring nodes), modes
+    // agrp, agrp + NG, ... of the pass; Dirichlet rows, rows beyond n_p and modes beyond N_xi are 0.
+    // Loads are unconditional from clamped addresses; the mask is applied when writing LDS.
+    const int nn = (int)g.n_nodes;
+    const int rstride = NT * nn;                     // one chaos mode in r
+    const int lrow = threadIdx.x % LR;
+    const int agrp = threadIdx.x / LR;
+    const bool gthread = agrp < NG && lrow < KP;
+    int src = 0;
+    bool live = lrow < NPP;
+    {
+        const int l = min(lrow, NPP - 1);
+        const int p = l % NP;
+        int m = 1;
+        for (int d = 0; d < DIM; ++d) {
+            const int id = cc[d] * K + (p / ipow(N1, d)) % N1;
+            live &= (id != 0) & (id != g.n1 - 1);
+            src += id * m;
+            m *= g.n1;
         }
-        rk[(i * NP + p) * ldr + al] = v;
+        src += (l / NP) * nn;
     }
-    __syncthreads();
-
-    const int l = threadIdx.x;            // patch row of this lane
-    if (l >= NPP) return;
-    const T* A = invT + cell * NPP * NPP + l;
-    const long long nb1 = (long long)g.n * N1;
-    long long nbn = 1;
+    // store role: row I of the patch in the broken layout [comp][b_z][b_y][b_x]
+    const int nb1 = g.n * N1;
+    int nbn = 1;
     for (int d = 0; d < DIM; ++d) nbn *= nb1;
-    const int p = l % NP, i = l / NP;
-    long long off = 0, mul = 1;
-    for (int d = 0; d < DIM; ++d) {
-        off += ((long long)cc[d] * N1 + (p / ipow(N1, d)) % N1) * mul;
-        mul *= nb1;
+    const int sstride = NT * nbn;                    // one chaos mode in the broken array
+    int dst = 0;
+    {
+        const int p = min(I, NPP - 1) % NP;
+        int bm = 1;
+        for (int d = 0; d < DIM; ++d) {
+            dst += (cc[d] * N1 + (p / ipow(N1, d)) % N1) * bm;
+            bm *= nb1;
+        }
+        dst += (min(I, NPP - 1) / NP) * nbn;
     }
-    constexpr int U = 8;                  // columns of the inverse in flight per lane
-    for (int strip = 0; strip < nstrip; ++strip) {
-        T acc[SW];
+
+    const int n_pass = (n_xi + kVankaModesPerPass - 1) / kVankaModesPerPass;
+#pragma unroll 1
+    for (int pass = 0; pass < n_pass; ++pass) {
+        const int m0 = pass * kVankaModesPerPass;         // first mode of this pass
+        if (pass > 0) {
+            __syncthreads();                              // every wave is done with the previous pass
 #pragma unroll
-        for (int u = 0; u < SW; ++u) acc[u] = T(0);
-        const T* rs = rk + strip * SW;
-        T nxt[U];
+            for (int u = 0; u < PF; ++u) ring[u] = load_b(u);
+        }
+        if (gthread) {
+            T v[GB];
 #pragma unroll
-        for (int u = 0; u < U; ++u) nxt[u] = (u < NPP) ? A[(long long)u * NPP] : T(0);
-        for (int m0 = 0; m0 < NPP; m0 += U) {
-            T cur[U];
+            for (int u = 0; u < GB; ++u) {
+                const int al = min(m0 + agrp + u * NG, n_xi - 1);
+                v[u] = r[src + al * rstride];
+            }
 #pragma unroll
-            for (int u = 0; u < U; ++u) cur[u] = nxt[u];
-            // prefetch the next U columns while this chunk is multiplied
-#pragma unroll
-            for (int u = 0; u < U; ++u) nxt[u] = (m0 + U + u < NPP) ? A[(long long)(m0 + U + u) * NPP] : T(0);
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (m0 + u >= NPP) break;
-                const T* rr = rs + (m0 + u) * ldr;
-#pragma unroll
-                for (int k2 = 0; k2 < SW; ++k2) acc[k2] += cur[u] * rr[k2];
+            for (int u = 0; u < GB; ++u) {
+                const int a = agrp + u * NG;
+                if (a < LDR) rk[lrow * LDR + a] = (live && m0 + a < n_xi) ? v[u] : T(0);
             }
         }
-        // cell-local correction into the broken layout [comp][b_z][b_y][b_x]
+        __syncthreads();
+
+        // C^T tile: all three mode tiles every step (modes beyond N_xi have zero rows in A), so the
+        // accumulators stay in the matrix-core registers and the MFMAs of consecutive steps overlap
+        v4 acc[kVankaTiles];
 #pragma unroll
-        for (int u = 0; u < SW; ++u) {
-            const int al = strip * SW + u;
-            if (al < n_xi) s_out[((long long)al * NT + i) * nbn + off] = acc[u];
+        for (int q = 0; q < kVankaTiles; ++q) acc[q] = v4{T(0), T(0), T(0), T(0)};
+        const T* const abase = rk + kk * LDR + (lane & 15);
+#pragma unroll
+        for (int step = 0; step < KS; ++step) {
+            const T bv = ring[step % PF];
+            if (step + PF < KS) ring[step % PF] = load_b(step + PF);
+            const T* arow = abase + step * 4 * LDR;
+#pragma unroll
+            for (int q = 0; q < kVankaTiles; ++q) acc[q] = M::run(arow[q * 16], bv, acc[q]);
+        }
+        // results of patch row I, modes m0 + 16q + out_row: straight into the broken array
+        if (I < NPP) {
+#pragma unroll
+            for (int q = 0; q < kVankaTiles; ++q) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int al = m0 + q * 16 + M::out_row(kk, v);
+                    if (al < n_xi) s_out[dst + al * sstride] = acc[q][v];
+                }
+            }
         }
     }
 }
@@ -362,17 +447,24 @@ __global__ void __launch_bounds__(256)
 template <int DIM, int K, int NT, typename T>
 hipError_t run_vanka(Grid g, int n_xi, const T* invT, const T* r, T* s_out, hipStream_t s) {
     constexpr int NPP = NT * ipow(K + 1, DIM);
-    constexpr int SW = 36;
-    const int nstrip = (n_xi + SW - 1) / SW;
-    const size_t lds = (size_t)NPP * nstrip * SW * sizeof(T);
-    if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
-    auto kern = k_vanka_cells<DIM, K, NT, T, SW>;
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    const int blocks = (int)g.n_cells;
-    const int threads = ((NPP + 63) / 64) * 64;
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds, s, g, n_xi, blocks, invT, r, s_out);
-    return hipGetLastError();
+    constexpr int KP = (NPP + 3) / 4 * 4;
+    constexpr int waves = (NPP + 15) / 16;
+    if constexpr (waves > 16) {
+        return hipErrorInvalidValue;      // n_p > 256 is rejected when the handle is created
+    } else {
+        long long nbn = 1;
+        for (int d = 0; d < DIM; ++d) nbn *= (long long)g.n * (K + 1);
+        if ((long long)n_xi * NT * g.n_nodes >= (1LL << 31) || (long long)n_xi * NT * nbn >= (1LL << 31) ||
+            g.n_cells >= (1LL << 31))
+            return hipErrorInvalidValue;  // 32-bit offsets
+        const size_t lds = (size_t)KP * kVankaLdr * sizeof(T);
+        auto kern = k_vanka_cells<DIM, K, NT, T>;
+        if (lds > 64 * 1024)
+            (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        const int n_cells = (int)g.n_cells;
+        hipLaunchKernelGGL(kern, dim3(n_cells), dim3(waves * 64), lds, s, g, n_xi, n_cells, invT, r, s_out);
+        return hipGetLastError();
+    }
 }
 
 template <int DIM, int K, typename T>

@@ -250,7 +250,7 @@ sg_status build(sg_handle h) {
     {
         const size_t n_ent_max = (size_t)h->n_xi * (2 * d.n_vars + 1) * 4;
         const size_t lds_apply = (size_t)(h->n_xi * h->NT + h->n_mu) * h->NP * sizeof(double) + n_ent_max * 16;
-        const size_t lds_vanka = (size_t)h->npp * ((h->n_xi + 35) / 36) * 36 * sizeof(double);
+        const size_t lds_vanka = vanka_lds_bytes(h->npp, sizeof(double));
         if (lds_apply > 160 * 1024 || lds_vanka > 160 * 1024)
             return fail(SG_EUNSUPPORTED, "problem too large for one workgroup's LDS (N_xi * N_t * (k+1)^d)");
     }
