@@ -4,10 +4,11 @@
 // action of AA is formed).
 //
 // Work decomposition (gfx950, wave64):
-//   * one launch over every cell; one workgroup = `cpb` consecutive cells x all N_xi * N_t
-//     components; one thread owns one (cell, component) pair and keeps its (k+1)^d point values
-//     in registers; workgroups are remapped so that each XCD (and its L2) works on one contiguous
-//     range of cells;
+//   * one launch over every cell; one workgroup = a segment of `cpb` consecutive cells of one cell
+//     row (along x) x all N_xi * N_t components; one thread owns one (cell, component) pair and
+//     keeps its (k+1)^d point values in registers; each XCD walks its own contiguous range of rows,
+//     in chunks of a few y-rows with z running (tiled_row), so rows in flight share node planes in
+//     its L2;
 //   * per thread: gather the cell's nodal values (Dirichlet columns dropped), interpolate to the
 //     Gauss points (d 1D sweeps with the GLL-basis table), take reference derivatives by Gauss
 //     collocation (d sweeps), and integrate back with the transposed sweeps;
@@ -22,6 +23,8 @@
 #pragma once
 
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
 #include "kernels.hpp"
 
@@ -99,14 +102,6 @@ __device__ __forceinline__ void sweeps_ip(T (&v)[ipow(N1, DIM)], const T* __rest
 // Keeps the scheduler from hoisting every unrolled load of a long loop ahead of its uses, which
 // would otherwise blow the register budget and spill.
 #define SG_FENCE() __builtin_amdgcn_sched_barrier(0)
-
-// Workgroups are dispatched round-robin over the 8 XCDs; give XCD x the contiguous block range
-// [start_x, start_x + count_x) so neighbouring cells share one L2.
-__device__ __forceinline__ int xcd_block(int b, int nb) {
-    const int q = nb / 8, r = nb % 8;
-    const int x = b % 8;
-    return x * q + min(x, r) + b / 8;
-}
 
 template <int NT, typename T>
 __device__ __forceinline__ T bt_of(const Tables<T>& tb, int ti) {
@@ -214,9 +209,13 @@ __device__ __forceinline__ void couple_point(T* rows, const T* crow, int q, int 
         for (int m = 0; m < M; ++m) {
             const int bm = tab.nbm[al][m], bp = tab.nbp[al][m];
             if (bm < 0 && bp < 0) continue;
-            T t = T(0);
-            if (bm >= 0) t += T(kSqrtTab[tab.idx[al][m]]) * g[bm];
-            if (bp >= 0) t += T(kSqrtTab[tab.idx[al][m] + 1]) * g[bp];
+            T t;
+            if (bm >= 0 && bp >= 0)
+                t = T(kSqrtTab[tab.idx[al][m]]) * g[bm] + T(kSqrtTab[tab.idx[al][m] + 1]) * g[bp];
+            else if (bm >= 0)
+                t = T(kSqrtTab[tab.idx[al][m]]) * g[bm];
+            else
+                t = T(kSqrtTab[tab.idx[al][m] + 1]) * g[bp];
             f += cm[m] * t;
         }
         rows[(al * NT + ti) * NP + q] = f;
@@ -292,6 +291,8 @@ __device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const Tables<T
         __syncthreads();
         const int cpb = a.cpb;
         const int ntask = cpb * NP * NT;
+        // workgroup size from the arguments (blockDim would be read from the dispatch packet in memory)
+        const int nthreads = cpb * a.n_xi * NT;
 #pragma unroll
         for (int dir = 0; dir < DIM; ++dir) {
             const int st = ipow(N1, dir);
@@ -305,7 +306,7 @@ __device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const Tables<T
                 my_row[q] = g;
             }
             __syncthreads();
-            for (int task = threadIdx.x; task < ntask; task += blockDim.x) {
+            for (int task = threadIdx.x; task < ntask; task += nthreads) {
                 const int q = task % NP;
                 const int tb_i = (task / NP) % NT;
                 const int sl = task / (NP * NT);
@@ -408,15 +409,19 @@ __global__ void __launch_bounds__(ipow(K + 1, DIM) > 27 ? 256 : 512)
     int* ent_c = ent_g + a.n_ent;                            // [n_ent] LDS row offset of mu
 
     const int t = threadIdx.x;
+    const int nthreads = NC * cpb;                           // the workgroup size
     const int slot = t % cpb;
     const int comp = t / cpb;
     const int alpha = comp / NT;
     const int ti = comp % NT;
-    const int lb = xcd_block(blockIdx.x, a.nblocks);
-    const long long cell0 = (long long)lb * cpb;
-    const long long ci = cell0 + slot;
-    const bool active = ci < a.g.n_cells;
+    // workgroup -> (cell row, segment of cpb cells along x); rows in the XCD-local tiled order
     const int n = a.g.n, n1 = a.g.n1;
+    const int segs = (n + cpb - 1) / cpb;
+    const int lb = xcd_position(blockIdx.x, a.nblocks);
+    const int x0 = (lb % segs) * cpb;
+    const long long cell0 = (long long)tiled_row<DIM>(lb / segs, n) * n + x0;
+    const long long ci = cell0 + slot;
+    const bool active = x0 + slot < n;
     const long long nn = a.g.n_nodes;
 
     int cc[3] = {0, 0, 0};
@@ -429,16 +434,16 @@ __global__ void __launch_bounds__(ipow(K + 1, DIM) > 27 ? 256 : 512)
     }
 
     // stage the coefficient values of this block's cells (contiguous in memory)
-    for (int idx = t; idx < a.n_mu * NP * cpb; idx += blockDim.x) {
+    for (int idx = t; idx < a.n_mu * NP * cpb; idx += nthreads) {
         const int q = idx % NP;
         const int mu = (idx / NP) % a.n_mu;
         const int s = idx / (NP * a.n_mu);
         const long long c2 = cell0 + s;
-        cl[s * CS + mu * NP + q] = (c2 < a.g.n_cells) ? a.coef[mu * a.coef_mode_stride + c2 * NP + q] : T(0);
+        cl[s * CS + mu * NP + q] = (x0 + s < n) ? a.coef[mu * a.coef_mode_stride + c2 * NP + q] : T(0);
     }
     // stage the coupling entries (beta, mu, w) as LDS offsets
     if constexpr (!MEAN && CM == 0) {
-        for (int e = t; e < a.n_ent; e += blockDim.x) {
+        for (int e = t; e < a.n_ent; e += nthreads) {
             ent_w[e] = a.cw[e];
             ent_g[e] = a.cbeta[e] * NT * NP;
             ent_c[e] = a.cmu[e] * NP;
@@ -477,33 +482,52 @@ __global__ void __launch_bounds__(ipow(K + 1, DIM) > 27 ? 256 : 512)
                                             ti, active, cc, exch, cl, SS, CS, active ? ci : 0);
 }
 
-// Cells per workgroup: the largest number of busy lanes per CU allowed by the kernel's register use
-// (queried from the code object), the launch bound and 160 KiB of LDS.
-inline int choose_cpb(const void* kern, int nc, size_t lds_fixed, size_t lds_per_cell, int max_threads) {
-    hipFuncAttributes attr{};
-    int vgpr = 256;
-    if (hipFuncGetAttributes(&attr, kern) == hipSuccess && attr.numRegs > 0) vgpr = attr.numRegs;
-    else (void)hipGetLastError();
-    const int alloc = ((vgpr + 7) / 8) * 8;
-    const int waves_simd = std::max(1, std::min(8, 512 / alloc));
-    const int waves_cu = 4 * waves_simd;
+// Cells per workgroup: the largest number of busy lanes per CU, with the number of resident
+// workgroups per CU from the runtime's occupancy calculator (registers, LDS, wave slots), among the
+// sizes that keep at least two workgroups per CU when there are any (a second workgroup runs while
+// the first waits at one of its barriers).
+inline int choose_cpb_uncached(const void* kern, int nc, size_t lds_fixed, size_t lds_per_cell, int max_threads) {
     int best = 1;
     long best_score = -1;
     for (int cpb = 1; nc * cpb <= max_threads; ++cpb) {
         const int threads = nc * cpb;
-        const int waves = (threads + 63) / 64;
-        const int by_w = waves_cu / waves;
         const size_t lds = lds_fixed + lds_per_cell * cpb;
-        const int by_l = lds > 160 * 1024 ? 0 : (lds == 0 ? 64 : (int)((160 * 1024) / lds));
-        const int blocks = std::min(by_w, by_l);
-        if (blocks == 0) continue;
-        const long score = (long)blocks * threads;
-        if (score > best_score) {
+        if (lds > 160 * 1024) break;
+        if (lds > 64 * 1024)
+            (void)hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        int blocks = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kern, threads, lds) != hipSuccess) {
+            (void)hipGetLastError();
+            continue;
+        }
+        const long score = (long)blocks * threads + (blocks >= 2 ? (1L << 30) : 0);
+        if (blocks > 0 && score > best_score) {
             best_score = score;
             best = cpb;
         }
     }
     return best;
+}
+
+// The choice depends only on the kernel and the sizes; remember it (the apply launch path is hot).
+inline int choose_cpb(const void* kern, int nc, size_t lds_fixed, size_t lds_per_cell, int max_threads) {
+    struct Entry {
+        const void* kern;
+        int nc;
+        size_t fixed, per_cell;
+        int cpb;
+    };
+    static std::mutex mu;
+    static std::vector<Entry> cache;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (const Entry& e : cache)
+            if (e.kern == kern && e.nc == nc && e.fixed == lds_fixed && e.per_cell == lds_per_cell) return e.cpb;
+    }
+    const int cpb = choose_cpb_uncached(kern, nc, lds_fixed, lds_per_cell, max_threads);
+    std::lock_guard<std::mutex> lk(mu);
+    cache.push_back({kern, nc, lds_fixed, lds_per_cell, cpb});
+    return cpb;
 }
 
 template <int DIM, int K, int NT, typename T>
@@ -552,7 +576,8 @@ hipError_t run_apply(const ApplyOp<T>& op, const T* x, T* s_out, hipStream_t s) 
     if (threads > MAXT || lds > 160 * 1024) return hipErrorInvalidConfiguration;
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    const long long blocks = (op.g.n_cells + cpb - 1) / cpb;
+    const long long rows = op.g.n_cells / op.g.n;
+    const long long blocks = rows * ((op.g.n + cpb - 1) / cpb);
     a.nblocks = (int)blocks;
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(threads), lds, s, a, *op.tables);
     return hipGetLastError();

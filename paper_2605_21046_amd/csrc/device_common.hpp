@@ -27,12 +27,35 @@ struct Tables {
     T vol;
 };
 
-// Index of the multigrid node line / cell colouring helpers.
+// Uniform Cartesian mesh of one level.
 struct Grid {
     int n;              // cells per direction
     int n1;             // nodes per direction = n k + 1
     long long n_nodes;  // n1^d
     long long n_cells;  // n^d
 };
+
+// Traversal order of cell rows (a row = the n cells along x at fixed y, z).  Workgroups are
+// dispatched round-robin over the 8 XCDs; XCD x gets the contiguous position range
+// [x q + min(x, r), ...) of the nb positions, so the rows it walks in turn stay in its L2.  In 3D the
+// rows are visited in chunks of `ty` consecutive y (ty | n), z running over the chunk, y fastest:
+// rows in flight together then share node planes in both y and z.
+__device__ __forceinline__ int xcd_position(int b, int nb) {
+    const int q = nb / 8, r = nb % 8;
+    const int x = b % 8;
+    return x * q + min(x, r) + b / 8;
+}
+__host__ __device__ constexpr int row_tile(int n) { return n % 4 == 0 ? 4 : (n % 2 == 0 ? 2 : 1); }
+// row (y + n z, or y in 2D) of the o-th row in traversal order
+template <int DIM>
+__device__ __forceinline__ int tiled_row(int o, int n) {
+    if constexpr (DIM == 2) {
+        return o;
+    } else {
+        const int ty = row_tile(n);
+        const int chunk = o / (ty * n), rem = o % (ty * n);
+        return chunk * ty + rem % ty + n * (rem / ty);
+    }
+}
 
 }  // namespace sg

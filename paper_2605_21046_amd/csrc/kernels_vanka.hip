@@ -332,9 +332,9 @@ __global__ void __launch_bounds__(vanka_threads(DIM, K, NT))
     const int kk = lane >> 4;
     const int I = (threadIdx.x >> 6) * 16 + (lane & 15);  // patch row of this lane (B column, output)
 
-    // contiguous cell ranges per XCD (workgroups are dispatched round-robin over the 8 XCDs)
-    const int b = blockIdx.x;
-    const int cell = (b % 8) * (n_cells / 8) + min(b % 8, n_cells % 8) + b / 8;
+    // cells in the XCD-local tiled row order
+    const int pos = xcd_position(blockIdx.x, n_cells);
+    const int cell = tiled_row<DIM>(pos / g.n, g.n) * g.n + pos % g.n;
     int cc[3] = {0, 0, 0};
     {
         int rr = cell;
