@@ -71,6 +71,10 @@ typedef struct {
     double vanka_omega;     /* damping of the additive Vanka correction                              */
     int fgmres_restart;     /* Krylov basis length before restart (<= 64)                            */
     sg_precision precision;
+    int transpose;          /* 0: the slab operator AA; 1: its transpose AA^T (the adjoint slab
+                             * problem).  For an affine coefficient G_mu, M_x, K_mu are symmetric and
+                             * B_t is diagonal, so AA^T is AA with A_t replaced by A_t^T; every entry
+                             * point of the handle (apply, Vanka, V-cycle, FGMRES) then acts on AA^T. */
 } sg_problem_desc;
 
 /* Counters of one slab solve (mirrors the paper's Table tab:finite-size-work-solver-performance). */
@@ -124,6 +128,47 @@ sg_status fgmres_solve_slab(sg_handle h, const double* b, double* x, double rtol
 /* Physical coordinates of the Gauss points of level `level`, written to the HOST array
  * xyz[n_cells(l)][(k+1)^d][d] (the points at which coef_qp is sampled).  Needs no handle. */
 sg_status sg_quadrature_points(const sg_problem_desc* desc, int level, double* xyz);
+
+/* Physical coordinates of the nodes of level `level` in global lexicographic order (x fastest),
+ * written to the HOST array xyz[n_nodes(l)][d] (Section 2.4: nodal Q_k basis; the support points are
+ * taken as the Gauss-Lobatto points, the paper naming none).  Needs no handle. */
+sg_status sg_node_coordinates(const sg_problem_desc* desc, int level, double* xyz);
+
+/* y = AA^T x for a handle made with transpose = 0 (y = AA x for transpose = 1): the operator of the
+ * adjoint slab problem (Problem tensor-product-slab-system with A_t transposed; the other factors of
+ * eq. local_rhs_tensor are symmetric).  FP64, finest level, identity rows on Dirichlet DoFs.  x and
+ * y are device vectors of sg_vector_length(h, 0) doubles and must not overlap.  Asynchronous. */
+sg_status sg_operator_apply_T(sg_handle h, const double* x, double* y, void* hip_stream);
+
+/* Slab transfer (eq. local_rhs_tensor, J = M_xi (x) C_t (x) M_x with [C_t]_ij = v_j(t_{n-1}^-)
+ * v_i(t_{n-1}^+), eq. Ct):  y = (I (x) C_t (x) M_x) x  (transpose = 0), the right-hand side that the
+ * previous slab's solution x induces on the next slab, or y = (I (x) C_t^T (x) M_x) x (transpose = 1),
+ * the same for the backward adjoint sweep.  For the right-Radau basis C_t = v(0) e_r^T: only the
+ * last time component of x (the end-of-slab trace) enters.  Rows of Dirichlet DoFs of y are 0 and
+ * columns of Dirichlet DoFs are dropped.  With x = the end-of-slab trace of an initial value u_0 in
+ * time component r (others 0), y is the initial trace vector B_0 (eq. initial_vector).  Asynchronous. */
+sg_status sg_slab_transfer(sg_handle h, int transpose, const double* x, double* y, void* hip_stream);
+
+/* Cell-wise stiffness bilinear form, the building block of the parameter gradient of an adjoint:
+ *     out[K] = lam^T (G_mu (x) B_t (x) K_{c|K}) u,   K = 0 .. n_cells(0) - 1 (x fastest),
+ * where mu = coef_mu[mu_index] selects the Galerkin tensor, c is the field given by its values at
+ * the Gauss points coef_qp[n_cells(0)][(k+1)^d] (HOST array, same layout and points as one mode of
+ * the create-time coef_qp on level 0) and K_{c|K} is the stiffness matrix of c restricted to cell K.
+ * lam and u are device slab vectors that vanish on Dirichlet DoFs; out is a device array of
+ * n_cells(0) doubles.  d/d theta of lam^T AA u for a_mu = theta c is sum_K out[K].  Asynchronous. */
+sg_status sg_stiffness_form_cells(sg_handle h, int mu_index, const double* coef_qp, const double* lam,
+                                  const double* u, double* out, void* hip_stream);
+
+/* Mean/variance quantity of interest at the end of a slab.  With u(T) the end-of-slab trace of the
+ * slab vector u (time component r) and Q(xi) = int_D u(x, T, xi)^2 dx = sum_{alpha,beta} m_{alpha beta}
+ * Psi_alpha Psi_beta, m_{alpha beta} = u_alpha(T)^T M_x u_beta(T), the chaos expansion of Q is
+ * q_eps = sum_{alpha,beta} m_{alpha beta} E[Psi_alpha Psi_beta Psi_eps] (|eps| <= 2 p_xi), so
+ * E[Q] = q_0 and Var[Q] = sum_{eps != 0} q_eps^2 (Section 3.1, eqs. qoi-mean-chaos and
+ * qoi-variance-chaos applied to Q).  Writes qoi[0] = E[Q], qoi[1] = Var[Q] (HOST array of 2) and, if
+ * grad != NULL, grad = dJ/du for J = w_mean E[Q] + w_var Var[Q] (a device slab vector, nonzero only in
+ * time component r on interior DoFs).  Synchronises the stream. */
+sg_status sg_qoi_mean_var(sg_handle h, const double* u, double w_mean, double w_var, double* qoi, double* grad,
+                          void* hip_stream);
 
 /* Message for the last non-OK status returned on the calling thread ("" if none). */
 const char* sg_last_error(void);

@@ -42,7 +42,14 @@ hipError_t launch_apply(const ApplyOp<T>& op, const T* x, T* s_out, hipStream_t 
 //   GATHER_SET:      out = sum                 (Dirichlet rows: out = x)
 //   GATHER_RESIDUAL: out = b - sum             (Dirichlet rows: out = b - x)
 //   GATHER_VANKA:    out += omega sum / mult   (Dirichlet rows: out = b); mult = cells sharing the node
-enum GatherOp { GATHER_SET = 0, GATHER_RESIDUAL = 1, GATHER_VANKA = 2 };
+//   GATHER_INTERIOR: out = sum                 (Dirichlet rows: out = 0)
+enum GatherOp { GATHER_SET = 0, GATHER_RESIDUAL = 1, GATHER_VANKA = 2, GATHER_INTERIOR = 3 };
+
+// out[K] = sum over the ncomp components and the (k+1)^d local nodes a of cell K of
+// lam[comp][node(K, a)] * s_in[comp][broken(K, a)]: the cell-wise bilinear form lam^T A_K u of a
+// cell-local operator whose per-cell results s_in = A_K u are in the broken layout.
+hipError_t launch_cell_dot(int dim, int k, Grid g, int ncomp, const double* lam, const double* s_in, double* out,
+                           hipStream_t s);
 template <typename T>
 hipError_t launch_node_gather(GatherOp op, int dim, int k, Grid g, int ncomp, const T* s_in, const T* x, const T* b,
                               T* out, T omega, hipStream_t s);

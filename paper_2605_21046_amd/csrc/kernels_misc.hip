@@ -89,6 +89,7 @@ __global__ void __launch_bounds__(256)
         if (bnd) {
             if (OP == GATHER_SET) out[gi] = x[gi];
             else if (OP == GATHER_RESIDUAL) out[gi] = b[gi] - x[gi];
+            else if (OP == GATHER_INTERIOR) out[gi] = T(0);
             else out[gi] = b[gi];
             continue;
         }
@@ -109,10 +110,48 @@ __global__ void __launch_bounds__(256)
             sum = (s00 + whi[1] * s01) + whi[2] * (s10 + whi[1] * s11);
             cnt = (T(1) + whi[0]) * (T(1) + whi[1]) * (T(1) + whi[2]);
         }
-        if (OP == GATHER_SET) out[gi] = sum;
+        if (OP == GATHER_SET || OP == GATHER_INTERIOR) out[gi] = sum;
         else if (OP == GATHER_RESIDUAL) out[gi] = b[gi] - sum;
         else out[gi] = out[gi] + omega * sum / cnt;
     }
+}
+
+// One workgroup per cell: sum of lam * s over the cell's (component, local node) pairs.
+__global__ void __launch_bounds__(256)
+    k_cell_dot(int dim, int k, Grid g, int ncomp, const double* __restrict__ lam, const double* __restrict__ s_in,
+               double* __restrict__ out) {
+    __shared__ double sh[256];
+    const int n1l = k + 1;
+    const int np = dim == 2 ? n1l * n1l : n1l * n1l * n1l;
+    const long long cell = blockIdx.x;
+    int cc[3] = {0, 0, 0};
+    {
+        long long r = cell;
+        for (int d = 0; d < dim; ++d) { cc[d] = (int)(r % g.n); r /= g.n; }
+    }
+    const long long nb1 = (long long)g.n * n1l;
+    long long nbn = 1;
+    for (int d = 0; d < dim; ++d) nbn *= nb1;
+    double acc = 0.0;
+    for (int idx = threadIdx.x; idx < ncomp * np; idx += 256) {
+        const int comp = idx / np, a = idx % np;
+        long long node = 0, brk = 0, m = 1, bm = 1;
+        for (int d = 0, aa = a; d < dim; ++d, aa /= n1l) {
+            const int ad = aa % n1l;
+            node += (long long)(cc[d] * k + ad) * m;
+            brk += ((long long)cc[d] * n1l + ad) * bm;
+            m *= g.n1;
+            bm *= nb1;
+        }
+        acc += lam[comp * g.n_nodes + node] * s_in[comp * nbn + brk];
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[cell] = sh[0];
 }
 
 template <typename T>
@@ -313,14 +352,23 @@ hipError_t launch_node_gather(GatherOp op, int dim, int k, Grid g, int ncomp, co
     if (dim == 2) {
         if (op == GATHER_SET) { SG_NG_K(GATHER_SET, 2) }
         else if (op == GATHER_RESIDUAL) { SG_NG_K(GATHER_RESIDUAL, 2) }
+        else if (op == GATHER_INTERIOR) { SG_NG_K(GATHER_INTERIOR, 2) }
         else { SG_NG_K(GATHER_VANKA, 2) }
     } else {
         if (op == GATHER_SET) { SG_NG_K(GATHER_SET, 3) }
         else if (op == GATHER_RESIDUAL) { SG_NG_K(GATHER_RESIDUAL, 3) }
+        else if (op == GATHER_INTERIOR) { SG_NG_K(GATHER_INTERIOR, 3) }
         else { SG_NG_K(GATHER_VANKA, 3) }
     }
 #undef SG_NG_K
 #undef SG_NG
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_dot(int dim, int k, Grid g, int ncomp, const double* lam, const double* s_in, double* out,
+                           hipStream_t s) {
+    if (g.n_cells > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_cell_dot, dim3((unsigned)g.n_cells), dim3(256), 0, s, dim, k, g, ncomp, lam, s_in, out);
     return hipGetLastError();
 }
 

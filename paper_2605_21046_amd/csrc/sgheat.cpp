@@ -116,6 +116,14 @@ struct sg_handle_s {
     DevBuf<double> sbuf;
     std::vector<double> hbuf;
     long long N = 0;
+    // operator variants on level 0: 1D tables, the other orientation of A_t, the end-of-slab
+    // transfer, scratch for the bilinear forms and the quantity of interest
+    std::vector<double> tS, tD, tgw, radau0;   // radau0[i] = v_i(0+)
+    Tables<double> tabT64{};
+    DevBuf<double> zcoef, fcoef, qpart, qout, qC;
+    std::vector<double> hstage;
+    std::vector<double> trip;                 // E[Psi_a Psi_b Psi_eps], [n_xi][n_xi][n_eps]
+    int n_eps = 0;
 };
 
 namespace {
@@ -159,6 +167,7 @@ sg_status validate(const sg_problem_desc* d) {
     if (d->pre_smooth < 0 || d->post_smooth < 0) return fail(SG_EINVAL, "smoothing counts must be >= 0");
     if (d->fgmres_restart < 1 || d->fgmres_restart > 64) return fail(SG_EINVAL, "fgmres_restart must be in 1..64");
     if (d->precision != SG_FP64 && d->precision != SG_MIXED) return fail(SG_EINVAL, "unknown precision");
+    if (d->transpose != 0 && d->transpose != 1) return fail(SG_EINVAL, "transpose must be 0 or 1");
     return SG_OK;
 }
 
@@ -256,6 +265,16 @@ sg_status build(sg_handle h) {
     }
     if (!time_matrices(d.time_degree, d.tau, &h->At, &h->Bt))
         return fail(SG_EINVAL, "time matrices: B_t is not diagonal");
+    if (d.transpose) {   // adjoint slab operator: A_t^T (every other factor is symmetric)
+        const std::vector<double> a = h->At;
+        for (int i = 0; i < h->NT; ++i)
+            for (int j = 0; j < h->NT; ++j) h->At[i * h->NT + j] = a[j * h->NT + i];
+    }
+    {
+        const std::vector<double> tn = right_radau_points(d.time_degree);
+        h->radau0.resize(h->NT);
+        for (int i = 0; i < h->NT; ++i) h->radau0[i] = lagrange_value(tn, i, 0.0);
+    }
 
     // coupling lists (full operator and mean block)
     {
@@ -292,6 +311,10 @@ sg_status build(sg_handle h) {
             Dn[q * N1 + a] = lagrange_deriv(gll, a, gq[q]);
         }
 
+    h->tS = S;
+    h->tD = D;
+    h->tgw = gw;
+
     // levels
     const int L = d.n_levels;
     h->lv.resize(L);
@@ -311,6 +334,12 @@ sg_status build(sg_handle h) {
         lv.len = (long long)h->n_xi * h->NT * lv.g.n_nodes;
         fill_tables(&lv.tab64, S, D, gw, h->At, h->Bt, N1, h->NT, std::pow(lv.h, dim));
         fill_tables(&lv.tab32, S, D, gw, h->At, h->Bt, N1, h->NT, std::pow(lv.h, dim));
+        if (l == 0) {
+            std::vector<double> at(h->NT * h->NT);
+            for (int i = 0; i < h->NT; ++i)
+                for (int j = 0; j < h->NT; ++j) at[i * h->NT + j] = h->At[j * h->NT + i];
+            fill_tables(&h->tabT64, S, D, gw, at, h->Bt, N1, h->NT, std::pow(lv.h, dim));
+        }
         // coefficients, pre-scaled by the Gauss weight and h^(d-2)
         const size_t per_mode = (size_t)lv.g.n_cells * h->NP;
         const int nm = (l == 0) ? h->n_mu : 1;
@@ -738,6 +767,56 @@ bool overlap(const void* a, const void* b, size_t bytes) {
     return pa < pb + bytes && pb < pa + bytes;
 }
 
+// ---- operator variants on level 0: adjoint orientation, slab transfer, bilinear forms, QoI --------
+
+// Level-0 tables with the time matrix `at` in place of A_t (row i is divided by B_t[i] as for A_t).
+Tables<double> tables_with(const sg_handle h, const std::vector<double>& at) {
+    Tables<double> tb{};
+    fill_tables(&tb, h->tS, h->tD, h->tgw, at, h->Bt, h->d.fe_degree + 1, h->NT, std::pow(h->lv[0].h, h->d.dim));
+    return tb;
+}
+
+// A zero mean-coefficient array of level 0 (mass-only variants).
+sg_status zero_coef(sg_handle h, hipStream_t s) {
+    const size_t n = (size_t)h->lv[0].g.n_cells * h->NP;
+    if (!h->zcoef.p) {
+        SG_TRY(h->zcoef.alloc(n, "zero coefficient"));
+        SG_HIP(launch_fill<double>(h->zcoef.p, 0.0, (long long)n, s));
+    }
+    return SG_OK;
+}
+
+// Level-0 operator variant: time tables `tb`, coefficient modes `coef` (the mean mode alone when
+// !full); cell-local results go to sbuf and, with y, are gathered into y.
+sg_status variant_apply(sg_handle h, const Tables<double>* tb, const double* coef, bool full, const double* x,
+                        double* y, GatherOp gop, hipStream_t s) {
+    ApplyOp<double> op = make_op<double>(h, 0, full);
+    op.tables = tb;
+    op.coef = coef;
+    SG_HIP(launch_apply<double>(op, x, h->sbuf.p, s));
+    if (y)
+        SG_HIP(launch_node_gather<double>(gop, h->d.dim, h->d.fe_degree, h->lv[0].g, h->n_xi * h->NT, h->sbuf.p, x,
+                                          nullptr, y, 0.0, s));
+    return SG_OK;
+}
+
+// E[Psi_a Psi_b Psi_eps] for a, b in the handle's index set and eps of total degree <= 2 p_xi.
+void build_triple_table(sg_handle h) {
+    if (!h->trip.empty()) return;
+    const int M = h->d.n_vars, p = h->d.chaos_degree, nx = h->n_xi;
+    const std::vector<std::vector<int>> A = total_degree_set(M, p);
+    const std::vector<std::vector<int>> E = total_degree_set(M, 2 * p);
+    h->n_eps = (int)E.size();
+    h->trip.assign((size_t)nx * nx * h->n_eps, 0.0);
+    for (int a = 0; a < nx; ++a)
+        for (int b = 0; b < nx; ++b)
+            for (int e = 0; e < h->n_eps; ++e) {
+                double v = 1.0;
+                for (int m = 0; m < M && v != 0.0; ++m) v *= hermite_triple_1d(A[a][m], A[b][m], E[e][m]);
+                h->trip[((size_t)a * nx + b) * h->n_eps + e] = v;
+            }
+}
+
 double dev_dot_sync(sg_handle h, const double* a, const double* b, long long n, hipStream_t s, sg_status* st) {
     double out = 0.0;
     *st = SG_OK;
@@ -945,6 +1024,123 @@ sg_status fgmres_solve_slab(sg_handle h, const double* b, double* x, double rtol
     return result;
 }
 
+sg_status sg_operator_apply_T(sg_handle h, const double* x, double* y, void* hip_stream) {
+    if (!h || !x || !y) return fail(SG_EINVAL, "null argument");
+    if (overlap(x, y, h->N * sizeof(double))) return fail(SG_EINVAL, "x and y overlap");
+    ApplyOp<double> op = make_op<double>(h, 0, true);
+    op.tables = &h->tabT64;
+    SG_TRY(op_apply<double>(h, op, x, y, nullptr, (hipStream_t)hip_stream));
+    return SG_OK;
+}
+
+sg_status sg_slab_transfer(sg_handle h, int transpose, const double* x, double* y, void* hip_stream) {
+    if (!h || !x || !y) return fail(SG_EINVAL, "null argument");
+    if (transpose != 0 && transpose != 1) return fail(SG_EINVAL, "transpose must be 0 or 1");
+    if (overlap(x, y, h->N * sizeof(double))) return fail(SG_EINVAL, "x and y overlap");
+    hipStream_t s = (hipStream_t)hip_stream;
+    SG_TRY(zero_coef(h, s));
+    const int NT = h->NT, r = NT - 1;
+    std::vector<double> ct((size_t)NT * NT, 0.0);   // C_t[i][j] = v_i(0+) [j == r]
+    for (int i = 0; i < NT; ++i) {
+        if (transpose) ct[(size_t)r * NT + i] = h->radau0[i];
+        else ct[(size_t)i * NT + r] = h->radau0[i];
+    }
+    const Tables<double> tb = tables_with(h, ct);
+    return variant_apply(h, &tb, h->zcoef.p, false, x, y, GATHER_INTERIOR, s);
+}
+
+sg_status sg_stiffness_form_cells(sg_handle h, int mu_index, const double* coef_qp, const double* lam,
+                                  const double* u, double* out, void* hip_stream) {
+    if (!h || !coef_qp || !lam || !u || !out) return fail(SG_EINVAL, "null argument");
+    if (mu_index < 0 || mu_index >= h->n_mu) return fail(SG_EINVAL, "mu_index out of range");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const Level& l0 = h->lv[0];
+    const int dim = h->d.dim, N1 = h->d.fe_degree + 1;
+    const size_t per_mode = (size_t)l0.g.n_cells * h->NP;
+    const bool mean = mu_index == h->cpl.mu0;
+    // the field at the Gauss points, scaled like the create-time coefficients (weight, h^(d-2))
+    h->hstage.resize(per_mode);
+    const double hs = std::pow(l0.h, dim - 2);
+    for (size_t c = 0; c < (size_t)l0.g.n_cells; ++c)
+        for (int q = 0; q < h->NP; ++q) {
+            double wq = hs;
+            for (int dd = 0, qq = q; dd < dim; ++dd, qq /= N1) wq *= h->tgw[qq % N1];
+            h->hstage[c * h->NP + q] = coef_qp[c * h->NP + q] * wq;
+        }
+    const size_t nmodes = mean ? 1 : (size_t)h->n_mu;
+    if (h->fcoef.n < (size_t)h->n_mu * per_mode) SG_TRY(h->fcoef.alloc((size_t)h->n_mu * per_mode, "form coefficient"));
+    if (!mean) SG_HIP(launch_fill<double>(h->fcoef.p, 0.0, (long long)(nmodes * per_mode), s));
+    double* dst = h->fcoef.p + (mean ? 0 : (size_t)mu_index * per_mode);
+    SG_HIP(hipMemcpyAsync(dst, h->hstage.data(), per_mode * sizeof(double), hipMemcpyHostToDevice, s));
+    const std::vector<double> no_mass((size_t)h->NT * h->NT, 0.0);
+    const Tables<double> tb = tables_with(h, no_mass);
+    SG_TRY(variant_apply(h, &tb, h->fcoef.p, !mean, u, nullptr, GATHER_SET, s));
+    SG_HIP(launch_cell_dot(dim, h->d.fe_degree, l0.g, h->n_xi * h->NT, lam, h->sbuf.p, out, s));
+    SG_HIP(hipStreamSynchronize(s));   // the host staging array is reused by the next call
+    return SG_OK;
+}
+
+sg_status sg_qoi_mean_var(sg_handle h, const double* u, double w_mean, double w_var, double* qoi, double* grad,
+                          void* hip_stream) {
+    if (!h || !u || !qoi) return fail(SG_EINVAL, "null argument");
+    if (grad && overlap(u, grad, h->N * sizeof(double))) return fail(SG_EINVAL, "u and grad overlap");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int nx = h->n_xi, NT = h->NT, r = NT - 1;
+    const long long nn = h->lv[0].g.n_nodes, ld = (long long)NT * nn;
+    SG_TRY(zero_coef(h, s));
+    // w = (I (x) e_r e_r^T (x) M_x) u: the mass-weighted end-of-slab trace, Dirichlet rows 0
+    std::vector<double> err((size_t)NT * NT, 0.0);
+    err[(size_t)r * NT + r] = 1.0;
+    const Tables<double> tb = tables_with(h, err);
+    double* w = h->w1.p;
+    SG_TRY(variant_apply(h, &tb, h->zcoef.p, false, u, w, GATHER_INTERIOR, s));
+    if (h->qpart.n < (size_t)kDotBlocks * nx) SG_TRY(h->qpart.alloc((size_t)kDotBlocks * nx, "QoI partials"));
+    if (h->qout.n < (size_t)nx * nx) SG_TRY(h->qout.alloc((size_t)nx * nx, "QoI Gram matrix"));
+    if (h->qC.n < (size_t)nx * nx) SG_TRY(h->qC.alloc((size_t)nx * nx, "QoI gradient weights"));
+    // Gram matrix m[b][a] = u_a(T) . (M_x u_b(T))
+    for (int b = 0; b < nx; ++b) {
+        SG_HIP(launch_multidot(u + (long long)r * nn, ld, nx, w + ((long long)b * NT + r) * nn, nn, h->qpart.p,
+                               kDotBlocks, s));
+        SG_HIP(launch_reduce_partials(h->qpart.p, kDotBlocks, nx, h->qout.p + (size_t)b * nx, s));
+    }
+    std::vector<double> m((size_t)nx * nx);
+    SG_HIP(hipMemcpyAsync(m.data(), h->qout.p, m.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    SG_HIP(hipStreamSynchronize(s));
+    build_triple_table(h);
+    const int ne = h->n_eps;
+    std::vector<double> q(ne, 0.0);
+    for (int a = 0; a < nx; ++a)
+        for (int b = 0; b < nx; ++b) {
+            const double mab = 0.5 * (m[(size_t)a * nx + b] + m[(size_t)b * nx + a]);
+            const double* t = &h->trip[((size_t)a * nx + b) * ne];
+            for (int e = 0; e < ne; ++e) q[e] += mab * t[e];
+        }
+    double var = 0.0;
+    for (int e = 1; e < ne; ++e) var += q[e] * q[e];
+    qoi[0] = q[0];
+    qoi[1] = var;
+    if (!grad) return SG_OK;
+    // dJ/du_a(T) = sum_d C[a][d] w_d,  C = 2 w_mean I + 4 w_var sum_{eps != 0} q_eps E[Psi_a Psi_d Psi_eps]
+    h->hstage.assign((size_t)nx * nx, 0.0);
+    for (int a = 0; a < nx; ++a)
+        for (int d = 0; d < nx; ++d) {
+            const double* t = &h->trip[((size_t)a * nx + d) * ne];
+            double c = (a == d) ? 2.0 * w_mean : 0.0;
+            for (int e = 1; e < ne; ++e) c += 4.0 * w_var * q[e] * t[e];
+            h->hstage[(size_t)a * nx + d] = c;
+        }
+    SG_HIP(hipMemcpyAsync(h->qC.p, h->hstage.data(), h->hstage.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    SG_HIP(launch_fill<double>(grad, 0.0, h->N, s));
+    for (int a = 0; a < nx; ++a)
+        for (int d0 = 0; d0 < nx; d0 += 64) {
+            const int kk = std::min(64, nx - d0);
+            SG_HIP(launch_multi_axpy(w + ((long long)d0 * NT + r) * nn, ld, kk, h->qC.p + (size_t)a * nx + d0,
+                                     grad + ((long long)a * NT + r) * nn, nn, s));
+        }
+    SG_HIP(hipStreamSynchronize(s));
+    return SG_OK;
+}
+
 sg_status sg_quadrature_points(const sg_problem_desc* d, int level, double* xyz) {
     if (!d || !xyz) return fail(SG_EINVAL, "null argument");
     if (d->dim != 2 && d->dim != 3) return fail(SG_EINVAL, "dim must be 2 or 3");
@@ -964,6 +1160,33 @@ sg_status sg_quadrature_points(const sg_problem_desc* d, int level, double* xyz)
         for (int i = 0; i < dim; ++i) { cc[i] = r % n; r /= n; }
         for (int q = 0; q < NP; ++q)
             for (int i = 0, qq = q; i < dim; ++i, qq /= N1) xyz[(c * NP + q) * dim + i] = d->lo + h * (cc[i] + gq[qq % N1]);
+    }
+    return SG_OK;
+}
+
+sg_status sg_node_coordinates(const sg_problem_desc* d, int level, double* xyz) {
+    if (!d || !xyz) return fail(SG_EINVAL, "null argument");
+    if (d->dim != 2 && d->dim != 3) return fail(SG_EINVAL, "dim must be 2 or 3");
+    if (d->fe_degree < 1 || d->fe_degree > 4 || d->n_cells_1d < 1) return fail(SG_EINVAL, "bad mesh");
+    if (level < 0 || (d->n_cells_1d >> level) < 1 || (d->n_cells_1d % (1 << level)) != 0)
+        return fail(SG_EINVAL, "level out of range");
+    const int n = d->n_cells_1d >> level, k = d->fe_degree, dim = d->dim;
+    const int n1 = n * k + 1;
+    const double h = (d->hi - d->lo) / n;
+    const std::vector<double> gll = gll_points(k);
+    std::vector<double> x1(n1);
+    for (int i = 0; i < n1; ++i) {
+        const int c = std::min(i / k, n - 1);
+        x1[i] = d->lo + h * (c + gll[i - c * k]);
+    }
+    long long nn = 1;
+    for (int i = 0; i < dim; ++i) nn *= n1;
+    for (long long v = 0; v < nn; ++v) {
+        long long r = v;
+        for (int i = 0; i < dim; ++i) {
+            xyz[v * dim + i] = x1[r % n1];
+            r /= n1;
+        }
     }
     return SG_OK;
 }

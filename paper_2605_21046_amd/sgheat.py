@@ -19,7 +19,8 @@ SG_FP64, SG_MIXED = 0, 1
 _STATUS = {0: "SG_OK", 1: "SG_NOT_CONVERGED", -1: "SG_EINVAL", -2: "SG_ENOMEM", -3: "SG_EHIP",
            -4: "SG_ESINGULAR", -5: "SG_EUNSUPPORTED"}
 EXPORTS = ["sg_create", "sg_destroy", "sg_vector_length", "sg_operator_apply", "sg_vanka_smooth",
-           "gmg_vcycle", "fgmres_solve_slab", "sg_quadrature_points", "sg_last_error"]
+           "gmg_vcycle", "fgmres_solve_slab", "sg_quadrature_points", "sg_node_coordinates", "sg_operator_apply_T",
+           "sg_slab_transfer", "sg_stiffness_form_cells", "sg_qoi_mean_var", "sg_last_error"]
 
 
 class SgError(RuntimeError):
@@ -35,7 +36,7 @@ class ProblemDesc(ctypes.Structure):
                 ("n_coef_modes", ctypes.c_int), ("coef_mu", ctypes.POINTER(ctypes.c_int)),
                 ("coef_qp", ctypes.POINTER(ctypes.c_double)), ("n_levels", ctypes.c_int),
                 ("pre_smooth", ctypes.c_int), ("post_smooth", ctypes.c_int), ("vanka_omega", ctypes.c_double),
-                ("fgmres_restart", ctypes.c_int), ("precision", ctypes.c_int)]
+                ("fgmres_restart", ctypes.c_int), ("precision", ctypes.c_int), ("transpose", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -61,10 +62,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gmg_vcycle.argtypes = [P, V, V, V]
     lib.fgmres_solve_slab.argtypes = [P, V, V, D, I, ctypes.POINTER(SolveInfo), V]
     lib.sg_quadrature_points.argtypes = [ctypes.POINTER(ProblemDesc), I, ctypes.POINTER(ctypes.c_double)]
+    lib.sg_node_coordinates.argtypes = [ctypes.POINTER(ProblemDesc), I, ctypes.POINTER(ctypes.c_double)]
+    lib.sg_operator_apply_T.argtypes = [P, V, V, V]
+    lib.sg_slab_transfer.argtypes = [P, I, V, V, V]
+    lib.sg_stiffness_form_cells.argtypes = [P, I, ctypes.POINTER(ctypes.c_double), V, V, V, V]
+    lib.sg_qoi_mean_var.argtypes = [P, V, D, D, ctypes.POINTER(ctypes.c_double), V, V]
     lib.sg_last_error.restype = ctypes.c_char_p
-    for f in ["sg_create", "sg_destroy", "sg_vector_length", "sg_operator_apply", "sg_vanka_smooth", "gmg_vcycle",
-              "fgmres_solve_slab", "sg_quadrature_points"]:
-        getattr(lib, f).restype = ctypes.c_int
+    for f in EXPORTS:
+        if f != "sg_last_error":
+            getattr(lib, f).restype = ctypes.c_int
     return lib
 
 
@@ -94,12 +100,13 @@ class Spec:
     post_smooth: int = 1
     vanka_omega: float = 1.0
     fgmres_restart: int = 30
+    transpose: int = 0
 
 
 def _desc(spec, precision=SG_FP64):
     d = ProblemDesc()
     for name in ["dim", "n_cells_1d", "fe_degree", "time_degree", "n_vars", "chaos_degree", "n_levels",
-                 "pre_smooth", "post_smooth", "fgmres_restart"]:
+                 "pre_smooth", "post_smooth", "fgmres_restart", "transpose"]:
         setattr(d, name, int(getattr(spec, name)))
     for name in ["lo", "hi", "tau", "vanka_omega"]:
         setattr(d, name, float(getattr(spec, name)))
@@ -114,6 +121,15 @@ def quadrature_points(spec, level: int) -> np.ndarray:
     npts = (spec.fe_degree + 1) ** spec.dim
     out = np.zeros((n ** spec.dim, npts, spec.dim))
     _check(_lib.sg_quadrature_points(ctypes.byref(d), level, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
+
+
+def node_coordinates(spec, level: int) -> np.ndarray:
+    """Physical node coordinates of a level, [n_nodes, d] (lexicographic, x fastest)."""
+    d = _desc(spec)
+    n1 = (spec.n_cells_1d >> level) * spec.fe_degree + 1
+    out = np.zeros((n1 ** spec.dim, spec.dim))
+    _check(_lib.sg_node_coordinates(ctypes.byref(d), level, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return out
 
 
@@ -179,6 +195,45 @@ class Problem:
         n = self.n(0)
         _check(_lib.sg_operator_apply(self._h, _ptr(x, n, "x"), _ptr(y, n, "y"), _stream(stream)))
         return y
+
+    def apply_T(self, x, y=None, stream=None):
+        """y = AA^T x (AA x for a handle made with transpose=1)."""
+        import torch
+        if y is None:
+            y = torch.empty_like(x)
+        n = self.n(0)
+        _check(_lib.sg_operator_apply_T(self._h, _ptr(x, n, "x"), _ptr(y, n, "y"), _stream(stream)))
+        return y
+
+    def slab_transfer(self, x, y=None, transpose=False, stream=None):
+        """y = (I (x) C_t (x) M_x) x, or with C_t^T."""
+        import torch
+        if y is None:
+            y = torch.empty_like(x)
+        n = self.n(0)
+        _check(_lib.sg_slab_transfer(self._h, int(bool(transpose)), _ptr(x, n, "x"), _ptr(y, n, "y"), _stream(stream)))
+        return y
+
+    def stiffness_form_cells(self, mu_index, coef_qp, lam, u, out=None, stream=None):
+        """out[K] = lam^T (G_mu (x) B_t (x) K_{c|K}) u for the field c given at the level-0 Gauss points."""
+        import torch
+        n = self.n(0)
+        n_cells = self.spec.n_cells_1d ** self.spec.dim
+        c = np.ascontiguousarray(np.asarray(coef_qp, dtype=np.float64).reshape(n_cells, -1))
+        if out is None:
+            out = torch.empty(n_cells, dtype=torch.float64, device=lam.device)
+        _check(_lib.sg_stiffness_form_cells(self._h, int(mu_index), c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            _ptr(lam, n, "lam"), _ptr(u, n, "u"), _ptr(out, n_cells, "out"),
+                                            _stream(stream)))
+        return out
+
+    def qoi_mean_var(self, u, w_mean=1.0, w_var=1.0, grad=None, stream=None):
+        """(E[Q], Var[Q]) of Q = int_D u(T)^2 and, if grad is a tensor, dJ/du for J = w_mean E + w_var Var."""
+        n = self.n(0)
+        q = (ctypes.c_double * 2)()
+        g = _ptr(grad, n, "grad") if grad is not None else None
+        _check(_lib.sg_qoi_mean_var(self._h, _ptr(u, n, "u"), float(w_mean), float(w_var), q, g, _stream(stream)))
+        return float(q[0]), float(q[1])
 
     def vanka_smooth(self, level, b, x, sweeps=1, stream=None):
         n = self.n(level)

@@ -158,3 +158,84 @@ def interior_target(w: Workload, seed: int = SEED_SOLVE_TARGET) -> np.ndarray:
     x = uniform_vector(w.n_dofs(0), seed).reshape(w.n_chaos * w.n_time, -1)
     x[:, ~inner] = 0.0
     return x.reshape(-1)
+
+
+# ---- adjoint workloads: a sequence of slabs, a parametrised coefficient, an initial value ------------
+SEED_ADJOINT_A0 = 3
+
+
+@dataclass(frozen=True)
+class AdjointWorkload:
+    """Slab sequence for the mean/variance QoI gradient: ``n_slabs`` slabs of ``base.tau``.
+
+    Coefficient a(x, xi) = a_0(x) + sum_m theta_m phi_m(x) xi_m with a_0 constant on each finest cell
+    (seeded 1 + a0_spread U[-1, 1]), phi_m the sine shapes; initial value u_0 = prod_k sin(pi x_k) in
+    the mean mode; no forcing.
+    """
+    base: Workload
+    n_slabs: int
+    a0_spread: float = 0.2
+
+    def theta0(self) -> np.ndarray:
+        return np.array([0.1 / m ** 2 for m in range(1, self.base.n_vars + 1)])
+
+    def a0_cells0(self) -> np.ndarray:
+        n = self.base.n_cells_1d ** self.base.dim
+        u = np.random.Generator(np.random.PCG64(SEED_ADJOINT_A0)).uniform(-1.0, 1.0, size=n)
+        return 1.0 + self.a0_spread * u
+
+
+ADJOINT_WORKLOADS = {
+    # 3D Q2 on 16^3 cells, dG(1), tau = 0.01, 10 slabs, M = 3, p_xi = 3 (20 modes), 3-level GMG
+    "c5": AdjointWorkload(Workload("c5", 3, 16, 2, 1, 0.01, 3, 3, 3, "sine"), 10),
+    # small cases for the tests
+    "a2": AdjointWorkload(Workload("a2", 2, 4, 2, 1, 0.02, 2, 2, 2, "sine"), 3),
+    "a3": AdjointWorkload(Workload("a3", 3, 2, 2, 1, 0.02, 2, 2, 1, "sine"), 2),
+}
+
+
+def cell_means_to_coarse(a_cells: np.ndarray, dim: int, n: int) -> np.ndarray:
+    """Per-cell values on n^d cells -> the mean over the 2^d children on (n/2)^d cells."""
+    a = np.asarray(a_cells, dtype=np.float64).reshape((n,) * dim)   # [z][y][x] (x fastest in memory)
+    for ax in range(dim):
+        sl = [slice(None)] * dim
+        sl0, sl1 = list(sl), list(sl)
+        sl0[ax] = slice(0, None, 2)
+        sl1[ax] = slice(1, None, 2)
+        a = 0.5 * (a[tuple(sl0)] + a[tuple(sl1)])
+    return a.reshape(-1)
+
+
+def adjoint_coef_levels(aw: AdjointWorkload, theta, a0_cells, points_fn):
+    """Coefficient values for every level in the slab library's layout, for parameters (theta, a0).
+
+    Level 0 carries a_0 per cell; coarser levels the mean of the children.  Returns (mu_list, coef)
+    with coef[level] of shape [M + 1, n_cells(level), n_points].
+    """
+    w = aw.base
+    M = w.n_vars
+    mus = [tuple([0] * M)] + [tuple(1 if j == m else 0 for j in range(M)) for m in range(M)]
+    out = []
+    a0 = np.asarray(a0_cells, dtype=np.float64)
+    for level in range(w.n_levels):
+        n = w.n_cells_1d >> level
+        pts = np.asarray(points_fn(level))                 # [n_cells, n_points, d]
+        vals = np.empty((M + 1,) + pts.shape[:2])
+        vals[0] = a0[:, None]
+        for m in range(1, M + 1):
+            vals[m] = theta[m - 1] * _sine_shape(m, pts)
+        out.append(vals)
+        if level + 1 < w.n_levels:
+            a0 = cell_means_to_coarse(a0, w.dim, n)
+    return mus, out
+
+
+def sine_shape_at(m: int, pts: np.ndarray) -> np.ndarray:
+    """phi_m at the given points (the derivative field of a_{e_m} with respect to theta_m)."""
+    return _sine_shape(m, np.asarray(pts, dtype=np.float64))
+
+
+def initial_value(x: np.ndarray) -> np.ndarray:
+    """u_0(x) = prod_k sin(pi x_k) (mean mode of the initial value)."""
+    x = np.asarray(x, dtype=np.float64)
+    return np.prod(np.sin(math.pi * x), axis=-1)
