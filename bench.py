@@ -129,6 +129,37 @@ def cpu_baseline(w, seconds_target=15.0):
             "c1_apply_gdofs": round(P1.n / dt1 / 1e9, 5), "c1_spsolve_s": round(t_sp, 4)}
 
 
+def adjoint_timing(torch, name="c5", reps=2):
+    """Gradient of J = E[Q] + Var[Q] with respect to the 3 amplitudes and the 4096 cell values of a_0
+    (forward sweep with slab-end checkpoints + adjoint sweep); wall time per gradient, set-up of the two
+    handles included."""
+    import sg_inputs
+    from paper_2605_21046_amd.adjoint import SlabSequence
+    aw = sg_inputs.ADJOINT_WORKLOADS[name]
+    seq = SlabSequence(aw, rtol=1e-10)
+    th, a0 = aw.theta0(), aw.a0_cells0()
+    seq.gradient(th, a0)
+    times, fwd = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J, _ = seq.forward(th, a0)[0], None
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dth, da0 = seq.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        times.append(t2 - t0)
+        fwd.append(t1 - t0)
+    stats = {k: int(sum(v)) for k, v in seq.stats.items()}
+    seq.close()
+    w = aw.base
+    return {"workload": f"{name}: {w.dim}D Q{w.fe_degree} on {w.n_cells_1d}^{w.dim} cells, dG({w.time_degree}), "
+                        f"M={w.n_vars}, p_xi={w.chaos_degree} ({w.n_chaos} modes), {aw.n_slabs} slabs of tau={w.tau}",
+            "gradient_ms": round(1e3 * float(np.mean(times)), 1), "forward_ms": round(1e3 * float(np.mean(fwd)), 1),
+            "J": J, "n_params": len(th) + len(a0), "fgmres_iterations": stats}
+
+
 def copy_bandwidth(torch, dev, reps=20):
     """Achievable HBM bandwidth of a plain device copy over two disjoint 1 GiB buffer pairs."""
     n = 1 << 27
@@ -156,6 +187,7 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient timing (16^3 cells, 10 slabs)")
     ap.add_argument("--only-apply", action="store_true", help="skip the solves (for profiling the apply)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy 5 times (reference for the HBM byte counters)")
@@ -285,6 +317,10 @@ def main():
         out["solve"] = res
     else:
         out["ms_per_step"] = round(t_apply * 1e3, 4)
+
+    if not args.no_adjoint and not args.only_apply:
+        out["adjoint"] = adjoint_timing(torch)
+        print(f"[bench] adjoint gradient {out['adjoint']['gradient_ms']} ms", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)

@@ -134,6 +134,14 @@ sg_status sg_quadrature_points(const sg_problem_desc* desc, int level, double* x
  * taken as the Gauss-Lobatto points, the paper naming none).  Needs no handle. */
 sg_status sg_node_coordinates(const sg_problem_desc* desc, int level, double* xyz);
 
+/* Replace the coefficient values of a handle (same index set, same layout as sg_problem_desc.coef_qp:
+ * HOST [n_levels][n_coef_modes][n_cells(l)][(k+1)^d], copied) and redo everything that depends on
+ * them: the Vanka patch inverses of every level and the coarsest-level inverse (Remark
+ * solver-matrix-free-sg).  Keeps every device allocation of the handle, so a parameter sweep (e.g.
+ * the forward/adjoint solves of an optimisation loop) pays no allocation.  Synchronous; must not
+ * overlap other calls on the handle.  SG_ESINGULAR if a patch or the coarse matrix is singular. */
+sg_status sg_update_coefficients(sg_handle h, const double* coef_qp);
+
 /* y = AA^T x for a handle made with transpose = 0 (y = AA x for transpose = 1): the operator of the
  * adjoint slab problem (Problem tensor-product-slab-system with A_t transposed; the other factors of
  * eq. local_rhs_tensor are symmetric).  FP64, finest level, identity rows on Dirichlet DoFs.  x and

@@ -60,14 +60,18 @@ class SlabSequence:
 
     # --- problem set-up for one parameter value ---------------------------------------------------
     def set_parameters(self, theta, a0_cells):
+        """Coefficients for (theta, a0): the handles are made once and updated in place afterwards."""
         import sg_inputs
-        self.close()
         mus, coef = sg_inputs.adjoint_coef_levels(self.aw, np.asarray(theta, dtype=np.float64),
                                                   np.asarray(a0_cells, dtype=np.float64),
                                                   lambda lvl: self.qp[lvl])
-        self.G = sgheat.Problem(self.spec, mus, coef, self.precision)
-        specT = sgheat.Spec(**{**self.spec.__dict__, "transpose": 1})
-        self.GT = sgheat.Problem(specT, mus, coef, self.precision)
+        if self.G is None:
+            self.G = sgheat.Problem(self.spec, mus, coef, self.precision)
+            specT = sgheat.Spec(**{**self.spec.__dict__, "transpose": 1})
+            self.GT = sgheat.Problem(specT, mus, coef, self.precision)
+        else:
+            self.G.update_coefficients(coef)
+            self.GT.update_coefficients(coef)
         self.theta = np.asarray(theta, dtype=np.float64)
 
     def close(self):

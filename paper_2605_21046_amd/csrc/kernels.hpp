@@ -70,6 +70,10 @@ struct PatchTime {
     double At[kMaxNT * kMaxNT];
     double Bt[kMaxNT];
 };
+// In-place inverse of a dense n x n FP64 matrix A (row-major) by Gauss-Jordan elimination with
+// partial pivoting, then its transpose into AinvT (column-major inverse, for coalesced reads of the
+// coarse solve).  Scratch: col[n], perm[n]; status is set to 1 if a pivot is zero.  2n + 2 launches.
+hipError_t launch_dense_invert(double* A, int n, double* col, int* perm, int* status, double* AinvT, hipStream_t s);
 hipError_t launch_patch_invert(int dim, int k, int nt, Grid g, const double* E, const double* Me,
                                const PatchTime& pt, double* inv64, float* inv32, int* status,
                                hipStream_t s);

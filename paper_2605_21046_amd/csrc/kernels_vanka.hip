@@ -491,6 +491,97 @@ hipError_t vanka_k(int k, int nt, Grid g, int n_xi, const T* invT, const T* r, T
 
 }  // namespace
 
+// ---- dense Gauss-Jordan inverse (coarsest level) -------------------------------------------------
+// Step k, part 1 (one workgroup): pivot p = argmax_{i >= k} |A[i][k]|, swap rows k and p, scale row k
+// by 1/A[k][k] (A[k][k] <- 1/A[k][k]), and stash column k (before the update) in col.
+__global__ void __launch_bounds__(1024) k_gj_pivot(double* __restrict__ A, int n, int k, double* __restrict__ col,
+                                                   int* __restrict__ perm, int* __restrict__ status) {
+    __shared__ double bv[1024];
+    __shared__ int bi[1024];
+    double best = -1.0;
+    int arg = k;
+    for (int i = k + threadIdx.x; i < n; i += 1024) {
+        const double v = fabs(A[(long long)i * n + k]);
+        if (v > best) { best = v; arg = i; }
+    }
+    bv[threadIdx.x] = best;
+    bi[threadIdx.x] = arg;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            const double o = bv[threadIdx.x + w];
+            const int oi = bi[threadIdx.x + w];
+            if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+                bv[threadIdx.x] = o;
+                bi[threadIdx.x] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    const int p = bi[0];
+    if (!(bv[0] > 0.0)) {
+        if (threadIdx.x == 0) *status = 1;
+        return;                       // uniform: every thread returns
+    }
+    if (p != k)
+        for (int j = threadIdx.x; j < n; j += 1024) {
+            const double t = A[(long long)k * n + j];
+            A[(long long)k * n + j] = A[(long long)p * n + j];
+            A[(long long)p * n + j] = t;
+        }
+    __syncthreads();
+    const double ipiv = 1.0 / A[(long long)k * n + k];
+    for (int i = threadIdx.x; i < n; i += 1024) col[i] = A[(long long)i * n + k];
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += 1024)
+        A[(long long)k * n + j] = (j == k) ? ipiv : A[(long long)k * n + j] * ipiv;
+    if (threadIdx.x == 0) perm[k] = p;
+}
+
+// Step k, part 2: every row i != k: A[i][j] -= col[i] A[k][j] (j != k), A[i][k] = -col[i] / pivot.
+__global__ void __launch_bounds__(256) k_gj_eliminate(double* __restrict__ A, int n, int k,
+                                                      const double* __restrict__ col, const int* __restrict__ status) {
+    if (*status) return;
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    const int i = blockIdx.y;
+    if (i == k || j >= n) return;
+    const double f = col[i];
+    if (f == 0.0) return;
+    const double akj = A[(long long)k * n + j];   // row k is final (scaled) after part 1
+    if (j == k) A[(long long)i * n + k] = -f * akj;
+    else A[(long long)i * n + j] -= f * akj;
+}
+
+// Undo the row interchanges on the inverse (column swaps in reverse order; one thread per row) and
+// write the transpose.
+__global__ void __launch_bounds__(256) k_gj_finish(double* __restrict__ A, int n, const int* __restrict__ perm,
+                                                   const int* __restrict__ status, double* __restrict__ AinvT) {
+    if (*status) return;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double* row = A + (long long)i * n;
+    for (int k = n - 1; k >= 0; --k) {
+        const int p = perm[k];
+        if (p != k) {
+            const double t = row[k];
+            row[k] = row[p];
+            row[p] = t;
+        }
+    }
+    for (int j = 0; j < n; ++j) AinvT[(long long)j * n + i] = row[j];
+}
+
+hipError_t launch_dense_invert(double* A, int n, double* col, int* perm, int* status, double* AinvT, hipStream_t s) {
+    if (n < 1 || n > 65535) return hipErrorInvalidValue;
+    const dim3 eg((n + 255) / 256, n);
+    for (int k = 0; k < n; ++k) {
+        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, s, A, n, k, col, perm, status);
+        hipLaunchKernelGGL(k_gj_eliminate, eg, dim3(256), 0, s, A, n, k, col, status);
+    }
+    hipLaunchKernelGGL(k_gj_finish, dim3((n + 255) / 256), dim3(256), 0, s, A, n, perm, status, AinvT);
+    return hipGetLastError();
+}
+
 hipError_t launch_elem_stiffness(int dim, int k, Grid g, const double* coef0, const ElemTables& et, double* E,
                                  hipStream_t s) {
     const int np = dim == 2 ? (k + 1) * (k + 1) : (k + 1) * (k + 1) * (k + 1);

@@ -13,7 +13,6 @@
 #include <cstring>
 #include <memory>
 #include <string>
-#include <thread>
 #include <vector>
 
 #include "../../include/sgheat.h"
@@ -50,6 +49,7 @@ struct DevBuf {
     size_t n = 0;
     ~DevBuf() { if (p) (void)hipFree(p); }
     sg_status alloc(size_t count, const char* what) {
+        if (p && n == count) return SG_OK;   // same size: keep the allocation
         if (p) (void)hipFree(p);
         p = nullptr;
         n = count;
@@ -118,9 +118,10 @@ struct sg_handle_s {
     long long N = 0;
     // operator variants on level 0: 1D tables, the other orientation of A_t, the end-of-slab
     // transfer, scratch for the bilinear forms and the quantity of interest
-    std::vector<double> tS, tD, tgw, radau0;   // radau0[i] = v_i(0+)
+    std::vector<double> tS, tD, tDn, tgw, radau0, Me1;   // radau0[i] = v_i(0+); Me1: unit-cell mass
     Tables<double> tabT64{};
     DevBuf<double> zcoef, fcoef, qpart, qout, qC;
+    DevBuf<double> elem_E, elem_M;             // element matrices of the patch set-up (reused)
     std::vector<double> hstage;
     std::vector<double> trip;                 // E[Psi_a Psi_b Psi_eps], [n_xi][n_xi][n_eps]
     int n_eps = 0;
@@ -195,49 +196,182 @@ void prolong_1d(int nc, int k, const std::vector<double>& gll, std::vector<int>*
     }
 }
 
-// Host Gauss-Jordan inversion with partial pivoting (coarsest level only).
-bool invert_dense(std::vector<double>& A, int n) {
-    std::vector<int> perm(n);
-    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    for (int k = 0; k < n; ++k) {
-        int p = k;
-        double best = std::fabs(A[(size_t)k * n + k]);
-        for (int i = k + 1; i < n; ++i)
-            if (std::fabs(A[(size_t)i * n + k]) > best) { best = std::fabs(A[(size_t)i * n + k]); p = i; }
-        if (!(best > 0.0)) return false;
-        perm[k] = p;
-        if (p != k)
-            for (int j = 0; j < n; ++j) std::swap(A[(size_t)k * n + j], A[(size_t)p * n + j]);
-        const double ipiv = 1.0 / A[(size_t)k * n + k];
-        double* rowk = &A[(size_t)k * n];
-        for (int j = 0; j < n; ++j) rowk[j] *= ipiv;
-        rowk[k] = ipiv;
-        auto work = [&](int i0, int i1) {
-            for (int i = i0; i < i1; ++i) {
-                if (i == k) continue;
-                double* ri = &A[(size_t)i * n];
-                const double f = ri[k];
-                if (f == 0.0) continue;
-                for (int j = 0; j < n; ++j) ri[j] -= f * rowk[j];
-                ri[k] = -f * ipiv;
-            }
-        };
-        if (n < 256 || nth == 1) {
-            work(0, n);
-        } else {
-            std::vector<std::thread> th;
-            const int chunk = (n + (int)nth - 1) / (int)nth;
-            for (unsigned t = 0; t < nth; ++t) {
-                const int i0 = (int)t * chunk, i1 = std::min(n, i0 + chunk);
-                if (i0 < i1) th.emplace_back(work, i0, i1);
-            }
-            for (auto& t : th) t.join();
+// Everything that depends on the coefficient values: the pre-scaled coefficients of every level,
+// the Vanka patch inverses and the coarsest-level inverse.  Called by sg_create and
+// sg_update_coefficients; the device arrays keep their allocations between calls.
+sg_status set_coefficients(sg_handle h, const double* coef_qp) {
+    const sg_problem_desc& d = h->d;
+    const int dim = d.dim, k = d.fe_degree, N1 = k + 1, L = d.n_levels;
+    const std::vector<double>& S = h->tS;
+    const std::vector<double>& Dn = h->tDn;
+    const std::vector<double>& gw = h->tgw;
+    const std::vector<double>& Me1 = h->Me1;
+    size_t coef_off = 0;
+    for (int l = 0; l < L; ++l) {
+        Level& lv = h->lv[l];
+        // coefficients, pre-scaled by the Gauss weight and h^(d-2)
+        const size_t per_mode = (size_t)lv.g.n_cells * h->NP;
+        const int nm = (l == 0) ? h->n_mu : 1;
+        std::vector<double> c64((size_t)nm * per_mode);
+        const double hs = std::pow(lv.h, dim - 2);
+        for (int mi = 0; mi < nm; ++mi) {
+            const int mu = (l == 0) ? mi : h->cpl.mu0;
+            const double* src = coef_qp + coef_off + (size_t)mu * per_mode;
+            for (size_t c = 0; c < (size_t)lv.g.n_cells; ++c)
+                for (int q = 0; q < h->NP; ++q) {
+                    double wq = hs;
+                    for (int dd = 0, qq = q; dd < dim; ++dd, qq /= N1) wq *= gw[qq % N1];
+                    c64[mi * per_mode + c * h->NP + q] = src[c * h->NP + q] * wq;
+                }
+        }
+        coef_off += (size_t)h->n_mu * per_mode;
+        SG_TRY(lv.coef64.upload(c64.data(), c64.size(), "coefficients"));
+        if (h->mixed) {
+            std::vector<float> c32(c64.begin(), c64.end());
+            SG_TRY(lv.coef32.upload(c32.data(), c32.size(), "coefficients"));
         }
     }
-    for (int k = n - 1; k >= 0; --k)
-        if (perm[k] != k)
-            for (int i = 0; i < n; ++i) std::swap(A[(size_t)i * n + k], A[(size_t)i * n + perm[k]]);
-    return true;
+
+    // Vanka patch inverses on every level (device)
+    {
+        PatchTime pt{};
+        for (int i = 0; i < h->NT; ++i) {
+            pt.Bt[i] = h->Bt[i];
+            for (int j = 0; j < h->NT; ++j) pt.At[i * h->NT + j] = h->At[i * h->NT + j];
+        }
+        ElemTables et{};
+        for (int i = 0; i < N1 * N1; ++i) {
+            et.S[i] = S[i];
+            et.Dn[i] = Dn[i];
+        }
+        DevBuf<int> status;
+        int zero = 0;
+        SG_TRY(status.upload(&zero, 1, "status"));
+        for (int l = 0; l < L; ++l) {
+            Level& lv = h->lv[l];
+            DevBuf<double>& E = h->elem_E;
+            DevBuf<double>& Me = h->elem_M;
+            if (E.n < (size_t)lv.g.n_cells * h->NP * h->NP)
+                SG_TRY(E.alloc((size_t)lv.g.n_cells * h->NP * h->NP, "element matrices"));
+            std::vector<double> Mel(Me1);
+            const double vol = std::pow(lv.h, dim);
+            for (double& v : Mel) v *= vol;
+            SG_TRY(Me.upload(Mel.data(), Mel.size(), "element matrices"));
+            const double* c0 = lv.coef64.p + (l == 0 ? (size_t)h->cpl.mu0 * lv.g.n_cells * h->NP : 0);
+            SG_HIP(launch_elem_stiffness(dim, k, lv.g, c0, et, E.p, nullptr));
+            const size_t ninv = (size_t)lv.g.n_cells * h->npp * h->npp;
+            const bool want32 = h->mixed && l < L - 1;
+            SG_TRY(lv.inv64.alloc(ninv, "patch inverses"));
+            if (want32) SG_TRY(lv.inv32.alloc(ninv, "patch inverses"));
+            SG_HIP(launch_patch_invert(dim, k, h->NT, lv.g, E.p, Me.p, pt, lv.inv64.p, want32 ? lv.inv32.p : nullptr,
+                                       status.p, nullptr));
+            SG_HIP(hipDeviceSynchronize());
+        }
+        int st = 0;
+        SG_HIP(hipMemcpy(&st, status.p, sizeof(int), hipMemcpyDeviceToHost));
+        if (st) return fail(SG_ESINGULAR, "a Vanka patch matrix is singular");
+    }
+
+    // coarsest level: dense A_0 on interior DoFs, inverted on the host
+    {
+        const Level& lc = h->lv[L - 1];
+        const int n = lc.g.n, n1 = lc.g.n1;
+        std::vector<int> interior_node(lc.g.n_nodes, -1);
+        std::vector<int> inodes;
+        for (long long node = 0; node < lc.g.n_nodes; ++node) {
+            bool bnd = false;
+            long long r = node;
+            for (int dd = 0; dd < dim; ++dd) {
+                const int id = r % n1;
+                r /= n1;
+                bnd |= (id == 0 || id == n1 - 1);
+            }
+            if (!bnd) {
+                interior_node[node] = (int)inodes.size();
+                inodes.push_back((int)node);
+            }
+        }
+        const int ni = (int)inodes.size();
+        h->nint = ni * h->NT;
+        if (h->nint > 12000) return fail(SG_EINVAL, "coarsest level too large for the dense solve; add levels");
+        std::vector<double> A((size_t)h->nint * h->nint, 0.0);
+        const double* c0 = coef_qp;
+        size_t off = 0;
+        for (int l = 0; l < L - 1; ++l) off += (size_t)h->n_mu * h->lv[l].g.n_cells * h->NP;
+        c0 += off + (size_t)h->cpl.mu0 * lc.g.n_cells * h->NP;
+        const double vol = std::pow(lc.h, dim), hs = std::pow(lc.h, dim - 2);
+        // reference stiffness integrands Kref[q][a][b] = w_q h^(d-2) sum_e dphi_a/dx_e dphi_b/dx_e (x_q)
+        const int NP = h->NP;
+        std::vector<double> Kref((size_t)NP * NP * NP);
+        for (int q = 0; q < NP; ++q) {
+            double wq = hs;
+            for (int dd = 0, qq = q; dd < dim; ++dd, qq /= N1) wq *= gw[qq % N1];
+            for (int a = 0; a < NP; ++a)
+                for (int b = 0; b < NP; ++b) {
+                    double gsum = 0.0;
+                    for (int e = 0; e < dim; ++e) {
+                        double va = 1.0, vb = 1.0;
+                        for (int dd = 0, qq = q, aa = a, bb = b; dd < dim; ++dd, qq /= N1, aa /= N1, bb /= N1) {
+                            va *= (dd == e ? Dn : S)[(qq % N1) * N1 + aa % N1];
+                            vb *= (dd == e ? Dn : S)[(qq % N1) * N1 + bb % N1];
+                        }
+                        gsum += va * vb;
+                    }
+                    Kref[((size_t)q * NP + a) * NP + b] = wq * gsum;
+                }
+        }
+        std::vector<double> Ke((size_t)NP * NP);
+        for (long long cell = 0; cell < lc.g.n_cells; ++cell) {
+            int cc[3] = {0, 0, 0};
+            long long r = cell;
+            for (int dd = 0; dd < dim; ++dd) { cc[dd] = r % n; r /= n; }
+            std::vector<int> nodes(NP);
+            for (int a = 0; a < NP; ++a) {
+                long long node = 0, mul = 1;
+                for (int dd = 0, aa = a; dd < dim; ++dd, aa /= N1) { node += (cc[dd] * k + aa % N1) * mul; mul *= n1; }
+                nodes[a] = interior_node[node];
+            }
+            std::fill(Ke.begin(), Ke.end(), 0.0);
+            for (int q = 0; q < NP; ++q) {
+                const double cq = c0[cell * NP + q];
+                const double* kr = &Kref[(size_t)q * NP * NP];
+                for (size_t ab = 0; ab < (size_t)NP * NP; ++ab) Ke[ab] += cq * kr[ab];
+            }
+            for (int a = 0; a < h->NP; ++a) {
+                if (nodes[a] < 0) continue;
+                for (int b = 0; b < h->NP; ++b) {
+                    if (nodes[b] < 0) continue;
+                    const double m = Me1[(size_t)a * h->NP + b] * vol, kv = Ke[(size_t)a * h->NP + b];
+                    for (int i = 0; i < h->NT; ++i)
+                        for (int j = 0; j < h->NT; ++j) {
+                            const size_t row = (size_t)i * ni + nodes[a], col = (size_t)j * ni + nodes[b];
+                            A[row * h->nint + col] += h->At[i * h->NT + j] * m + (i == j ? h->Bt[i] * kv : 0.0);
+                        }
+                }
+            }
+        }
+        // Gauss-Jordan inverse on the device (the matrix is a few thousand rows at most)
+        if (h->nint > 0) {
+            DevBuf<double> Ad, col;
+            DevBuf<int> perm, status;
+            int zero = 0;
+            SG_TRY(Ad.upload(A.data(), A.size(), "coarse matrix"));
+            SG_TRY(col.alloc(h->nint, "coarse pivots"));
+            SG_TRY(perm.alloc(h->nint, "coarse pivots"));
+            SG_TRY(status.upload(&zero, 1, "status"));
+            SG_TRY(h->coarse_invT.alloc((size_t)h->nint * h->nint, "coarse inverse"));
+            SG_HIP(launch_dense_invert(Ad.p, h->nint, col.p, perm.p, status.p, h->coarse_invT.p, nullptr));
+            int st = 0;
+            SG_HIP(hipMemcpy(&st, status.p, sizeof(int), hipMemcpyDeviceToHost));
+            if (st) return fail(SG_ESINGULAR, "coarsest-level matrix is singular");
+        }
+        std::vector<int> dofs(h->nint);
+        for (int i = 0; i < h->NT; ++i)
+            for (int a = 0; a < ni; ++a) dofs[i * ni + a] = i * (int)lc.g.n_nodes + inodes[a];
+        SG_TRY(h->coarse_dofs.upload(dofs.data(), dofs.size(), "coarse dofs"));
+    }
+
+    return SG_OK;
 }
 
 sg_status build(sg_handle h) {
@@ -313,12 +447,12 @@ sg_status build(sg_handle h) {
 
     h->tS = S;
     h->tD = D;
+    h->tDn = Dn;
     h->tgw = gw;
 
     // levels
     const int L = d.n_levels;
     h->lv.resize(L);
-    size_t coef_off = 0;
     for (int l = 0; l < L; ++l) {
         Level& lv = h->lv[l];
         const int n = d.n_cells_1d >> l;
@@ -339,27 +473,6 @@ sg_status build(sg_handle h) {
             for (int i = 0; i < h->NT; ++i)
                 for (int j = 0; j < h->NT; ++j) at[i * h->NT + j] = h->At[j * h->NT + i];
             fill_tables(&h->tabT64, S, D, gw, at, h->Bt, N1, h->NT, std::pow(lv.h, dim));
-        }
-        // coefficients, pre-scaled by the Gauss weight and h^(d-2)
-        const size_t per_mode = (size_t)lv.g.n_cells * h->NP;
-        const int nm = (l == 0) ? h->n_mu : 1;
-        std::vector<double> c64((size_t)nm * per_mode);
-        const double hs = std::pow(lv.h, dim - 2);
-        for (int mi = 0; mi < nm; ++mi) {
-            const int mu = (l == 0) ? mi : h->cpl.mu0;
-            const double* src = d.coef_qp + coef_off + (size_t)mu * per_mode;
-            for (size_t c = 0; c < (size_t)lv.g.n_cells; ++c)
-                for (int q = 0; q < h->NP; ++q) {
-                    double wq = hs;
-                    for (int dd = 0, qq = q; dd < dim; ++dd, qq /= N1) wq *= gw[qq % N1];
-                    c64[mi * per_mode + c * h->NP + q] = src[c * h->NP + q] * wq;
-                }
-        }
-        coef_off += (size_t)h->n_mu * per_mode;
-        SG_TRY(lv.coef64.upload(c64.data(), c64.size(), "coefficients"));
-        if (h->mixed) {
-            std::vector<float> c32(c64.begin(), c64.end());
-            SG_TRY(lv.coef32.upload(c32.data(), c32.size(), "coefficients"));
         }
         // work vectors
         SG_TRY(lv.b64.alloc(lv.len, "level vectors"));
@@ -387,124 +500,8 @@ sg_status build(sg_handle h) {
             Me1[(size_t)a * h->NP + b] = s;
         }
 
-    // Vanka patch inverses on every level (device)
-    {
-        PatchTime pt{};
-        for (int i = 0; i < h->NT; ++i) {
-            pt.Bt[i] = h->Bt[i];
-            for (int j = 0; j < h->NT; ++j) pt.At[i * h->NT + j] = h->At[i * h->NT + j];
-        }
-        ElemTables et{};
-        for (int i = 0; i < N1 * N1; ++i) {
-            et.S[i] = S[i];
-            et.Dn[i] = Dn[i];
-        }
-        DevBuf<int> status;
-        int zero = 0;
-        SG_TRY(status.upload(&zero, 1, "status"));
-        for (int l = 0; l < L; ++l) {
-            Level& lv = h->lv[l];
-            DevBuf<double> E, Me;
-            SG_TRY(E.alloc((size_t)lv.g.n_cells * h->NP * h->NP, "element matrices"));
-            std::vector<double> Mel(Me1);
-            const double vol = std::pow(lv.h, dim);
-            for (double& v : Mel) v *= vol;
-            SG_TRY(Me.upload(Mel.data(), Mel.size(), "element matrices"));
-            const double* c0 = lv.coef64.p + (l == 0 ? (size_t)h->cpl.mu0 * lv.g.n_cells * h->NP : 0);
-            SG_HIP(launch_elem_stiffness(dim, k, lv.g, c0, et, E.p, nullptr));
-            const size_t ninv = (size_t)lv.g.n_cells * h->npp * h->npp;
-            const bool want32 = h->mixed && l < L - 1;
-            SG_TRY(lv.inv64.alloc(ninv, "patch inverses"));
-            if (want32) SG_TRY(lv.inv32.alloc(ninv, "patch inverses"));
-            SG_HIP(launch_patch_invert(dim, k, h->NT, lv.g, E.p, Me.p, pt, lv.inv64.p, want32 ? lv.inv32.p : nullptr,
-                                       status.p, nullptr));
-            SG_HIP(hipDeviceSynchronize());
-        }
-        int st = 0;
-        SG_HIP(hipMemcpy(&st, status.p, sizeof(int), hipMemcpyDeviceToHost));
-        if (st) return fail(SG_ESINGULAR, "a Vanka patch matrix is singular");
-    }
-
-    // coarsest level: dense A_0 on interior DoFs, inverted on the host
-    {
-        const Level& lc = h->lv[L - 1];
-        const int n = lc.g.n, n1 = lc.g.n1;
-        std::vector<int> interior_node(lc.g.n_nodes, -1);
-        std::vector<int> inodes;
-        for (long long node = 0; node < lc.g.n_nodes; ++node) {
-            bool bnd = false;
-            long long r = node;
-            for (int dd = 0; dd < dim; ++dd) {
-                const int id = r % n1;
-                r /= n1;
-                bnd |= (id == 0 || id == n1 - 1);
-            }
-            if (!bnd) {
-                interior_node[node] = (int)inodes.size();
-                inodes.push_back((int)node);
-            }
-        }
-        const int ni = (int)inodes.size();
-        h->nint = ni * h->NT;
-        if (h->nint > 12000) return fail(SG_EINVAL, "coarsest level too large for the dense solve; add levels");
-        std::vector<double> A((size_t)h->nint * h->nint, 0.0);
-        const double* c0 = d.coef_qp;
-        size_t off = 0;
-        for (int l = 0; l < L - 1; ++l) off += (size_t)h->n_mu * h->lv[l].g.n_cells * h->NP;
-        c0 += off + (size_t)h->cpl.mu0 * lc.g.n_cells * h->NP;
-        const double vol = std::pow(lc.h, dim), hs = std::pow(lc.h, dim - 2);
-        std::vector<double> Ke((size_t)h->NP * h->NP);
-        for (long long cell = 0; cell < lc.g.n_cells; ++cell) {
-            int cc[3] = {0, 0, 0};
-            long long r = cell;
-            for (int dd = 0; dd < dim; ++dd) { cc[dd] = r % n; r /= n; }
-            std::vector<int> nodes(h->NP);
-            for (int a = 0; a < h->NP; ++a) {
-                long long node = 0, mul = 1;
-                for (int dd = 0, aa = a; dd < dim; ++dd, aa /= N1) { node += (cc[dd] * k + aa % N1) * mul; mul *= n1; }
-                nodes[a] = interior_node[node];
-            }
-            for (int a = 0; a < h->NP; ++a)
-                for (int b = 0; b < h->NP; ++b) {
-                    double s = 0.0;
-                    for (int q = 0; q < h->NP; ++q) {
-                        double wq = hs, gsum = 0.0;
-                        for (int dd = 0, qq = q; dd < dim; ++dd, qq /= N1) wq *= gw[qq % N1];
-                        for (int e = 0; e < dim; ++e) {
-                            double va = 1.0, vb = 1.0;
-                            for (int dd = 0, qq = q, aa = a, bb = b; dd < dim; ++dd, qq /= N1, aa /= N1, bb /= N1) {
-                                va *= (dd == e ? Dn : S)[(qq % N1) * N1 + aa % N1];
-                                vb *= (dd == e ? Dn : S)[(qq % N1) * N1 + bb % N1];
-                            }
-                            gsum += va * vb;
-                        }
-                        s += c0[cell * h->NP + q] * wq * gsum;
-                    }
-                    Ke[(size_t)a * h->NP + b] = s;
-                }
-            for (int a = 0; a < h->NP; ++a) {
-                if (nodes[a] < 0) continue;
-                for (int b = 0; b < h->NP; ++b) {
-                    if (nodes[b] < 0) continue;
-                    const double m = Me1[(size_t)a * h->NP + b] * vol, kv = Ke[(size_t)a * h->NP + b];
-                    for (int i = 0; i < h->NT; ++i)
-                        for (int j = 0; j < h->NT; ++j) {
-                            const size_t row = (size_t)i * ni + nodes[a], col = (size_t)j * ni + nodes[b];
-                            A[row * h->nint + col] += h->At[i * h->NT + j] * m + (i == j ? h->Bt[i] * kv : 0.0);
-                        }
-                }
-            }
-        }
-        if (!invert_dense(A, h->nint)) return fail(SG_ESINGULAR, "coarsest-level matrix is singular");
-        std::vector<double> AT((size_t)h->nint * h->nint);
-        for (int i = 0; i < h->nint; ++i)
-            for (int j = 0; j < h->nint; ++j) AT[(size_t)j * h->nint + i] = A[(size_t)i * h->nint + j];
-        std::vector<int> dofs(h->nint);
-        for (int i = 0; i < h->NT; ++i)
-            for (int a = 0; a < ni; ++a) dofs[i * ni + a] = i * (int)lc.g.n_nodes + inodes[a];
-        SG_TRY(h->coarse_invT.upload(AT.data(), AT.size(), "coarse inverse"));
-        SG_TRY(h->coarse_dofs.upload(dofs.data(), dofs.size(), "coarse dofs"));
-    }
+    h->Me1 = Me1;
+    SG_TRY(set_coefficients(h, d.coef_qp));
 
     // transfer stencils and temporaries
     size_t tmax = 0;
@@ -1022,6 +1019,15 @@ sg_status fgmres_solve_slab(sg_handle h, const double* b, double* x, double rtol
     if (info) *info = inf;
     if (result == SG_NOT_CONVERGED) g_last_error = "FGMRES did not reach the tolerance within max_iter";
     return result;
+}
+
+sg_status sg_update_coefficients(sg_handle h, const double* coef_qp) {
+    if (!h || !coef_qp) return fail(SG_EINVAL, "null argument");
+    try {
+        return set_coefficients(h, coef_qp);
+    } catch (const std::bad_alloc&) {
+        return fail(SG_ENOMEM, "host allocation failed during the coefficient update");
+    }
 }
 
 sg_status sg_operator_apply_T(sg_handle h, const double* x, double* y, void* hip_stream) {

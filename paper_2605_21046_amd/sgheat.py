@@ -19,7 +19,7 @@ SG_FP64, SG_MIXED = 0, 1
 _STATUS = {0: "SG_OK", 1: "SG_NOT_CONVERGED", -1: "SG_EINVAL", -2: "SG_ENOMEM", -3: "SG_EHIP",
            -4: "SG_ESINGULAR", -5: "SG_EUNSUPPORTED"}
 EXPORTS = ["sg_create", "sg_destroy", "sg_vector_length", "sg_operator_apply", "sg_vanka_smooth",
-           "gmg_vcycle", "fgmres_solve_slab", "sg_quadrature_points", "sg_node_coordinates", "sg_operator_apply_T",
+           "gmg_vcycle", "fgmres_solve_slab", "sg_quadrature_points", "sg_node_coordinates", "sg_update_coefficients", "sg_operator_apply_T",
            "sg_slab_transfer", "sg_stiffness_form_cells", "sg_qoi_mean_var", "sg_last_error"]
 
 
@@ -63,6 +63,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fgmres_solve_slab.argtypes = [P, V, V, D, I, ctypes.POINTER(SolveInfo), V]
     lib.sg_quadrature_points.argtypes = [ctypes.POINTER(ProblemDesc), I, ctypes.POINTER(ctypes.c_double)]
     lib.sg_node_coordinates.argtypes = [ctypes.POINTER(ProblemDesc), I, ctypes.POINTER(ctypes.c_double)]
+    lib.sg_update_coefficients.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
     lib.sg_operator_apply_T.argtypes = [P, V, V, V]
     lib.sg_slab_transfer.argtypes = [P, I, V, V, V]
     lib.sg_stiffness_form_cells.argtypes = [P, I, ctypes.POINTER(ctypes.c_double), V, V, V, V]
@@ -171,6 +172,11 @@ class Problem:
         self.precision = precision
         self.shape = (math_comb(spec.n_vars + spec.chaos_degree, spec.chaos_degree), spec.time_degree + 1,
                       (spec.n_cells_1d * spec.fe_degree + 1) ** spec.dim)
+
+    def update_coefficients(self, coef_qp_levels):
+        """New coefficient values (same modes and layout as at construction); keeps the allocations."""
+        coef = np.ascontiguousarray(np.concatenate([np.asarray(c, np.float64).reshape(-1) for c in coef_qp_levels]))
+        _check(_lib.sg_update_coefficients(self._h, coef.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
