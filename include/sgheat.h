@@ -71,6 +71,13 @@ typedef struct {
     double vanka_omega;     /* damping of the additive Vanka correction                              */
     int fgmres_restart;     /* Krylov basis length before restart (<= 64)                            */
     sg_precision precision;
+    int n_samples;          /* 0: stochastic Galerkin (modes = the total-degree set of degree p_xi).
+                             * > 0: a batch of pathwise problems (Section 5.1, Problem
+                             * mc-pathwise-deterministic): "mode" s is the sample xi^(s) = samples[s],
+                             * G_mu = diag(Psi_mu(xi^(s))), so row block s is the deterministic slab
+                             * system with coefficient a(x, xi^(s)); chaos_degree is then ignored.  The
+                             * preconditioner keeps the mean block A_0 for every sample.             */
+    const double* samples;  /* host [n_samples][n_vars] (copied), used when n_samples > 0            */
     int transpose;          /* 0: the slab operator AA; 1: its transpose AA^T (the adjoint slab
                              * problem).  For an affine coefficient G_mu, M_x, K_mu are symmetric and
                              * B_t is diagonal, so AA^T is AA with A_t replaced by A_t^T; every entry
@@ -176,7 +183,15 @@ sg_status sg_stiffness_form_cells(sg_handle h, int mu_index, const double* coef_
  * grad != NULL, grad = dJ/du for J = w_mean E[Q] + w_var Var[Q] (a device slab vector, nonzero only in
  * time component r on interior DoFs).  Synchronises the stream. */
 sg_status sg_qoi_mean_var(sg_handle h, const double* u, double w_mean, double w_var, double* qoi, double* grad,
-                          void* hip_stream);
+                          void* hip_stream);   /* SG_EUNSUPPORTED for a sample-batch handle */
+
+/* Monte-Carlo estimators over the samples of a handle made with n_samples = N > 1 (Section 5.2, eqs.
+ * mc-mean-estimator and mc-variance-estimator-unbiased), per time component and node:
+ *     mean[i][node] = (1/N) sum_s u[s][i][node],
+ *     var[i][node]  = 1/(N-1) sum_s (u[s][i][node] - mean[i][node])^2.
+ * u is a device slab vector of the handle; mean and var are device arrays of N_t * n_nodes(0)
+ * doubles (var may be NULL).  Two passes over the samples, FP64.  Asynchronous. */
+sg_status sg_sample_statistics(sg_handle h, const double* u, double* mean, double* var, void* hip_stream);
 
 /* Message for the last non-OK status returned on the calling thread ("" if none). */
 const char* sg_last_error(void);

@@ -166,22 +166,29 @@ double hermite_triple_1d(int a, int b, int c) {
            (factorial(s - a) * factorial(s - b) * factorial(s - c));
 }
 
-bool build_coupling(int M, int p, int n_mu, const int* mu, Coupling* out, std::string* err) {
-    auto idx = total_degree_set(M, p);
-    const int n_xi = (int)idx.size();
-    out->n_xi = n_xi;
-    out->n_mu = n_mu;
-    out->ptr.assign(1, 0);
-    out->beta.clear();
-    out->w.clear();
+// He_n(x) / sqrt(n!) by the three-term recurrence He_{n+1} = x He_n - n He_{n-1}.
+double hermite_normalized(int n, double x) {
+    double hm = 1.0, h = x;
+    if (n == 0) return 1.0;
+    double fact = 1.0;
+    for (int k = 1; k < n; ++k) {
+        const double hn = x * h - k * hm;
+        hm = h;
+        h = hn;
+    }
+    for (int k = 2; k <= n; ++k) fact *= k;
+    return h / std::sqrt(fact);
+}
+
+namespace {
+bool check_modes(int M, int n_mu, const int* mu, Coupling* out, std::string* err) {
     out->affine = true;
     out->mu0 = -1;
     for (int k = 0; k < n_mu; ++k) {
-        int deg = 0, nz = 0;
+        int deg = 0;
         for (int m = 0; m < M; ++m) {
             if (mu[k * M + m] < 0) { *err = "negative entry in coef_mu"; return false; }
             deg += mu[k * M + m];
-            nz += mu[k * M + m] != 0;
         }
         if (deg == 0) {
             if (out->mu0 >= 0) { *err = "coef_mu lists mu = 0 twice"; return false; }
@@ -190,6 +197,38 @@ bool build_coupling(int M, int p, int n_mu, const int* mu, Coupling* out, std::s
         if (deg > 1) out->affine = false;
     }
     if (out->mu0 < 0) { *err = "coef_mu must contain mu = 0"; return false; }
+    return true;
+}
+}  // namespace
+
+bool build_sample_coupling(int M, int n_samples, const double* xi, int n_mu, const int* mu, Coupling* out,
+                           std::string* err) {
+    out->n_xi = n_samples;
+    out->n_mu = n_mu;
+    out->ptr.assign(1, 0);
+    out->beta.clear();
+    out->w.clear();
+    if (!check_modes(M, n_mu, mu, out, err)) return false;
+    for (int s = 0; s < n_samples; ++s)
+        for (int k = 0; k < n_mu; ++k) {
+            double v = 1.0;
+            for (int m = 0; m < M; ++m) v *= hermite_normalized(mu[k * M + m], xi[(size_t)s * M + m]);
+            out->beta.push_back(s);
+            out->w.push_back(v);
+            out->ptr.push_back((int)out->beta.size());
+        }
+    return true;
+}
+
+bool build_coupling(int M, int p, int n_mu, const int* mu, Coupling* out, std::string* err) {
+    auto idx = total_degree_set(M, p);
+    const int n_xi = (int)idx.size();
+    out->n_xi = n_xi;
+    out->n_mu = n_mu;
+    out->ptr.assign(1, 0);
+    out->beta.clear();
+    out->w.clear();
+    if (!check_modes(M, n_mu, mu, out, err)) return false;
     for (int a = 0; a < n_xi; ++a)
         for (int k = 0; k < n_mu; ++k) {
             for (int b = 0; b < n_xi; ++b) {

@@ -44,4 +44,13 @@ struct Coupling {
 };
 bool build_coupling(int M, int p, int n_mu, const int* mu, Coupling* out, std::string* err);
 
+// Normalised probabilists' Hermite polynomial He_n(x) / sqrt(n!).
+double hermite_normalized(int n, double x);
+
+// A batch of pathwise problems (Section 5.1: one deterministic problem per sample xi^(s)) in the
+// same Kronecker form: "mode" s is sample s and G_mu = diag(Psi_mu(xi^(s))), so sum_mu G_mu a_mu is
+// the sampled coefficient a(x, xi^(s)) on the diagonal.  xi is [n_samples][M].
+bool build_sample_coupling(int M, int n_samples, const double* xi, int n_mu, const int* mu, Coupling* out,
+                           std::string* err);
+
 }  // namespace sg

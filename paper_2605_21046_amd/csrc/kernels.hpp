@@ -50,6 +50,10 @@ enum GatherOp { GATHER_SET = 0, GATHER_RESIDUAL = 1, GATHER_VANKA = 2, GATHER_IN
 // cell-local operator whose per-cell results s_in = A_K u are in the broken layout.
 hipError_t launch_cell_dot(int dim, int k, Grid g, int ncomp, const double* lam, const double* s_in, double* out,
                            hipStream_t s);
+
+// mean[i][node] and unbiased var[i][node] over N sample blocks of a slab vector u[N][nt][nn]
+hipError_t launch_sample_stats(const double* u, int N, int nt, long long nn, double* mean, double* var,
+                               hipStream_t s);
 template <typename T>
 hipError_t launch_node_gather(GatherOp op, int dim, int k, Grid g, int ncomp, const T* s_in, const T* x, const T* b,
                               T* out, T omega, hipStream_t s);

@@ -116,6 +116,31 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// Mean and unbiased variance over the N samples (component blocks s * nt + i) at every (i, node).
+__global__ void __launch_bounds__(256)
+    k_sample_stats(const double* __restrict__ u, int N, int nt, long long nn, double* __restrict__ mean,
+                   double* __restrict__ var) {
+    const long long total = (long long)nt * nn;
+    for (long long idx = blockIdx.x * 256LL + threadIdx.x; idx < total; idx += (long long)gridDim.x * 256) {
+        const long long i = idx / nn, node = idx % nn;
+        const double* p = u + i * nn + node;
+        const long long stride = (long long)nt * nn;
+        double s = 0.0;
+        for (int k = 0; k < N; ++k) s += p[k * stride];
+        const double m = s / N;
+        mean[idx] = m;
+        if (var) {
+            double q = 0.0;
+            for (int k = 0; k < N; ++k) {
+                const double d = p[k * stride] - m;
+                q += d * d;
+            }
+            var[idx] = N > 1 ? q / (N - 1) : 0.0;
+        }
+    }
+}
+
+
 // One workgroup per cell: sum of lam * s over the cell's (component, local node) pairs.
 __global__ void __launch_bounds__(256)
     k_cell_dot(int dim, int k, Grid g, int ncomp, const double* __restrict__ lam, const double* __restrict__ s_in,
@@ -362,6 +387,13 @@ hipError_t launch_node_gather(GatherOp op, int dim, int k, Grid g, int ncomp, co
     }
 #undef SG_NG_K
 #undef SG_NG
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_stats(const double* u, int N, int nt, long long nn, double* mean, double* var, hipStream_t s) {
+    const long long total = (long long)nt * nn;
+    const unsigned blocks = (unsigned)std::min<long long>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_sample_stats, dim3(blocks), dim3(256), 0, s, u, N, nt, nn, mean, var);
     return hipGetLastError();
 }
 

@@ -93,6 +93,7 @@ struct Level {
 struct sg_handle_s {
     sg_problem_desc d{};
     std::vector<int> coef_mu;
+    std::vector<double> samples;   // sample-batch handles: [n_samples][n_vars]
     int NP = 0, NT = 0, n_xi = 0, n_mu = 0, npp = 0;
     Coupling cpl;
     bool mixed = false;
@@ -169,6 +170,7 @@ sg_status validate(const sg_problem_desc* d) {
     if (d->fgmres_restart < 1 || d->fgmres_restart > 64) return fail(SG_EINVAL, "fgmres_restart must be in 1..64");
     if (d->precision != SG_FP64 && d->precision != SG_MIXED) return fail(SG_EINVAL, "unknown precision");
     if (d->transpose != 0 && d->transpose != 1) return fail(SG_EINVAL, "transpose must be 0 or 1");
+    if (d->n_samples < 0 || (d->n_samples > 0 && !d->samples)) return fail(SG_EINVAL, "samples missing");
     return SG_OK;
 }
 
@@ -206,6 +208,21 @@ sg_status set_coefficients(sg_handle h, const double* coef_qp) {
     const std::vector<double>& Dn = h->tDn;
     const std::vector<double>& gw = h->tgw;
     const std::vector<double>& Me1 = h->Me1;
+    if (d.n_samples > 0) {
+        // every pathwise coefficient a(x, xi^(s)) = sum_mu Psi_mu(xi^(s)) a_mu(x) must be positive at the
+        // finest level's Gauss points (the sample problems are then uniformly elliptic)
+        const size_t per_mode = (size_t)h->lv[0].g.n_cells * h->NP;
+        for (int smp = 0; smp < d.n_samples; ++smp) {
+            const int* pp = h->cpl.ptr.data() + (size_t)smp * h->n_mu;
+            for (size_t q = 0; q < per_mode; ++q) {
+                double a = 0.0;
+                for (int mi = 0; mi < h->n_mu; ++mi) a += h->cpl.w[pp[mi]] * coef_qp[(size_t)mi * per_mode + q];
+                if (!(a > 0.0))
+                    return fail(SG_EINVAL, "the coefficient of sample " + std::to_string(smp) +
+                                               " is not positive at every Gauss point");
+            }
+        }
+    }
     size_t coef_off = 0;
     for (int l = 0; l < L; ++l) {
         Level& lv = h->lv[l];
@@ -381,8 +398,11 @@ sg_status build(sg_handle h) {
     h->NT = d.time_degree + 1;
     h->mixed = d.precision == SG_MIXED;
     std::string err;
-    if (!build_coupling(d.n_vars, d.chaos_degree, d.n_coef_modes, h->coef_mu.data(), &h->cpl, &err))
-        return fail(SG_EINVAL, err);
+    const bool ok = d.n_samples > 0
+                        ? build_sample_coupling(d.n_vars, d.n_samples, h->samples.data(), d.n_coef_modes,
+                                                h->coef_mu.data(), &h->cpl, &err)
+                        : build_coupling(d.n_vars, d.chaos_degree, d.n_coef_modes, h->coef_mu.data(), &h->cpl, &err);
+    if (!ok) return fail(SG_EINVAL, err);
     h->n_xi = h->cpl.n_xi;
     h->n_mu = d.n_coef_modes;
     h->npp = h->NT * h->NP;
@@ -633,7 +653,7 @@ ApplyOp<T> make_op(const sg_handle h, int level, bool full) {
     }
     op.mean = !full;
     op.n_ent = full ? (int)h->cpl.beta.size() : h->n_xi;
-    op.affine = h->cpl.affine && h->d.n_vars <= 8;
+    op.affine = h->cpl.affine && h->d.n_vars <= 8 && h->d.n_samples == 0;   // Hermite tables only
     op.chaos_m = h->d.n_vars;
     op.chaos_p = h->d.chaos_degree;
     op.mu0 = h->cpl.mu0;
@@ -839,6 +859,8 @@ sg_status sg_create(const sg_problem_desc* desc, sg_handle* out) {
     h->d = *desc;
     h->coef_mu.assign(desc->coef_mu, desc->coef_mu + (size_t)desc->n_coef_modes * desc->n_vars);
     h->d.coef_mu = h->coef_mu.data();
+    if (desc->n_samples > 0) h->samples.assign(desc->samples, desc->samples + (size_t)desc->n_samples * desc->n_vars);
+    h->d.samples = nullptr;   // host array not retained
     try {
         sg_status s = build(h.get());
         h->d.coef_qp = nullptr;   // host array not retained
@@ -1089,6 +1111,7 @@ sg_status sg_stiffness_form_cells(sg_handle h, int mu_index, const double* coef_
 sg_status sg_qoi_mean_var(sg_handle h, const double* u, double w_mean, double w_var, double* qoi, double* grad,
                           void* hip_stream) {
     if (!h || !u || !qoi) return fail(SG_EINVAL, "null argument");
+    if (h->d.n_samples > 0) return fail(SG_EUNSUPPORTED, "the chaos QoI needs a stochastic Galerkin handle");
     if (grad && overlap(u, grad, h->N * sizeof(double))) return fail(SG_EINVAL, "u and grad overlap");
     hipStream_t s = (hipStream_t)hip_stream;
     const int nx = h->n_xi, NT = h->NT, r = NT - 1;
@@ -1167,6 +1190,13 @@ sg_status sg_quadrature_points(const sg_problem_desc* d, int level, double* xyz)
         for (int q = 0; q < NP; ++q)
             for (int i = 0, qq = q; i < dim; ++i, qq /= N1) xyz[(c * NP + q) * dim + i] = d->lo + h * (cc[i] + gq[qq % N1]);
     }
+    return SG_OK;
+}
+
+sg_status sg_sample_statistics(sg_handle h, const double* u, double* mean, double* var, void* hip_stream) {
+    if (!h || !u || !mean) return fail(SG_EINVAL, "null argument");
+    if (h->d.n_samples < 1) return fail(SG_EINVAL, "not a sample-batch handle");
+    SG_HIP(launch_sample_stats(u, h->d.n_samples, h->NT, h->lv[0].g.n_nodes, mean, var, (hipStream_t)hip_stream));
     return SG_OK;
 }
 

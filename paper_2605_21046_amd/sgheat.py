@@ -20,7 +20,7 @@ _STATUS = {0: "SG_OK", 1: "SG_NOT_CONVERGED", -1: "SG_EINVAL", -2: "SG_ENOMEM", 
            -4: "SG_ESINGULAR", -5: "SG_EUNSUPPORTED"}
 EXPORTS = ["sg_create", "sg_destroy", "sg_vector_length", "sg_operator_apply", "sg_vanka_smooth",
            "gmg_vcycle", "fgmres_solve_slab", "sg_quadrature_points", "sg_node_coordinates", "sg_update_coefficients", "sg_operator_apply_T",
-           "sg_slab_transfer", "sg_stiffness_form_cells", "sg_qoi_mean_var", "sg_last_error"]
+           "sg_slab_transfer", "sg_stiffness_form_cells", "sg_qoi_mean_var", "sg_sample_statistics", "sg_last_error"]
 
 
 class SgError(RuntimeError):
@@ -36,7 +36,8 @@ class ProblemDesc(ctypes.Structure):
                 ("n_coef_modes", ctypes.c_int), ("coef_mu", ctypes.POINTER(ctypes.c_int)),
                 ("coef_qp", ctypes.POINTER(ctypes.c_double)), ("n_levels", ctypes.c_int),
                 ("pre_smooth", ctypes.c_int), ("post_smooth", ctypes.c_int), ("vanka_omega", ctypes.c_double),
-                ("fgmres_restart", ctypes.c_int), ("precision", ctypes.c_int), ("transpose", ctypes.c_int)]
+                ("fgmres_restart", ctypes.c_int), ("precision", ctypes.c_int), ("n_samples", ctypes.c_int),
+                ("samples", ctypes.POINTER(ctypes.c_double)), ("transpose", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -68,6 +69,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sg_slab_transfer.argtypes = [P, I, V, V, V]
     lib.sg_stiffness_form_cells.argtypes = [P, I, ctypes.POINTER(ctypes.c_double), V, V, V, V]
     lib.sg_qoi_mean_var.argtypes = [P, V, D, D, ctypes.POINTER(ctypes.c_double), V, V]
+    lib.sg_sample_statistics.argtypes = [P, V, V, V, V]
     lib.sg_last_error.restype = ctypes.c_char_p
     for f in EXPORTS:
         if f != "sg_last_error":
@@ -158,7 +160,9 @@ def _stream(stream):
 class Problem:
     """One slab problem on the GPU (a handle of libsgheat.so)."""
 
-    def __init__(self, spec, coef_mu, coef_qp_levels, precision=SG_FP64):
+    def __init__(self, spec, coef_mu, coef_qp_levels, precision=SG_FP64, samples=None):
+        """samples: None for the stochastic Galerkin operator, or [n_samples, n_vars] points xi^(s) for a
+        batch of pathwise problems (block s = the deterministic slab system at a(x, xi^(s)))."""
         self.spec = spec
         mus = np.ascontiguousarray(np.asarray(coef_mu, dtype=np.int32).reshape(-1, spec.n_vars))
         coef = np.ascontiguousarray(np.concatenate([np.asarray(c, np.float64).reshape(-1) for c in coef_qp_levels]))
@@ -166,12 +170,18 @@ class Problem:
         d.n_coef_modes = mus.shape[0]
         d.coef_mu = mus.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
         d.coef_qp = coef.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        n_modes = math_comb(spec.n_vars + spec.chaos_degree, spec.chaos_degree)
+        if samples is not None:
+            xi = np.ascontiguousarray(np.asarray(samples, dtype=np.float64).reshape(-1, spec.n_vars))
+            d.n_samples = xi.shape[0]
+            d.samples = xi.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            n_modes = xi.shape[0]
         h = ctypes.c_void_p()
         _check(_lib.sg_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
         self.precision = precision
-        self.shape = (math_comb(spec.n_vars + spec.chaos_degree, spec.chaos_degree), spec.time_degree + 1,
-                      (spec.n_cells_1d * spec.fe_degree + 1) ** spec.dim)
+        self.n_samples = 0 if samples is None else n_modes
+        self.shape = (n_modes, spec.time_degree + 1, (spec.n_cells_1d * spec.fe_degree + 1) ** spec.dim)
 
     def update_coefficients(self, coef_qp_levels):
         """New coefficient values (same modes and layout as at construction); keeps the allocations."""
@@ -240,6 +250,17 @@ class Problem:
         g = _ptr(grad, n, "grad") if grad is not None else None
         _check(_lib.sg_qoi_mean_var(self._h, _ptr(u, n, "u"), float(w_mean), float(w_var), q, g, _stream(stream)))
         return float(q[0]), float(q[1])
+
+    def sample_statistics(self, u, mean=None, var=None, stream=None):
+        """Sample mean and unbiased sample variance over the batch, each [N_t * n_nodes] (var optional)."""
+        import torch
+        n = self.n(0)
+        m = self.shape[1] * self.shape[2]
+        if mean is None:
+            mean = torch.empty(m, dtype=torch.float64, device=u.device)
+        v = _ptr(var, m, "var") if var is not None else None
+        _check(_lib.sg_sample_statistics(self._h, _ptr(u, n, "u"), _ptr(mean, m, "mean"), v, _stream(stream)))
+        return mean, var
 
     def vanka_smooth(self, level, b, x, sweeps=1, stream=None):
         n = self.n(level)

@@ -239,3 +239,30 @@ def initial_value(x: np.ndarray) -> np.ndarray:
     """u_0(x) = prod_k sin(pi x_k) (mean mode of the initial value)."""
     x = np.asarray(x, dtype=np.float64)
     return np.prod(np.sin(math.pi * x), axis=-1)
+
+
+@dataclass(frozen=True)
+class SampleWorkload:
+    """A batch of pathwise (Monte-Carlo) problems: the slab sequence of ``base`` (``n_slabs`` slabs of
+    ``base.tau``, initial value u_0 = prod_k sin(pi x_k), no forcing) with the coefficient of
+    ``base.field`` evaluated at ``n_samples`` draws xi ~ N(0, I_M) from the PCG64 stream ``seed``.
+    ``base.chaos_degree`` is not used."""
+    base: Workload
+    n_samples: int
+    n_slabs: int
+    seed: int = SEED_MC_DRAWS
+
+    def samples(self) -> np.ndarray:
+        g = np.random.Generator(np.random.PCG64(self.seed))
+        return g.standard_normal((self.n_samples, self.base.n_vars))
+
+
+SAMPLE_WORKLOADS = {
+    # 256 samples of the 8x8-cell workload's coefficient on 2D Q2 64^2 cells, dG(1), tau = 0.01,
+    # 20 slabs, 4-level GMG: 256 x 2 x 16641 = 8,520,192 DoFs per slab
+    "c4": SampleWorkload(Workload("c4", 2, 64, 2, 1, 0.01, 2, 0, 4, "c1"), 256, 20),
+    # small cases for the tests
+    "m2": SampleWorkload(Workload("m2", 2, 4, 2, 1, 0.02, 2, 0, 2, "c1"), 12, 3, seed=5),
+    "m3": SampleWorkload(Workload("m3", 3, 2, 2, 1, 0.02, 3, 0, 1, "sine"), 5, 2, seed=6),
+    "m2q3": SampleWorkload(Workload("m2q3", 2, 4, 3, 2, 0.02, 2, 0, 2, "sine"), 7, 2, seed=7),
+}
