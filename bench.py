@@ -160,6 +160,77 @@ def adjoint_timing(torch, name="c5", reps=2):
             "J": J, "n_params": len(th) + len(a0), "fgmres_iterations": stats}
 
 
+def sample_batch_timing(torch, name="c4", reps=2):
+    """All slabs of the Monte-Carlo batch (256 pathwise problems in one handle): wall time of the whole
+    time march (right-hand sides, slab solves to 1e-8, transfers) and of the sample statistics, FP64 and
+    mixed precision; set-up excluded."""
+    import sg_inputs
+    from paper_2605_21046_amd import sgheat
+    from paper_2605_21046_amd.montecarlo import SampleBatch
+    sw = sg_inputs.SAMPLE_WORKLOADS[name]
+    w = sw.base
+    out = {"workload": f"{name}: {sw.n_samples} samples xi ~ N(0, I_{w.n_vars}) (seed {sw.seed}), {w.dim}D "
+                       f"Q{w.fe_degree} on {w.n_cells_1d}^{w.dim} cells, dG({w.time_degree}), {sw.n_slabs} slabs of "
+                       f"tau={w.tau}, {w.n_levels}-level GMG, slab solves to rtol 1e-8"}
+    for label, prec in (("fp64", sgheat.SG_FP64), ("mixed", sgheat.SG_MIXED)):
+        B = SampleBatch(sw, rtol=1e-8, precision=prec)
+        n_dofs = B.P.n(0)
+        B.run()
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u = B.run()
+            mean, var = B.statistics(u)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        its = [i["iterations"] for i in B.info]
+        t = float(np.min(times))
+        out[f"{label}_ms"] = round(1e3 * t, 1)
+        out[f"{label}_ms_per_slab"] = round(1e3 * t / sw.n_slabs, 2)
+        out[f"{label}_iterations_per_slab"] = [min(its), max(its)]
+        out[f"{label}_sample_slabs_per_s"] = round(sw.n_samples * sw.n_slabs / t, 1)
+        out["dofs_per_slab"] = n_dofs
+        B.close()
+    return out
+
+
+def member_batch_timing(torch, name="c4", reps=2):
+    """All slabs of the 64 SG problems of degree 1..4 (packed into member-batch handles): wall time of
+    the whole time march (slab solves to 1e-8, transfers) and of the chaos moments, FP64 and mixed;
+    set-up excluded."""
+    import sg_inputs
+    from paper_2605_21046_amd import sgheat
+    from paper_2605_21046_amd.sgbatch import MemberBatch
+    mw = sg_inputs.MEMBER_WORKLOADS[name]
+    w = mw.base
+    out = {"workload": f"{name}: {len(mw.degrees)} SG problems of total degree "
+                       f"{'/'.join(str(p) for p in sorted(set(mw.degrees)))} (M={w.n_vars}), {w.dim}D Q{w.fe_degree} "
+                       f"on {w.n_cells_1d}^{w.dim} cells, dG({w.time_degree}), {mw.n_slabs} slabs of tau={w.tau}, "
+                       f"{w.n_levels}-level GMG, slab solves to rtol 1e-8"}
+    for label, prec in (("fp64", sgheat.SG_FP64), ("mixed", sgheat.SG_MIXED)):
+        B = MemberBatch(mw, rtol=1e-8, precision=prec)
+        B.run()
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            us = B.run()
+            B.moments(us)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        its = [i["iterations"] for i in B.info]
+        t = float(np.min(times))
+        out["handles"] = len(B.handles)
+        out["modes_per_handle"] = [B.handles[k].shape[0] for k in range(len(B.handles))]
+        out["dofs_per_slab"] = int(sum(P.n(0) for P in B.handles))
+        out[f"{label}_ms"] = round(1e3 * t, 1)
+        out[f"{label}_iterations_per_slab"] = [min(its), max(its)]
+        out[f"{label}_problem_slabs_per_s"] = round(len(mw.degrees) * mw.n_slabs / t, 1)
+        B.close()
+    return out
+
+
 def copy_bandwidth(torch, dev, reps=20):
     """Achievable HBM bandwidth of a plain device copy over two disjoint 1 GiB buffer pairs."""
     n = 1 << 27
@@ -188,6 +259,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient timing (16^3 cells, 10 slabs)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the Monte-Carlo batch timing (256 samples, 20 slabs)")
     ap.add_argument("--only-apply", action="store_true", help="skip the solves (for profiling the apply)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy 5 times (reference for the HBM byte counters)")
@@ -321,6 +393,14 @@ def main():
     if not args.no_adjoint and not args.only_apply:
         out["adjoint"] = adjoint_timing(torch)
         print(f"[bench] adjoint gradient {out['adjoint']['gradient_ms']} ms", file=sys.stderr, flush=True)
+
+    if not args.no_batch and not args.only_apply:
+        out["sample_batch"] = sample_batch_timing(torch)
+        print(f"[bench] sample batch {out['sample_batch']['fp64_ms']} ms fp64, {out['sample_batch']['mixed_ms']} ms mixed",
+              file=sys.stderr, flush=True)
+        out["member_batch"] = member_batch_timing(torch)
+        print(f"[bench] member batch {out['member_batch']['fp64_ms']} ms fp64, {out['member_batch']['mixed_ms']} ms mixed",
+              file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)

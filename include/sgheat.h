@@ -78,6 +78,15 @@ typedef struct {
                              * system with coefficient a(x, xi^(s)); chaos_degree is then ignored.  The
                              * preconditioner keeps the mean block A_0 for every sample.             */
     const double* samples;  /* host [n_samples][n_vars] (copied), used when n_samples > 0            */
+    int n_members;          /* 0: one stochastic Galerkin problem.  > 0: a batch of independent SG
+                             * problems in one handle (exclusive with n_samples): member j has the
+                             * total-degree index set of degree member_degree[j] (chaos_degree is then
+                             * ignored) and the coefficient sum_mu member_scale[j][mu] a_mu, so each
+                             * G_mu is block diagonal over the members.  Modes are numbered member by
+                             * member (member j's modes follow those of members 0..j-1, each in the
+                             * graded order of a single problem).                                       */
+    const int* member_degree;     /* host [n_members] (copied)                                       */
+    const double* member_scale;   /* host [n_members][n_coef_modes] (copied); the mu = 0 entry must be 1 */
     int transpose;          /* 0: the slab operator AA; 1: its transpose AA^T (the adjoint slab
                              * problem).  For an affine coefficient G_mu, M_x, K_mu are symmetric and
                              * B_t is diagonal, so AA^T is AA with A_t replaced by A_t^T; every entry
@@ -183,7 +192,7 @@ sg_status sg_stiffness_form_cells(sg_handle h, int mu_index, const double* coef_
  * grad != NULL, grad = dJ/du for J = w_mean E[Q] + w_var Var[Q] (a device slab vector, nonzero only in
  * time component r on interior DoFs).  Synchronises the stream. */
 sg_status sg_qoi_mean_var(sg_handle h, const double* u, double w_mean, double w_var, double* qoi, double* grad,
-                          void* hip_stream);   /* SG_EUNSUPPORTED for a sample-batch handle */
+                          void* hip_stream);   /* SG_EUNSUPPORTED for sample and member batches */
 
 /* Monte-Carlo estimators over the samples of a handle made with n_samples = N > 1 (Section 5.2, eqs.
  * mc-mean-estimator and mc-variance-estimator-unbiased), per time component and node:
@@ -192,6 +201,14 @@ sg_status sg_qoi_mean_var(sg_handle h, const double* u, double w_mean, double w_
  * u is a device slab vector of the handle; mean and var are device arrays of N_t * n_nodes(0)
  * doubles (var may be NULL).  Two passes over the samples, FP64.  Asynchronous. */
 sg_status sg_sample_statistics(sg_handle h, const double* u, double* mean, double* var, void* hip_stream);
+
+/* Chaos moments of a slab vector (Section 3.1, eqs. qoi-mean-chaos and qoi-variance-chaos): per member j
+ * of the handle (one member for a plain SG handle), time component i and node,
+ *     mean[j][i][node] = u[first mode of j][i][node],
+ *     var[j][i][node]  = sum over the member's other modes alpha of u[alpha][i][node]^2.
+ * mean and var are device arrays of n_members * N_t * n_nodes(0) doubles (var may be NULL).
+ * SG_EINVAL for a sample-batch handle.  Asynchronous. */
+sg_status sg_chaos_moments(sg_handle h, const double* u, double* mean, double* var, void* hip_stream);
 
 /* Message for the last non-OK status returned on the calling thread ("" if none). */
 const char* sg_last_error(void);

@@ -220,6 +220,38 @@ bool build_sample_coupling(int M, int n_samples, const double* xi, int n_mu, con
     return true;
 }
 
+bool build_batch_coupling(int M, int n_members, const int* degrees, const double* scale, int n_mu, const int* mu,
+                          Coupling* out, std::vector<int>* offsets, std::string* err) {
+    out->n_mu = n_mu;
+    out->ptr.assign(1, 0);
+    out->beta.clear();
+    out->w.clear();
+    if (!check_modes(M, n_mu, mu, out, err)) return false;
+    offsets->assign(1, 0);
+    for (int j = 0; j < n_members; ++j) {
+        if (degrees[j] < 0) { *err = "negative member degree"; return false; }
+        if (scale[(size_t)j * n_mu + out->mu0] != 1.0) { *err = "member scale of mu = 0 must be 1"; return false; }
+        const auto idx = total_degree_set(M, degrees[j]);
+        const int off = offsets->back();
+        for (size_t a = 0; a < idx.size(); ++a)
+            for (int k = 0; k < n_mu; ++k) {
+                const double sc = scale[(size_t)j * n_mu + k];
+                for (size_t b = 0; b < idx.size(); ++b) {
+                    double v = sc;
+                    for (int m = 0; m < M && v != 0.0; ++m) v *= hermite_triple_1d(mu[k * M + m], idx[a][m], idx[b][m]);
+                    if (v != 0.0) {
+                        out->beta.push_back(off + (int)b);
+                        out->w.push_back(v);
+                    }
+                }
+                out->ptr.push_back((int)out->beta.size());
+            }
+        offsets->push_back(off + (int)idx.size());
+    }
+    out->n_xi = offsets->back();
+    return true;
+}
+
 bool build_coupling(int M, int p, int n_mu, const int* mu, Coupling* out, std::string* err) {
     auto idx = total_degree_set(M, p);
     const int n_xi = (int)idx.size();

@@ -53,4 +53,11 @@ double hermite_normalized(int n, double x);
 bool build_sample_coupling(int M, int n_samples, const double* xi, int n_mu, const int* mu, Coupling* out,
                            std::string* err);
 
+// A batch of independent stochastic Galerkin problems in one Kronecker form: member j has the
+// total-degree set of degree degrees[j] and the coefficient sum_mu scale[j][mu] a_mu, so G_mu is
+// block diagonal with blocks scale[j][mu] G_mu(Lambda_{p_j}).  Global mode = offsets[j] + local mode;
+// offsets has n_members + 1 entries.  scale[j][mu = 0] must be 1 (the members share the mean field).
+bool build_batch_coupling(int M, int n_members, const int* degrees, const double* scale, int n_mu, const int* mu,
+                          Coupling* out, std::vector<int>* offsets, std::string* err);
+
 }  // namespace sg

@@ -52,6 +52,10 @@ hipError_t launch_cell_dot(int dim, int k, Grid g, int ncomp, const double* lam,
                            hipStream_t s);
 
 // mean[i][node] and unbiased var[i][node] over N sample blocks of a slab vector u[N][nt][nn]
+// mean[j][i][node] = u[off[j]][i][node], var = sum_{off[j] < a < off[j+1]} u[a][i][node]^2
+hipError_t launch_chaos_moments(const double* u, const int* off, int n_members, int nt, long long nn, double* mean,
+                                double* var, hipStream_t s);
+
 hipError_t launch_sample_stats(const double* u, int N, int nt, long long nn, double* mean, double* var,
                                hipStream_t s);
 template <typename T>

@@ -141,6 +141,28 @@ __global__ void __launch_bounds__(256)
 }
 
 
+// Chaos moments per member: mean = the member's first mode, var = sum of squares of its other modes.
+__global__ void __launch_bounds__(256)
+    k_chaos_moments(const double* __restrict__ u, const int* __restrict__ off, int n_members, int nt, long long nn,
+                    double* __restrict__ mean, double* __restrict__ var) {
+    const long long per = (long long)nt * nn;
+    const long long total = (long long)n_members * per;
+    for (long long idx = blockIdx.x * 256LL + threadIdx.x; idx < total; idx += (long long)gridDim.x * 256) {
+        const int j = (int)(idx / per);
+        const long long r = idx % per;
+        const int a0 = off[j], a1 = off[j + 1];
+        mean[idx] = u[(long long)a0 * per + r];
+        if (var) {
+            double q = 0.0;
+            for (int a = a0 + 1; a < a1; ++a) {
+                const double v = u[(long long)a * per + r];
+                q += v * v;
+            }
+            var[idx] = q;
+        }
+    }
+}
+
 // One workgroup per cell: sum of lam * s over the cell's (component, local node) pairs.
 __global__ void __launch_bounds__(256)
     k_cell_dot(int dim, int k, Grid g, int ncomp, const double* __restrict__ lam, const double* __restrict__ s_in,
@@ -394,6 +416,14 @@ hipError_t launch_sample_stats(const double* u, int N, int nt, long long nn, dou
     const long long total = (long long)nt * nn;
     const unsigned blocks = (unsigned)std::min<long long>((total + 255) / 256, 65536);
     hipLaunchKernelGGL(k_sample_stats, dim3(blocks), dim3(256), 0, s, u, N, nt, nn, mean, var);
+    return hipGetLastError();
+}
+
+hipError_t launch_chaos_moments(const double* u, const int* off, int n_members, int nt, long long nn, double* mean,
+                                double* var, hipStream_t s) {
+    const long long total = (long long)n_members * nt * nn;
+    const unsigned blocks = (unsigned)std::min<long long>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_chaos_moments, dim3(blocks), dim3(256), 0, s, u, off, n_members, nt, nn, mean, var);
     return hipGetLastError();
 }
 

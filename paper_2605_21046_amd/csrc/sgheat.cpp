@@ -94,6 +94,10 @@ struct sg_handle_s {
     sg_problem_desc d{};
     std::vector<int> coef_mu;
     std::vector<double> samples;   // sample-batch handles: [n_samples][n_vars]
+    std::vector<int> member_degree;     // member batches: [n_members]
+    std::vector<double> member_scale;   // [n_members][n_mu]
+    std::vector<int> member_off;        // first mode of every member, n_members + 1 entries
+    DevBuf<int> moff;                   // member_off on the device
     int NP = 0, NT = 0, n_xi = 0, n_mu = 0, npp = 0;
     Coupling cpl;
     bool mixed = false;
@@ -171,6 +175,9 @@ sg_status validate(const sg_problem_desc* d) {
     if (d->precision != SG_FP64 && d->precision != SG_MIXED) return fail(SG_EINVAL, "unknown precision");
     if (d->transpose != 0 && d->transpose != 1) return fail(SG_EINVAL, "transpose must be 0 or 1");
     if (d->n_samples < 0 || (d->n_samples > 0 && !d->samples)) return fail(SG_EINVAL, "samples missing");
+    if (d->n_members < 0 || (d->n_members > 0 && (!d->member_degree || !d->member_scale)))
+        return fail(SG_EINVAL, "member_degree / member_scale missing");
+    if (d->n_members > 0 && d->n_samples > 0) return fail(SG_EINVAL, "n_samples and n_members are exclusive");
     return SG_OK;
 }
 
@@ -398,11 +405,19 @@ sg_status build(sg_handle h) {
     h->NT = d.time_degree + 1;
     h->mixed = d.precision == SG_MIXED;
     std::string err;
-    const bool ok = d.n_samples > 0
-                        ? build_sample_coupling(d.n_vars, d.n_samples, h->samples.data(), d.n_coef_modes,
-                                                h->coef_mu.data(), &h->cpl, &err)
-                        : build_coupling(d.n_vars, d.chaos_degree, d.n_coef_modes, h->coef_mu.data(), &h->cpl, &err);
+    bool ok;
+    if (d.n_samples > 0) {
+        ok = build_sample_coupling(d.n_vars, d.n_samples, h->samples.data(), d.n_coef_modes, h->coef_mu.data(),
+                                   &h->cpl, &err);
+    } else if (d.n_members > 0) {
+        ok = build_batch_coupling(d.n_vars, d.n_members, h->member_degree.data(), h->member_scale.data(),
+                                  d.n_coef_modes, h->coef_mu.data(), &h->cpl, &h->member_off, &err);
+    } else {
+        ok = build_coupling(d.n_vars, d.chaos_degree, d.n_coef_modes, h->coef_mu.data(), &h->cpl, &err);
+        h->member_off = {0, h->cpl.n_xi};
+    }
     if (!ok) return fail(SG_EINVAL, err);
+    if (d.n_samples == 0) SG_TRY(h->moff.upload(h->member_off.data(), h->member_off.size(), "member offsets"));
     h->n_xi = h->cpl.n_xi;
     h->n_mu = d.n_coef_modes;
     h->npp = h->NT * h->NP;
@@ -653,7 +668,8 @@ ApplyOp<T> make_op(const sg_handle h, int level, bool full) {
     }
     op.mean = !full;
     op.n_ent = full ? (int)h->cpl.beta.size() : h->n_xi;
-    op.affine = h->cpl.affine && h->d.n_vars <= 8 && h->d.n_samples == 0;   // Hermite tables only
+    // compile-time Hermite tables describe a single total-degree problem only
+    op.affine = h->cpl.affine && h->d.n_vars <= 8 && h->d.n_samples == 0 && h->d.n_members == 0;
     op.chaos_m = h->d.n_vars;
     op.chaos_p = h->d.chaos_degree;
     op.mu0 = h->cpl.mu0;
@@ -861,6 +877,12 @@ sg_status sg_create(const sg_problem_desc* desc, sg_handle* out) {
     h->d.coef_mu = h->coef_mu.data();
     if (desc->n_samples > 0) h->samples.assign(desc->samples, desc->samples + (size_t)desc->n_samples * desc->n_vars);
     h->d.samples = nullptr;   // host array not retained
+    if (desc->n_members > 0) {
+        h->member_degree.assign(desc->member_degree, desc->member_degree + desc->n_members);
+        h->member_scale.assign(desc->member_scale, desc->member_scale + (size_t)desc->n_members * desc->n_coef_modes);
+    }
+    h->d.member_degree = nullptr;
+    h->d.member_scale = nullptr;
     try {
         sg_status s = build(h.get());
         h->d.coef_qp = nullptr;   // host array not retained
@@ -1111,7 +1133,8 @@ sg_status sg_stiffness_form_cells(sg_handle h, int mu_index, const double* coef_
 sg_status sg_qoi_mean_var(sg_handle h, const double* u, double w_mean, double w_var, double* qoi, double* grad,
                           void* hip_stream) {
     if (!h || !u || !qoi) return fail(SG_EINVAL, "null argument");
-    if (h->d.n_samples > 0) return fail(SG_EUNSUPPORTED, "the chaos QoI needs a stochastic Galerkin handle");
+    if (h->d.n_samples > 0 || h->d.n_members > 0)
+        return fail(SG_EUNSUPPORTED, "the chaos QoI needs a single stochastic Galerkin problem");
     if (grad && overlap(u, grad, h->N * sizeof(double))) return fail(SG_EINVAL, "u and grad overlap");
     hipStream_t s = (hipStream_t)hip_stream;
     const int nx = h->n_xi, NT = h->NT, r = NT - 1;
@@ -1197,6 +1220,14 @@ sg_status sg_sample_statistics(sg_handle h, const double* u, double* mean, doubl
     if (!h || !u || !mean) return fail(SG_EINVAL, "null argument");
     if (h->d.n_samples < 1) return fail(SG_EINVAL, "not a sample-batch handle");
     SG_HIP(launch_sample_stats(u, h->d.n_samples, h->NT, h->lv[0].g.n_nodes, mean, var, (hipStream_t)hip_stream));
+    return SG_OK;
+}
+
+sg_status sg_chaos_moments(sg_handle h, const double* u, double* mean, double* var, void* hip_stream) {
+    if (!h || !u || !mean) return fail(SG_EINVAL, "null argument");
+    if (h->d.n_samples > 0) return fail(SG_EINVAL, "a sample-batch handle has no chaos modes");
+    SG_HIP(launch_chaos_moments(u, h->moff.p, (int)h->member_off.size() - 1, h->NT, h->lv[0].g.n_nodes, mean, var,
+                                (hipStream_t)hip_stream));
     return SG_OK;
 }
 

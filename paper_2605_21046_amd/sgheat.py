@@ -20,7 +20,7 @@ _STATUS = {0: "SG_OK", 1: "SG_NOT_CONVERGED", -1: "SG_EINVAL", -2: "SG_ENOMEM", 
            -4: "SG_ESINGULAR", -5: "SG_EUNSUPPORTED"}
 EXPORTS = ["sg_create", "sg_destroy", "sg_vector_length", "sg_operator_apply", "sg_vanka_smooth",
            "gmg_vcycle", "fgmres_solve_slab", "sg_quadrature_points", "sg_node_coordinates", "sg_update_coefficients", "sg_operator_apply_T",
-           "sg_slab_transfer", "sg_stiffness_form_cells", "sg_qoi_mean_var", "sg_sample_statistics", "sg_last_error"]
+           "sg_slab_transfer", "sg_stiffness_form_cells", "sg_qoi_mean_var", "sg_sample_statistics", "sg_chaos_moments", "sg_last_error"]
 
 
 class SgError(RuntimeError):
@@ -37,7 +37,9 @@ class ProblemDesc(ctypes.Structure):
                 ("coef_qp", ctypes.POINTER(ctypes.c_double)), ("n_levels", ctypes.c_int),
                 ("pre_smooth", ctypes.c_int), ("post_smooth", ctypes.c_int), ("vanka_omega", ctypes.c_double),
                 ("fgmres_restart", ctypes.c_int), ("precision", ctypes.c_int), ("n_samples", ctypes.c_int),
-                ("samples", ctypes.POINTER(ctypes.c_double)), ("transpose", ctypes.c_int)]
+                ("samples", ctypes.POINTER(ctypes.c_double)), ("n_members", ctypes.c_int),
+                ("member_degree", ctypes.POINTER(ctypes.c_int)), ("member_scale", ctypes.POINTER(ctypes.c_double)),
+                ("transpose", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -70,6 +72,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sg_stiffness_form_cells.argtypes = [P, I, ctypes.POINTER(ctypes.c_double), V, V, V, V]
     lib.sg_qoi_mean_var.argtypes = [P, V, D, D, ctypes.POINTER(ctypes.c_double), V, V]
     lib.sg_sample_statistics.argtypes = [P, V, V, V, V]
+    lib.sg_chaos_moments.argtypes = [P, V, V, V, V]
     lib.sg_last_error.restype = ctypes.c_char_p
     for f in EXPORTS:
         if f != "sg_last_error":
@@ -160,9 +163,11 @@ def _stream(stream):
 class Problem:
     """One slab problem on the GPU (a handle of libsgheat.so)."""
 
-    def __init__(self, spec, coef_mu, coef_qp_levels, precision=SG_FP64, samples=None):
+    def __init__(self, spec, coef_mu, coef_qp_levels, precision=SG_FP64, samples=None, members=None):
         """samples: None for the stochastic Galerkin operator, or [n_samples, n_vars] points xi^(s) for a
-        batch of pathwise problems (block s = the deterministic slab system at a(x, xi^(s)))."""
+        batch of pathwise problems (block s = the deterministic slab system at a(x, xi^(s))).
+        members: None, or (degrees [J], scales [J, n_coef_modes]) for a batch of J independent SG
+        problems (member j: total degree degrees[j], coefficient sum_mu scales[j, mu] a_mu)."""
         self.spec = spec
         mus = np.ascontiguousarray(np.asarray(coef_mu, dtype=np.int32).reshape(-1, spec.n_vars))
         coef = np.ascontiguousarray(np.concatenate([np.asarray(c, np.float64).reshape(-1) for c in coef_qp_levels]))
@@ -176,6 +181,15 @@ class Problem:
             d.n_samples = xi.shape[0]
             d.samples = xi.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             n_modes = xi.shape[0]
+        self.member_modes = [n_modes]
+        if members is not None:
+            deg = np.ascontiguousarray(np.asarray(members[0], dtype=np.int32).reshape(-1))
+            sc = np.ascontiguousarray(np.asarray(members[1], dtype=np.float64).reshape(deg.size, mus.shape[0]))
+            d.n_members = deg.size
+            d.member_degree = deg.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+            d.member_scale = sc.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            self.member_modes = [math_comb(spec.n_vars + int(p), int(p)) for p in deg]
+            n_modes = sum(self.member_modes)
         h = ctypes.c_void_p()
         _check(_lib.sg_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -260,6 +274,18 @@ class Problem:
             mean = torch.empty(m, dtype=torch.float64, device=u.device)
         v = _ptr(var, m, "var") if var is not None else None
         _check(_lib.sg_sample_statistics(self._h, _ptr(u, n, "u"), _ptr(mean, m, "mean"), v, _stream(stream)))
+        return mean, var
+
+    def chaos_moments(self, u, mean=None, var=None, stream=None):
+        """Per member: mean (first mode) and variance (sum of squares of the other modes), each
+        [n_members * N_t * n_nodes] (var optional)."""
+        import torch
+        n = self.n(0)
+        m = len(self.member_modes) * self.shape[1] * self.shape[2]
+        if mean is None:
+            mean = torch.empty(m, dtype=torch.float64, device=u.device)
+        v = _ptr(var, m, "var") if var is not None else None
+        _check(_lib.sg_chaos_moments(self._h, _ptr(u, n, "u"), _ptr(mean, m, "mean"), v, _stream(stream)))
         return mean, var
 
     def vanka_smooth(self, level, b, x, sweeps=1, stream=None):

@@ -99,9 +99,13 @@ def coefficient_modes(w: Workload, x: np.ndarray):
     Returns ``(mu_list, values)`` with ``values[k]`` = a_{mu_k}(x).  The first mode is mu = 0.
     * "c1":   a = 1 + 0.1 xi_1 sin(pi x) sin(pi y) + 0.05 xi_2 sin(2 pi x) sin(pi y)
     * "sine": a = 1 + sum_m (0.1 / m^2) xi_m phi_m(x)
+    * "finite": the non-affine coefficient of the finite-chaos benchmark (M = 4, d = 2), see
+      finite_chaos_coefficient_modes.
     """
     x = np.asarray(x, dtype=np.float64)
     M = w.n_vars
+    if w.field == "finite":
+        return finite_chaos_coefficient_modes(x)
     mus = [tuple([0] * M)]
     vals = [np.ones(x.shape[:-1])]
     for m in range(1, M + 1):
@@ -121,6 +125,79 @@ def coefficient_modes(w: Workload, x: np.ndarray):
             raise ValueError(f"unknown field {w.field}")
         vals.append(v)
     return mus, np.stack(vals)
+
+
+# Finite-chaos benchmark (Section 3.2, eqs. diffusion_benchmark and finite-exact-solution-M4-q6):
+# D = (-1, 1)^2, T = 1, M = 4, a = d_min + (xi_1 x_1^2 + xi_2 x_1 x_2 + xi_3 x_2^2 + xi_4)^2,
+# u = phi(x, t) G_q(xi), phi = t^4 sin(pi (x_1 + 1) / 2) sin(pi (x_2 + 1) / 2),
+# G_q = sum_{|alpha| <= q} c_alpha Psi_alpha, c_0 = 1, c_alpha = eta^|alpha|.
+FINITE_D_MIN = 0.2
+FINITE_ETA = 0.35
+FINITE_Q = 6
+
+
+def _finite_shapes(x: np.ndarray) -> list:
+    """g_1..g_4 = x_1^2, x_1 x_2, x_2^2, 1: a = d_min + (sum_k xi_k g_k)^2."""
+    x1, x2 = x[..., 0], x[..., 1]
+    return [x1 * x1, x1 * x2, x2 * x2, np.ones_like(x1)]
+
+
+def finite_chaos_coefficient_modes(x: np.ndarray):
+    """Hermite modes of a = d_min + (sum_k xi_k g_k)^2 at points x [..., 2]: 11 modes.
+
+    With xi_k^2 = sqrt(2) Psi_{2 e_k} + 1 and xi_k xi_l = Psi_{e_k + e_l} (k != l):
+        a_0 = d_min + sum_k g_k^2,  a_{2 e_k} = sqrt(2) g_k^2,  a_{e_k + e_l} = 2 g_k g_l.
+    """
+    g = _finite_shapes(np.asarray(x, dtype=np.float64))
+    mus = [(0, 0, 0, 0)]
+    vals = [FINITE_D_MIN + sum(gk * gk for gk in g)]
+    for k in range(4):
+        mu = [0] * 4
+        mu[k] = 2
+        mus.append(tuple(mu))
+        vals.append(math.sqrt(2.0) * g[k] * g[k])
+    for k in range(4):
+        for l in range(k + 1, 4):
+            mu = [0] * 4
+            mu[k] = mu[l] = 1
+            mus.append(tuple(mu))
+            vals.append(2.0 * g[k] * g[l])
+    return mus, np.stack(vals)
+
+
+def finite_chaos_coefficient_at(x: np.ndarray, xi: np.ndarray) -> np.ndarray:
+    """a(x, xi) = d_min + (sum_k xi_k g_k(x))^2 at points x [..., 2] for one sample xi [4]."""
+    g = _finite_shapes(np.asarray(x, dtype=np.float64))
+    s = sum(float(xi[k]) * g[k] for k in range(4))
+    return FINITE_D_MIN + s * s
+
+
+def finite_chaos_phi(x: np.ndarray) -> tuple:
+    """Spatial factor sin(pi (x_1 + 1) / 2) sin(pi (x_2 + 1) / 2) and its gradient [..., 2]."""
+    x = np.asarray(x, dtype=np.float64)
+    h = 0.5 * math.pi
+    s1, s2 = np.sin(h * (x[..., 0] + 1)), np.sin(h * (x[..., 1] + 1))
+    c1, c2 = np.cos(h * (x[..., 0] + 1)), np.cos(h * (x[..., 1] + 1))
+    return s1 * s2, np.stack([h * c1 * s2, h * s1 * c2], axis=-1)
+
+
+@dataclass(frozen=True)
+class FiniteChaosWorkload:
+    """The finite-chaos benchmark discretised with ``base`` (dim 2, domain (-1, 1)^2, field "finite",
+    tau = T / n_slabs) at stochastic degree ``base.chaos_degree``."""
+    base: Workload
+    n_slabs: int
+
+    def c_alpha(self, alpha) -> float:
+        n = sum(alpha)
+        return 0.0 if n > FINITE_Q else (1.0 if n == 0 else FINITE_ETA ** n)
+
+
+def finite_chaos_workload(n_cells_1d: int, fe_degree: int, time_degree: int, n_slabs: int, p_xi: int,
+                          n_levels: int) -> FiniteChaosWorkload:
+    w = Workload(f"fc{n_cells_1d}q{fe_degree}r{time_degree}p{p_xi}", 2, n_cells_1d, fe_degree, time_degree,
+                 1.0 / n_slabs, 4, p_xi, n_levels, "finite", lo=-1.0, hi=1.0)
+    return FiniteChaosWorkload(w, n_slabs)
 
 
 def uniform_vector(n: int, seed: int) -> np.ndarray:
@@ -265,4 +342,41 @@ SAMPLE_WORKLOADS = {
     "m2": SampleWorkload(Workload("m2", 2, 4, 2, 1, 0.02, 2, 0, 2, "c1"), 12, 3, seed=5),
     "m3": SampleWorkload(Workload("m3", 3, 2, 2, 1, 0.02, 3, 0, 1, "sine"), 5, 2, seed=6),
     "m2q3": SampleWorkload(Workload("m2q3", 2, 4, 3, 2, 0.02, 2, 0, 2, "sine"), 7, 2, seed=7),
+}
+
+
+SEED_MEMBER_SCALES = 8
+
+
+@dataclass(frozen=True)
+class MemberWorkload:
+    """A batch of independent stochastic Galerkin problems sharing the mesh, the time discretisation
+    and the mean coefficient: member j has total degree ``degrees[j]`` and the coefficient
+    a_0 + sum_m s_{j,m} a_{e_m} xi_m with s_{j,m} ~ U[0.5, 1.5] (PCG64 stream ``seed``); the slab
+    sequence of ``base`` (``n_slabs`` slabs, u_0 = prod_k sin(pi x_k) in the mean mode, no forcing)."""
+    base: Workload
+    degrees: tuple
+    n_slabs: int
+    seed: int = SEED_MEMBER_SCALES
+
+    def scales(self, coef_mu) -> np.ndarray:
+        """[n_members, n_coef_modes]: 1 for mu = 0, the member's factor s_{j,m} for mu = e_m."""
+        g = np.random.Generator(np.random.PCG64(self.seed))
+        s = g.uniform(0.5, 1.5, size=(len(self.degrees), self.base.n_vars))
+        out = np.ones((len(self.degrees), len(coef_mu)))
+        for k, mu in enumerate(coef_mu):
+            if sum(mu) == 1:
+                out[:, k] = s[:, int(np.argmax(mu))]
+            elif sum(mu) > 1:
+                raise ValueError("member scales are defined for affine coefficients")
+        return out
+
+
+MEMBER_WORKLOADS = {
+    # 64 SG problems, 16 each of degree 1, 2, 3, 4 (3 / 6 / 10 / 15 modes), on the 64^2-cell Q2 mesh
+    # of the sample batch, dG(1), tau = 0.01, 20 slabs, 4-level GMG
+    "c4": MemberWorkload(Workload("c4sg", 2, 64, 2, 1, 0.01, 2, 0, 4, "c1"), (1,) * 16 + (2,) * 16 + (3,) * 16 + (4,) * 16, 20),
+    # small cases for the tests
+    "b2": MemberWorkload(Workload("b2", 2, 4, 2, 1, 0.02, 2, 0, 2, "c1"), (1, 2, 3, 0, 2), 3, seed=9),
+    "b3": MemberWorkload(Workload("b3", 3, 2, 2, 1, 0.02, 3, 0, 1, "sine"), (1, 2), 2, seed=10),
 }
