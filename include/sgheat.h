@@ -44,7 +44,7 @@ typedef enum {
     SG_ENOMEM = -2,         /* device or host allocation failed */
     SG_EHIP = -3,           /* a HIP runtime call failed; the message names it */
     SG_ESINGULAR = -4,      /* a Vanka patch matrix or the coarsest-level matrix is singular */
-    SG_EUNSUPPORTED = -5    /* valid request this build does not implement (e.g. non-affine preconditioner) */
+    SG_EUNSUPPORTED = -5    /* valid request this build does not implement (e.g. too many components per cell) */
 } sg_status;
 
 typedef enum {
@@ -88,8 +88,8 @@ typedef struct {
     const int* member_degree;     /* host [n_members] (copied)                                       */
     const double* member_scale;   /* host [n_members][n_coef_modes] (copied); the mu = 0 entry must be 1 */
     int transpose;          /* 0: the slab operator AA; 1: its transpose AA^T (the adjoint slab
-                             * problem).  For an affine coefficient G_mu, M_x, K_mu are symmetric and
-                             * B_t is diagonal, so AA^T is AA with A_t replaced by A_t^T; every entry
+                             * problem).  Every G_mu (a triple-product matrix), M_x and K_mu is symmetric
+                             * and B_t is diagonal, so AA^T is AA with A_t replaced by A_t^T; every entry
                              * point of the handle (apply, Vanka, V-cycle, FGMRES) then acts on AA^T. */
 } sg_problem_desc;
 
@@ -129,8 +129,9 @@ sg_status sg_operator_apply(sg_handle h, const double* x, double* y, void* hip_s
 sg_status sg_vanka_smooth(sg_handle h, int level, const double* b, double* x, int sweeps, void* hip_stream);
 
 /* z = one V-cycle for (I_xi (x) A_0) z = r: the stochastic block-Jacobi preconditioner with the
- * mean-based diagonal block (every diagonal block equals A_0 for an affine coefficient).
- * Requires an affine coefficient set (mu in {0, e_1..e_M}), else SG_EUNSUPPORTED at create.
+ * mean-based diagonal block (every diagonal block equals A_0 for an affine coefficient; for a
+ * non-affine coefficient set, such as the finite-chaos benchmark's, the diagonal blocks differ and A_0
+ * stands in for all of them, so FGMRES needs more iterations but converges to the same solution).
  * FP64 interface; FP32 inside with SG_MIXED.  Asynchronous on the stream. */
 sg_status gmg_vcycle(sg_handle h, const double* r, double* z, void* hip_stream);
 
@@ -209,6 +210,58 @@ sg_status sg_sample_statistics(sg_handle h, const double* u, double* mean, doubl
  * mean and var are device arrays of n_members * N_t * n_nodes(0) doubles (var may be NULL).
  * SG_EINVAL for a sample-batch handle.  Asynchronous. */
 sg_status sg_chaos_moments(sg_handle h, const double* u, double* mean, double* var, void* hip_stream);
+
+/* ---- Prescribed solutions and their forcing (Section 3.2, the finite-chaos benchmark; eqs.
+ * load_vector, finite_rhs_factorized, and the error quantities of Definition
+ * def:error-norms-and-quantities).  These let a caller march a slab sequence with a forcing term
+ * F^(n) and measure the error against a separable exact solution u = theta(t) s(x) sum_a c_a Psi_a. */
+
+/* Physical points of the nq1-point Gauss rule per direction on every cell of a level,
+ * [n_cells][nq1^d][d] (cells and points lexicographic, x fastest).  Host only. */
+sg_status sg_gauss_points(const sg_problem_desc* desc, int level, int nq1, double* xyz);
+
+/* The handle's chaos index set, alpha[N_xi][n_vars], in the order of the modes of a slab vector
+ * (total degree, graded).  Single stochastic Galerkin handles only.  Host only. */
+sg_status sg_index_set(sg_handle h, int* alpha);
+
+/* Galerkin projection weights of the product of the coefficient modes with a given chaos expansion
+ * (eq. triple_stoch): out[mu][beta] = sum_s src_c[s] E[Psi_mu Psi_{src_alpha[s]} Psi_beta] for the
+ * handle's coefficient modes mu and modes beta.  With src = the exact solution's chaos coefficients,
+ * sum_mu out[mu][beta] a_mu is E[a G Psi_beta], the factor of the projected forcing f_beta.  Host only. */
+sg_status sg_chaos_projection(sg_handle h, int n_src, const int* src_alpha, const double* src_c, double* out);
+
+/* The ntq-point Gauss rule of one slab: reference points s[k] in (0, 1) and weights w[k] (times tau).
+ * Host only. */
+sg_status sg_time_rule(sg_handle h, int ntq, double* s, double* w);
+
+/* Time loads of n_g functions g given at that rule's points of a slab: out[g][i] = int_{I_n} g v_i dt
+ * (v_i the right-Radau nodal basis), gvals [n_g][ntq].  Host only. */
+sg_status sg_time_load_weights(sg_handle h, int ntq, int n_g, const double* gvals, double* out);
+
+/* Spatial load vectors on the finest level: out[f][j] = sum_K sum_q w_q |K| (fval[f][K][q] psi_j(x_q)
+ * + sum_e fgrad[f][K][q][e] d_e psi_j(x_q)) at the nq1-point Gauss rule (points as sg_gauss_points),
+ * Dirichlet entries 0.  fval [n_fields][n_cells][nq1^d] and fgrad [n_fields][n_cells][nq1^d][d] are device
+ * arrays (either may be NULL), out a device array [n_fields][n_nodes(0)].  Asynchronous. */
+sg_status sg_load_vectors(sg_handle h, int nq1, int n_fields, const double* fval, const double* fgrad, double* out,
+                          void* hip_stream);
+
+/* Separable slab vector: y[alpha][i][node] = beta * y + sum_t W[t][alpha][i] V[t][node] (a load vector
+ * F^(n) = sum_t (chaos x time weights) (x) spatial load).  W host [n_terms][N_xi][N_t] (copied; the call
+ * waits for the stream first), V device [n_terms][n_nodes(0)], y a device slab vector. */
+sg_status sg_separable_vector(sg_handle h, int n_terms, const double* W, const double* V, double beta, double* y,
+                              void* hip_stream);
+
+/* Error sums of one slab vector u against u_ex = theta(t) s(x) sum_a c[a] Psi_a on that slab, by the
+ * nq1-point Gauss rule per space direction and the ntq-point rule in time (sg_time_rule):
+ *   out[0] = sum_a |c_a theta s - u_a|^2,  out[1] = the same for the gradients,
+ *   out[2], out[3] = the a = 0 terms alone (mean error),
+ *   out[4] = |C2 theta^2 s^2 - sum_{a != 0} u_a^2|^2, out[5] = the same for the gradients (variance error),
+ *   out[6] = |theta s|^2, out[7] = |theta grad s|^2,
+ * each integrated over the slab and D.  s_qp [n_cells][nq1^d], gs_qp [n_cells][nq1^d][d] are device
+ * arrays; theta [ntq] and c [N_xi] host arrays; C2 = sum of c^2 over the exact solution's nonzero modes.
+ * Single SG handles; 2D k <= 4 or 3D k <= 2.  Synchronous. */
+sg_status sg_separable_error(sg_handle h, const double* u, int nq1, const double* s_qp, const double* gs_qp, int ntq,
+                             const double* theta, const double* c, double C2, double* out, void* hip_stream);
 
 /* Message for the last non-OK status returned on the calling thread ("" if none). */
 const char* sg_last_error(void);

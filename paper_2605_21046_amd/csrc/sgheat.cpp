@@ -127,6 +127,7 @@ struct sg_handle_s {
     Tables<double> tabT64{};
     DevBuf<double> zcoef, fcoef, qpart, qout, qC;
     DevBuf<double> elem_E, elem_M;             // element matrices of the patch set-up (reused)
+    DevBuf<double> sepW, errC, errPart, errOut;  // separable weights, error-sum work arrays
     std::vector<double> hstage;
     std::vector<double> trip;                 // E[Psi_a Psi_b Psi_eps], [n_xi][n_xi][n_eps]
     int n_eps = 0;
@@ -422,11 +423,9 @@ sg_status build(sg_handle h) {
     h->n_mu = d.n_coef_modes;
     h->npp = h->NT * h->NP;
     if (h->n_xi * h->NT * 1 > 512) return fail(SG_EUNSUPPORTED, "N_xi * N_t must be <= 512");
-    if (!h->cpl.affine)
-        return fail(SG_EUNSUPPORTED, "the block-Jacobi preconditioner needs an affine coefficient (mu in {0, e_m})");
     if (h->npp > 256) return fail(SG_EUNSUPPORTED, "Vanka patches larger than 256 DoFs are not supported");
     {
-        const size_t n_ent_max = (size_t)h->n_xi * (2 * d.n_vars + 1) * 4;
+        const size_t n_ent_max = h->cpl.beta.size();
         const size_t lds_apply = (size_t)(h->n_xi * h->NT + h->n_mu) * h->NP * sizeof(double) + n_ent_max * 16;
         const size_t lds_vanka = vanka_lds_bytes(h->npp, sizeof(double));
         if (lds_apply > 160 * 1024 || lds_vanka > 160 * 1024)
@@ -1193,17 +1192,18 @@ sg_status sg_qoi_mean_var(sg_handle h, const double* u, double w_mean, double w_
     return SG_OK;
 }
 
-sg_status sg_quadrature_points(const sg_problem_desc* d, int level, double* xyz) {
+sg_status sg_gauss_points(const sg_problem_desc* d, int level, int nq1, double* xyz) {
     if (!d || !xyz) return fail(SG_EINVAL, "null argument");
     if (d->dim != 2 && d->dim != 3) return fail(SG_EINVAL, "dim must be 2 or 3");
     if (d->fe_degree < 1 || d->fe_degree > 4 || d->n_cells_1d < 1) return fail(SG_EINVAL, "bad mesh");
+    if (nq1 < 1 || nq1 > kMaxQ1) return fail(SG_EINVAL, "nq1 must be in 1..8");
     if (level < 0 || (d->n_cells_1d >> level) < 1 || (d->n_cells_1d % (1 << level)) != 0)
         return fail(SG_EINVAL, "level out of range");
-    const int n = d->n_cells_1d >> level, N1 = d->fe_degree + 1, dim = d->dim;
+    const int n = d->n_cells_1d >> level, dim = d->dim;
     const double h = (d->hi - d->lo) / n;
     std::vector<double> gw;
-    const std::vector<double> gq = gauss_points(N1, &gw);
-    const int NP = ipow_h(N1, dim);
+    const std::vector<double> gq = gauss_points(nq1, &gw);
+    const int NP = ipow_h(nq1, dim);
     long long ncell = 1;
     for (int i = 0; i < dim; ++i) ncell *= n;
     for (long long c = 0; c < ncell; ++c) {
@@ -1211,8 +1211,155 @@ sg_status sg_quadrature_points(const sg_problem_desc* d, int level, double* xyz)
         long long r = c;
         for (int i = 0; i < dim; ++i) { cc[i] = r % n; r /= n; }
         for (int q = 0; q < NP; ++q)
-            for (int i = 0, qq = q; i < dim; ++i, qq /= N1) xyz[(c * NP + q) * dim + i] = d->lo + h * (cc[i] + gq[qq % N1]);
+            for (int i = 0, qq = q; i < dim; ++i, qq /= nq1) xyz[(c * NP + q) * dim + i] = d->lo + h * (cc[i] + gq[qq % nq1]);
     }
+    return SG_OK;
+}
+
+sg_status sg_quadrature_points(const sg_problem_desc* d, int level, double* xyz) {
+    if (!d) return fail(SG_EINVAL, "null argument");
+    return sg_gauss_points(d, level, d->fe_degree + 1, xyz);
+}
+
+sg_status sg_index_set(sg_handle h, int* alpha) {
+    if (!h || !alpha) return fail(SG_EINVAL, "null argument");
+    if (h->d.n_samples > 0 || h->d.n_members > 0) return fail(SG_EINVAL, "needs a single stochastic Galerkin problem");
+    const auto idx = total_degree_set(h->d.n_vars, h->d.chaos_degree);
+    for (size_t a = 0; a < idx.size(); ++a)
+        for (int m = 0; m < h->d.n_vars; ++m) alpha[a * h->d.n_vars + m] = idx[a][m];
+    return SG_OK;
+}
+
+sg_status sg_chaos_projection(sg_handle h, int n_src, const int* src_alpha, const double* src_c, double* out) {
+    if (!h || (n_src > 0 && (!src_alpha || !src_c)) || !out || n_src < 0) return fail(SG_EINVAL, "bad argument");
+    if (h->d.n_samples > 0 || h->d.n_members > 0) return fail(SG_EINVAL, "needs a single stochastic Galerkin problem");
+    const int M = h->d.n_vars;
+    const auto idx = total_degree_set(M, h->d.chaos_degree);
+    for (int k = 0; k < h->n_mu; ++k)
+        for (size_t b = 0; b < idx.size(); ++b) {
+            double tot = 0.0;
+            for (int si = 0; si < n_src; ++si) {
+                double v = src_c[si];
+                for (int m = 0; m < M && v != 0.0; ++m)
+                    v *= hermite_triple_1d(h->coef_mu[(size_t)k * M + m], src_alpha[(size_t)si * M + m], idx[b][m]);
+                tot += v;
+            }
+            out[(size_t)k * idx.size() + b] = tot;
+        }
+    return SG_OK;
+}
+
+sg_status sg_time_rule(sg_handle h, int ntq, double* s, double* w) {
+    if (!h || !s || !w) return fail(SG_EINVAL, "null argument");
+    if (ntq < 1 || ntq > kMaxTimeQ) return fail(SG_EINVAL, "ntq must be in 1..8");
+    std::vector<double> gw;
+    const std::vector<double> gq = gauss_points(ntq, &gw);
+    for (int k = 0; k < ntq; ++k) {
+        s[k] = gq[k];
+        w[k] = gw[k] * h->d.tau;
+    }
+    return SG_OK;
+}
+
+sg_status sg_time_load_weights(sg_handle h, int ntq, int n_g, const double* gvals, double* out) {
+    if (!h || !gvals || !out) return fail(SG_EINVAL, "null argument");
+    if (ntq < 1 || ntq > kMaxTimeQ || n_g < 0) return fail(SG_EINVAL, "ntq must be in 1..8");
+    std::vector<double> gw;
+    const std::vector<double> gq = gauss_points(ntq, &gw);
+    const std::vector<double> tn = right_radau_points(h->d.time_degree);
+    for (int g = 0; g < n_g; ++g)
+        for (int i = 0; i < h->NT; ++i) {
+            double acc = 0.0;
+            for (int k = 0; k < ntq; ++k) acc += gw[k] * h->d.tau * gvals[(size_t)g * ntq + k] * lagrange_value(tn, i, gq[k]);
+            out[(size_t)g * h->NT + i] = acc;
+        }
+    return SG_OK;
+}
+
+namespace {
+QTables make_qtables(int k, int nq1) {
+    QTables tb{};
+    std::vector<double> gw;
+    const std::vector<double> gq = gauss_points(nq1, &gw);
+    const std::vector<double> gll = gll_points(k);
+    for (int q = 0; q < nq1; ++q) {
+        tb.w[q] = gw[q];
+        for (int a = 0; a <= k; ++a) {
+            tb.V[q][a] = lagrange_value(gll, a, gq[q]);
+            tb.D[q][a] = lagrange_deriv(gll, a, gq[q]);
+        }
+    }
+    return tb;
+}
+}  // namespace
+
+sg_status sg_load_vectors(sg_handle h, int nq1, int n_fields, const double* fval, const double* fgrad, double* out,
+                          void* hip_stream) {
+    if (!h || !out || n_fields < 0) return fail(SG_EINVAL, "bad argument");
+    if (nq1 < 1 || nq1 > kMaxQ1) return fail(SG_EINVAL, "nq1 must be in 1..8");
+    if (n_fields == 0) return SG_OK;
+    const hipStream_t s = (hipStream_t)hip_stream;
+    const Level& l0 = h->lv[0];
+    const QTables tb = make_qtables(h->d.fe_degree, nq1);
+    const int cap = h->n_xi * h->NT;          // fields per pass through the broken-node buffer
+    const long long nq = ipow_h(nq1, h->d.dim);
+    for (int f0 = 0; f0 < n_fields; f0 += cap) {
+        const int nf = std::min(cap, n_fields - f0);
+        const long long off = (long long)f0 * l0.g.n_cells * nq;
+        SG_HIP(launch_load_cells(h->d.dim, h->d.fe_degree, l0.g, nq1, tb, l0.h, fval ? fval + off : nullptr,
+                                 fgrad ? fgrad + off * h->d.dim : nullptr, nf, h->sbuf.p, s));
+        SG_HIP(launch_node_gather<double>(GATHER_INTERIOR, h->d.dim, h->d.fe_degree, l0.g, nf, h->sbuf.p, nullptr,
+                                          nullptr, out + (long long)f0 * l0.g.n_nodes, 0.0, s));
+    }
+    return SG_OK;
+}
+
+sg_status sg_separable_vector(sg_handle h, int n_terms, const double* W, const double* V, double beta, double* y,
+                              void* hip_stream) {
+    if (!h || !y || n_terms < 0 || (n_terms > 0 && (!W || !V))) return fail(SG_EINVAL, "bad argument");
+    const hipStream_t s = (hipStream_t)hip_stream;
+    const size_t nw = (size_t)std::max(n_terms, 1) * h->n_xi * h->NT;
+    SG_TRY(h->sepW.alloc(nw, "separable weights"));
+    SG_HIP(hipStreamSynchronize(s));            // the previous call's kernel may still read sepW
+    if (n_terms > 0) SG_HIP(hipMemcpy(h->sepW.p, W, sizeof(double) * n_terms * h->n_xi * h->NT, hipMemcpyHostToDevice));
+    SG_HIP(launch_separable(n_terms, h->n_xi * h->NT, h->lv[0].g.n_nodes, h->sepW.p, V, beta, y, s));
+    return SG_OK;
+}
+
+sg_status sg_separable_error(sg_handle h, const double* u, int nq1, const double* s_qp, const double* gs_qp, int ntq,
+                             const double* theta, const double* c, double C2, double* out, void* hip_stream) {
+    if (!h || !u || !s_qp || !gs_qp || !theta || !c || !out) return fail(SG_EINVAL, "null argument");
+    if (nq1 < 1 || nq1 > kMaxQ1 || ntq < 1 || ntq > kMaxTimeQ) return fail(SG_EINVAL, "nq1 and ntq must be in 1..8");
+    if (h->d.n_samples > 0 || h->d.n_members > 0) return fail(SG_EINVAL, "needs a single stochastic Galerkin problem");
+    if (!error_cells_supported(h->d.dim, h->d.fe_degree, h->NT))
+        return fail(SG_EUNSUPPORTED, "error sums: 2D k <= 4 or 3D k <= 2, dG(r) with r <= 3");
+    const size_t lds = (size_t)h->n_xi * h->NT * h->NP * sizeof(double);
+    if (lds > 160 * 1024) return fail(SG_EUNSUPPORTED, "error sums: N_xi * N_t * (k+1)^d values exceed one LDS");
+    const hipStream_t s = (hipStream_t)hip_stream;
+    const Level& l0 = h->lv[0];
+    const QTables tb = make_qtables(h->d.fe_degree, nq1);
+    TimeTables tt{};
+    tt.ntq = ntq;
+    {
+        std::vector<double> gw;
+        const std::vector<double> gq = gauss_points(ntq, &gw);
+        const std::vector<double> tn = right_radau_points(h->d.time_degree);
+        for (int k = 0; k < ntq; ++k) {
+            tt.w[k] = gw[k] * h->d.tau;
+            tt.theta[k] = theta[k];
+            for (int i = 0; i < h->NT; ++i) tt.v[i][k] = lagrange_value(tn, i, gq[k]);
+        }
+    }
+    SG_TRY(h->errC.alloc((size_t)h->n_xi, "error sums"));
+    SG_TRY(h->errPart.alloc((size_t)l0.g.n_cells * 8, "error sums"));
+    SG_TRY(h->errOut.alloc(8, "error sums"));
+    SG_HIP(hipStreamSynchronize(s));
+    SG_HIP(hipMemcpy(h->errC.p, c, sizeof(double) * h->n_xi, hipMemcpyHostToDevice));
+    SG_HIP(launch_error_cells(h->d.dim, h->d.fe_degree, h->NT, l0.g, nq1, tb, l0.h, tt, h->n_xi, u, h->errC.p, C2, s_qp,
+                              gs_qp, h->errPart.p, s));
+    SG_HIP(launch_reduce_partials(h->errPart.p, (int)l0.g.n_cells, 8, h->errOut.p, s));
+    SG_HIP(hipMemcpyAsync(out, h->errOut.p, sizeof(double) * 8, hipMemcpyDeviceToHost, s));
+    SG_HIP(hipStreamSynchronize(s));
     return SG_OK;
 }
 

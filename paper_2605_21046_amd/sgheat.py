@@ -20,7 +20,9 @@ _STATUS = {0: "SG_OK", 1: "SG_NOT_CONVERGED", -1: "SG_EINVAL", -2: "SG_ENOMEM", 
            -4: "SG_ESINGULAR", -5: "SG_EUNSUPPORTED"}
 EXPORTS = ["sg_create", "sg_destroy", "sg_vector_length", "sg_operator_apply", "sg_vanka_smooth",
            "gmg_vcycle", "fgmres_solve_slab", "sg_quadrature_points", "sg_node_coordinates", "sg_update_coefficients", "sg_operator_apply_T",
-           "sg_slab_transfer", "sg_stiffness_form_cells", "sg_qoi_mean_var", "sg_sample_statistics", "sg_chaos_moments", "sg_last_error"]
+           "sg_slab_transfer", "sg_stiffness_form_cells", "sg_qoi_mean_var", "sg_sample_statistics", "sg_chaos_moments", "sg_gauss_points", "sg_index_set", "sg_chaos_projection",
+           "sg_time_rule", "sg_time_load_weights", "sg_load_vectors", "sg_separable_vector", "sg_separable_error",
+           "sg_last_error"]
 
 
 class SgError(RuntimeError):
@@ -73,6 +75,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sg_qoi_mean_var.argtypes = [P, V, D, D, ctypes.POINTER(ctypes.c_double), V, V]
     lib.sg_sample_statistics.argtypes = [P, V, V, V, V]
     lib.sg_chaos_moments.argtypes = [P, V, V, V, V]
+    PD, PI = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+    lib.sg_gauss_points.argtypes = [ctypes.POINTER(ProblemDesc), I, I, PD]
+    lib.sg_index_set.argtypes = [P, PI]
+    lib.sg_chaos_projection.argtypes = [P, I, PI, PD, PD]
+    lib.sg_time_rule.argtypes = [P, I, PD, PD]
+    lib.sg_time_load_weights.argtypes = [P, I, I, PD, PD]
+    lib.sg_load_vectors.argtypes = [P, I, I, V, V, V, V]
+    lib.sg_separable_vector.argtypes = [P, I, PD, V, D, V, V]
+    lib.sg_separable_error.argtypes = [P, V, I, V, V, I, PD, PD, D, PD, V]
     lib.sg_last_error.restype = ctypes.c_char_p
     for f in EXPORTS:
         if f != "sg_last_error":
@@ -128,6 +139,19 @@ def quadrature_points(spec, level: int) -> np.ndarray:
     out = np.zeros((n ** spec.dim, npts, spec.dim))
     _check(_lib.sg_quadrature_points(ctypes.byref(d), level, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return out
+
+
+def gauss_points(spec, level: int, nq1: int) -> np.ndarray:
+    """Physical points of the nq1-point Gauss rule per direction, [n_cells, nq1^d, d]."""
+    d = _desc(spec)
+    n = spec.n_cells_1d >> level
+    out = np.zeros((n ** spec.dim, nq1 ** spec.dim, spec.dim))
+    _check(_lib.sg_gauss_points(ctypes.byref(d), level, nq1, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
 def node_coordinates(spec, level: int) -> np.ndarray:
@@ -195,6 +219,7 @@ class Problem:
         self._h = h
         self.precision = precision
         self.n_samples = 0 if samples is None else n_modes
+        self.n_mu = mus.shape[0]
         self.shape = (n_modes, spec.time_degree + 1, (spec.n_cells_1d * spec.fe_degree + 1) ** spec.dim)
 
     def update_coefficients(self, coef_qp_levels):
@@ -287,6 +312,66 @@ class Problem:
         v = _ptr(var, m, "var") if var is not None else None
         _check(_lib.sg_chaos_moments(self._h, _ptr(u, n, "u"), _ptr(mean, m, "mean"), v, _stream(stream)))
         return mean, var
+
+    # --- prescribed solutions and forcing ------------------------------------------------------------
+    def index_set(self) -> np.ndarray:
+        out = np.zeros((self.shape[0], self.spec.n_vars), dtype=np.int32)
+        _check(_lib.sg_index_set(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
+        return out
+
+    def chaos_projection(self, src_alpha, src_c) -> np.ndarray:
+        """out[mu, beta] = sum_s src_c[s] E[Psi_mu Psi_{src_alpha[s]} Psi_beta] (coefficient modes x modes)."""
+        a = np.ascontiguousarray(np.asarray(src_alpha, dtype=np.int32).reshape(-1, self.spec.n_vars))
+        c = np.ascontiguousarray(np.asarray(src_c, dtype=np.float64).reshape(-1))
+        out = np.zeros((self.n_mu, self.shape[0]))
+        _check(_lib.sg_chaos_projection(self._h, a.shape[0], a.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(c),
+                                        _dp(out)))
+        return out
+
+    def time_rule(self, ntq: int):
+        s, w = np.zeros(ntq), np.zeros(ntq)
+        _check(_lib.sg_time_rule(self._h, ntq, _dp(s), _dp(w)))
+        return s, w
+
+    def time_load_weights(self, gvals) -> np.ndarray:
+        g = np.ascontiguousarray(np.atleast_2d(np.asarray(gvals, dtype=np.float64)))
+        out = np.zeros((g.shape[0], self.shape[1]))
+        _check(_lib.sg_time_load_weights(self._h, g.shape[1], g.shape[0], _dp(g), _dp(out)))
+        return out
+
+    def load_vectors(self, nq1, fval=None, fgrad=None, n_fields=None, out=None, stream=None):
+        """Spatial loads [n_fields, n_nodes] of fields at the nq1-point Gauss rule (device tensors)."""
+        import torch
+        nf = n_fields if n_fields is not None else (fval if fval is not None else fgrad).shape[0]
+        n_cells = self.spec.n_cells_1d ** self.spec.dim
+        nq = nq1 ** self.spec.dim
+        if out is None:
+            out = torch.empty(nf, self.shape[2], dtype=torch.float64, device="cuda")
+        fv = _ptr(fval, nf * n_cells * nq, "fval") if fval is not None else None
+        fg = _ptr(fgrad, nf * n_cells * nq * self.spec.dim, "fgrad") if fgrad is not None else None
+        _check(_lib.sg_load_vectors(self._h, nq1, nf, fv, fg, _ptr(out, nf * self.shape[2], "out"), _stream(stream)))
+        return out
+
+    def separable_vector(self, W, V, y, beta=0.0, stream=None):
+        """y = beta y + sum_t W[t] (x) V[t], W [n_terms, N_xi, N_t] (host), V [n_terms, n_nodes] (device)."""
+        Wc = np.ascontiguousarray(np.asarray(W, dtype=np.float64).reshape(-1, self.shape[0], self.shape[1]))
+        nt = Wc.shape[0]
+        _check(_lib.sg_separable_vector(self._h, nt, _dp(Wc), _ptr(V, nt * self.shape[2], "V"), float(beta),
+                                        _ptr(y, self.n(0), "y"), _stream(stream)))
+        return y
+
+    def separable_error(self, u, nq1, s_qp, gs_qp, theta, c, C2, stream=None) -> np.ndarray:
+        """The 8 error sums of one slab against theta(t) s(x) sum_a c_a Psi_a (see the header)."""
+        n_cells = self.spec.n_cells_1d ** self.spec.dim
+        nq = nq1 ** self.spec.dim
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+        cc = np.ascontiguousarray(np.asarray(c, dtype=np.float64))
+        assert cc.size == self.shape[0]
+        out = np.zeros(8)
+        _check(_lib.sg_separable_error(self._h, _ptr(u, self.n(0), "u"), nq1, _ptr(s_qp, n_cells * nq, "s_qp"),
+                                       _ptr(gs_qp, n_cells * nq * self.spec.dim, "gs_qp"), th.size, _dp(th), _dp(cc),
+                                       float(C2), _dp(out), _stream(stream)))
+        return out
 
     def vanka_smooth(self, level, b, x, sweeps=1, stream=None):
         n = self.n(level)

@@ -9,6 +9,7 @@ Every workload here is affine in xi, so the active set is {0, e_1, ..., e_M} and
 """
 from __future__ import annotations
 
+import itertools
 import math
 from dataclasses import dataclass, field, asdict
 
@@ -179,6 +180,13 @@ def finite_chaos_phi(x: np.ndarray) -> tuple:
     s1, s2 = np.sin(h * (x[..., 0] + 1)), np.sin(h * (x[..., 1] + 1))
     c1, c2 = np.cos(h * (x[..., 0] + 1)), np.cos(h * (x[..., 1] + 1))
     return s1 * s2, np.stack([h * c1 * s2, h * s1 * c2], axis=-1)
+
+
+def finite_chaos_exact_modes():
+    """Multi-indices of Lambda_q (M = 4, q = 6) and the exact solution's coefficients c_alpha."""
+    alphas = [a for a in itertools.product(range(FINITE_Q + 1), repeat=4) if sum(a) <= FINITE_Q]
+    c = [1.0 if sum(a) == 0 else FINITE_ETA ** sum(a) for a in alphas]
+    return np.array(alphas, dtype=np.int32), np.array(c)
 
 
 @dataclass(frozen=True)
