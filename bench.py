@@ -231,6 +231,28 @@ def member_batch_timing(torch, name="c4", reps=2):
     return out
 
 
+def finite_chaos_table(torch, p_max, n_cells=128, n_slabs=64, n_levels=5):
+    """The finite-chaos benchmark at the paper's discretisation (2D Q3 on n_cells^2 cells of (-1,1)^2,
+    dG(3), n_slabs slabs): error quantities and wall time per stochastic degree p = 0..p_max."""
+    import sg_inputs
+    from paper_2605_21046_amd.finitechaos import FiniteChaosRun
+    rows = []
+    for p in range(p_max + 1):
+        fw = sg_inputs.finite_chaos_workload(n_cells, 3, 3, n_slabs, p, n_levels)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        R = FiniteChaosRun(fw, rtol=1e-10)
+        errs, _ = R.run()
+        torch.cuda.synchronize()
+        its = [i["iterations"] for i in R.info]
+        rows.append({"p_xi": p, "N_xi": R.P.shape[0], "dofs_per_slab": R.P.n(0), **{k: float(f"{v:.6e}") for k, v in errs.items()},
+                     "wall_s": round(time.perf_counter() - t0, 2), "iterations_per_slab": [min(its), max(its)]})
+        R.close()
+        print(f"[bench] finite chaos p={p}: {rows[-1]}", file=sys.stderr, flush=True)
+    return {"workload": f"finite-chaos benchmark: 2D Q3 on {n_cells}^2 cells of (-1,1)^2, dG(3), {n_slabs} slabs, "
+                        f"M=4, q=6, eta=0.35, slab solves to rtol 1e-10", "rows": rows}
+
+
 def copy_bandwidth(torch, dev, reps=20):
     """Achievable HBM bandwidth of a plain device copy over two disjoint 1 GiB buffer pairs."""
     n = 1 << 27
@@ -261,6 +283,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient timing (16^3 cells, 10 slabs)")
     ap.add_argument("--no-batch", action="store_true", help="skip the Monte-Carlo batch timing (256 samples, 20 slabs)")
     ap.add_argument("--only-apply", action="store_true", help="skip the solves (for profiling the apply)")
+    ap.add_argument("--finite-chaos", type=int, default=-1, metavar="P",
+                    help="also run the finite-chaos benchmark for p_xi = 0..P at the paper's discretisation")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy 5 times (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -401,6 +425,9 @@ def main():
         out["member_batch"] = member_batch_timing(torch)
         print(f"[bench] member batch {out['member_batch']['fp64_ms']} ms fp64, {out['member_batch']['mixed_ms']} ms mixed",
               file=sys.stderr, flush=True)
+
+    if args.finite_chaos >= 0:
+        out["finite_chaos"] = finite_chaos_table(torch, args.finite_chaos)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
