@@ -52,36 +52,6 @@ hipError_t launch_cell_dot(int dim, int k, Grid g, int ncomp, const double* lam,
                            hipStream_t s);
 
 // mean[i][node] and unbiased var[i][node] over N sample blocks of a slab vector u[N][nt][nn]
-// 1D tables of the GLL Lagrange basis at an nq1-point Gauss rule on (0, 1): values V[q][a], reference
-// derivatives D[q][a], weights w[q] (nq1 <= 8, k <= 4).
-constexpr int kMaxQ1 = 8;
-struct QTables {
-    double V[kMaxQ1][5];
-    double D[kMaxQ1][5];
-    double w[kMaxQ1];
-};
-// Time rule on one slab: basis values v[i][k] at the rule's points, weights w[k] (times tau) and the
-// temporal factor theta at the points' physical times.
-constexpr int kMaxTimeQ = 8;
-struct TimeTables {
-    double v[4][kMaxTimeQ];
-    double w[kMaxTimeQ];
-    double theta[kMaxTimeQ];
-    int ntq;
-};
-// S[field][broken node] = sum_q w_q |K| (f psi_a + g . grad psi_a) for nf fields
-hipError_t launch_load_cells(int dim, int k, Grid g, int nq1, const QTables& tb, double h, const double* f,
-                             const double* gq, int nf, double* S, hipStream_t s);
-// y = beta y + sum_t W[t][comp] V[t][node]
-hipError_t launch_separable(int n_terms, int ncomp, long long nn, const double* W, const double* V, double beta,
-                            double* y, hipStream_t s);
-// per-cell error sums [n_cells][8]: full L2, full H1, mean L2, mean H1, var L2, var H1, |theta s|^2,
-// |theta grad s|^2 against c_alpha theta(t) s(x)
-bool error_cells_supported(int dim, int k, int nt);
-hipError_t launch_error_cells(int dim, int k, int nt, Grid g, int nq1, const QTables& tb, double h,
-                              const TimeTables& tt, int n_xi, const double* u, const double* c, double C2,
-                              const double* s_qp, const double* gs_qp, double* part, hipStream_t s);
-
 // mean[j][i][node] = u[off[j]][i][node], var = sum_{off[j] < a < off[j+1]} u[a][i][node]^2
 hipError_t launch_chaos_moments(const double* u, const int* off, int n_members, int nt, long long nn, double* mean,
                                 double* var, hipStream_t s);

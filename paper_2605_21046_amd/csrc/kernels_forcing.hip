@@ -10,7 +10,7 @@
 
 #include <algorithm>
 
-#include "kernels.hpp"
+#include "forcing.hpp"
 
 namespace sg {
 

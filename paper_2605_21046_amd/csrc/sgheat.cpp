@@ -18,6 +18,7 @@
 #include "../../include/sgheat.h"
 #include "basis.hpp"
 #include "kernels.hpp"
+#include "forcing.hpp"
 
 using namespace sg;
 

@@ -388,3 +388,36 @@ MEMBER_WORKLOADS = {
     "b2": MemberWorkload(Workload("b2", 2, 4, 2, 1, 0.02, 2, 0, 2, "c1"), (1, 2, 3, 0, 2), 3, seed=9),
     "b3": MemberWorkload(Workload("b3", 3, 2, 2, 1, 0.02, 3, 0, 1, "sine"), (1, 2), 2, seed=10),
 }
+
+
+@dataclass(frozen=True)
+class MCErrorWorkload:
+    """Monte-Carlo study of the finite-chaos benchmark: pathwise problems (coefficient and forcing of
+    Section 3.2 at xi^(s)) discretised with ``base`` (field "finite", dim 2, (-1, 1)^2, chaos degree
+    unused), ``n_slabs`` slabs of tau = T / n_slabs, ``n_samples`` draws xi ~ N(0, I_4) from the PCG64
+    stream ``seed``, solved ``batch`` samples per handle."""
+    base: Workload
+    n_slabs: int
+    n_samples: int
+    batch: int
+    seed: int
+
+    def samples(self) -> np.ndarray:
+        g = np.random.Generator(np.random.PCG64(self.seed))
+        return g.standard_normal((self.n_samples, 4))
+
+
+def mc_error_workload(n_cells_1d: int, fe_degree: int, time_degree: int, n_slabs: int, n_samples: int, batch: int,
+                      seed: int, n_levels: int) -> MCErrorWorkload:
+    w = Workload(f"mc{n_cells_1d}q{fe_degree}r{time_degree}", 2, n_cells_1d, fe_degree, time_degree, 1.0 / n_slabs, 4,
+                 0, n_levels, "finite", lo=-1.0, hi=1.0)
+    return MCErrorWorkload(w, n_slabs, n_samples, batch, seed)
+
+
+MC_ERROR_WORKLOADS = {
+    # 2D Q3 on 32^2 cells of (-1,1)^2 (h = 1/16), dG(3), tau = 1/16 (16 slabs), 512 samples in 4 handles
+    "c6": mc_error_workload(32, 3, 3, 16, 512, 128, 12, 4),
+    # small cases for the tests
+    "e2": mc_error_workload(4, 3, 3, 2, 6, 3, 13, 2),
+    "e3": mc_error_workload(4, 2, 1, 3, 5, 5, 14, 2),
+}
