@@ -37,7 +37,7 @@ APPLY_SOURCES = ["device_common.hpp", "kernels.hpp", "apply_impl.hpp", "apply_3d
 # sources the entry no longer matches and the traffic is reported as null until it is measured again.
 MEASURED_TRAFFIC = {
     # profiles/sg_apply_c2_hbm_traffic.md
-    ("c2", "fd4484f91f3f4048"): {"fetch_bytes": 860248981, "write_bytes": 822841139},
+    ("c2", "c65e3ee9ae8aef0e"): {"fetch_bytes": 859779665, "write_bytes": 822180009},
 }
 
 

@@ -263,6 +263,31 @@ sg_status sg_separable_vector(sg_handle h, int n_terms, const double* W, const d
 sg_status sg_separable_error(sg_handle h, const double* u, int nq1, const double* s_qp, const double* gs_qp, int ntq,
                              const double* theta, const double* c, double C2, double* out, void* hip_stream);
 
+/* ---- Monte-Carlo estimators at quadrature points and their error split (Section 5.2-5.4, eqs.
+ * mc-mean-estimator, mc-variance-estimator-unbiased, mc-error-mean-L2,mc-error-var-L2, mc-disc-mean-error,
+ * mc-disc-var-error).  The estimators are formed pointwise at the space-time quadrature points from
+ * running sums over the samples, so several sample-batch handles (on the same mesh) can feed one
+ * estimate. */
+
+/* Psi_alpha(xi^(s)) for the handle's samples and the given multi-indices: out[s][j], alpha [n_idx][n_vars].
+ * Sample-batch handles only.  Host only. */
+sg_status sg_sample_psi(sg_handle h, int n_idx, const int* alpha, double* out);
+
+/* acc[cell][q][k][0] += sum_s u_s(x_q, t_k), acc[cell][q][k][1] += sum_s u_s(x_q, t_k)^2 over the samples of
+ * the sample-batch slab vector u, at the nq1-point Gauss rule per space direction (points as
+ * sg_gauss_points) and the ntq-point time rule (sg_time_rule).  acc is a caller-owned device array of
+ * n_cells * nq1^d * ntq * 2 doubles, zeroed by the caller.  Asynchronous. */
+sg_status sg_sample_qp_moments(sg_handle h, const double* u, int nq1, int ntq, double* acc, void* hip_stream);
+
+/* From such sums over n_tot >= 2 samples: mean M = S1/n_tot and unbiased variance V = (S2 - n_tot M^2)/(n_tot - 1)
+ * at every quadrature point, and over the slab and D
+ *   out[0], out[1] = int |M - mean_targets[j] theta s|^2,   out[2], out[3] = int |V - var_targets[j] theta^2 s^2|^2,
+ *   out[4] = int |theta s|^2,  out[5] = int |theta s|^4,
+ * for a separable reference theta(t) s(x) (s_qp device [n_cells][nq1^d], theta host [ntq]).  Synchronous. */
+sg_status sg_moment_errors(sg_handle h, const double* acc, long long n_tot, int nq1, const double* s_qp, int ntq,
+                           const double* theta, const double* mean_targets, const double* var_targets, double* out,
+                           void* hip_stream);
+
 /* Message for the last non-OK status returned on the calling thread ("" if none). */
 const char* sg_last_error(void);
 

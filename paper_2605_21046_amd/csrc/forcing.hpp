@@ -37,4 +37,13 @@ hipError_t launch_error_cells(int dim, int k, int nt, Grid g, int nq1, const QTa
                               const TimeTables& tt, int n_xi, const double* u, const double* c, double C2,
                               const double* s_qp, const double* gs_qp, double* part, hipStream_t s);
 
+// acc[cell][q][tq][2] += (sum_s u_s, sum_s u_s^2) at the quadrature points, over the n_s samples of u
+hipError_t launch_sample_qp_moments(int dim, int k, int nt, Grid g, int nq1, const QTables& tb, const TimeTables& tt,
+                                    int n_s, const double* u, double* acc, hipStream_t s);
+// part[cell][6]: squared errors of the sample mean / unbiased variance (from acc) against m_j theta s and
+// v_j theta^2 s^2, then |theta s|^2 and |theta^2 s^2|^2
+hipError_t launch_moment_errors(int dim, Grid g, int nq1, const QTables& tb, double h, const TimeTables& tt, double n_tot,
+                                const double* acc, const double* s_qp, double m0, double m1, double v0, double v1,
+                                double* part, hipStream_t s);
+
 }  // namespace sg

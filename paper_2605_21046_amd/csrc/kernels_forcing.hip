@@ -235,6 +235,137 @@ __global__ void __launch_bounds__(64)
     }
 }
 
+// Sample moments at the space-time quadrature points: acc[cell][q][tq][0..1] += (sum_s u_s, sum_s u_s^2)
+// over the samples of a sample-batch slab vector.  One wave per cell, the cell's values in LDS.
+template <int DIM, int K, int NT>
+__global__ void __launch_bounds__(64)
+    k_sample_qp_moments(Grid g, int nq1, QTables tb, TimeTables tt, int n_s, const double* __restrict__ u,
+                        double* __restrict__ acc) {
+    constexpr int N1 = K + 1;
+    constexpr int NP = DIM == 2 ? N1 * N1 : N1 * N1 * N1;
+    extern __shared__ double lds[];                 // [n_s * NT][NP]
+    const int t = threadIdx.x;
+    const long long cell = blockIdx.x;
+    const int n = g.n, n1 = g.n1;
+    const long long nn = g.n_nodes;
+    int cc[3] = {0, 0, 0};
+    {
+        long long r = cell;
+        for (int d = 0; d < DIM; ++d) {
+            cc[d] = (int)(r % n);
+            r /= n;
+        }
+    }
+    const int ncomp = n_s * NT;
+    for (int idx = t; idx < ncomp * NP; idx += 64) {
+        const int comp = idx / NP, a = idx % NP;
+        int ra = a;
+        long long node = 0, mul = 1;
+        for (int d = 0; d < DIM; ++d) {
+            node += (long long)(cc[d] * K + ra % N1) * mul;
+            ra /= N1;
+            mul *= n1;
+        }
+        lds[idx] = u[(long long)comp * nn + node];
+    }
+    __syncthreads();
+    const int nq = DIM == 2 ? nq1 * nq1 : nq1 * nq1 * nq1;
+    for (int q = t; q < nq; q += 64) {
+        int qq[3] = {0, 0, 0};
+        int rq = q;
+        for (int d = 0; d < DIM; ++d) {
+            qq[d] = rq % nq1;
+            rq /= nq1;
+        }
+        double psi[NP];
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+            int ra = a;
+            double p = 1.0;
+            for (int d = 0; d < DIM; ++d) {
+                p *= tb.V[qq[d]][ra % N1];
+                ra /= N1;
+            }
+            psi[a] = p;
+        }
+        double s1[kMaxTimeQ], s2[kMaxTimeQ];
+#pragma unroll
+        for (int k = 0; k < kMaxTimeQ; ++k) s1[k] = s2[k] = 0.0;
+        for (int sm = 0; sm < n_s; ++sm) {
+            double val[NT];
+#pragma unroll
+            for (int i = 0; i < NT; ++i) {
+                const double* row = lds + (sm * NT + i) * NP;
+                double v = 0.0;
+#pragma unroll
+                for (int a = 0; a < NP; ++a) v += row[a] * psi[a];
+                val[i] = v;
+            }
+#pragma unroll
+            for (int k = 0; k < kMaxTimeQ; ++k) {
+                if (k >= tt.ntq) break;
+                double x = 0.0;
+#pragma unroll
+                for (int i = 0; i < NT; ++i) x += tt.v[i][k] * val[i];
+                s1[k] += x;
+                s2[k] += x * x;
+            }
+        }
+        double* out = acc + (cell * nq + q) * (long long)tt.ntq * 2;
+#pragma unroll
+        for (int k = 0; k < kMaxTimeQ; ++k) {
+            if (k >= tt.ntq) break;
+            out[2 * k] += s1[k];
+            out[2 * k + 1] += s2[k];
+        }
+    }
+}
+
+// Errors of the sample mean and unbiased sample variance (from acc over n_tot samples) against
+// m_j theta s and v_j theta^2 s^2 (j = 0, 1); part[cell][6] = the four squared errors, |theta s|^2 and
+// |theta^2 s^2|^2, integrated over the cell and the slab.
+template <int DIM>
+__global__ void __launch_bounds__(64)
+    k_moment_errors(Grid g, int nq1, QTables tb, double h, TimeTables tt, double n_tot, const double* __restrict__ acc,
+                    const double* __restrict__ s_qp, double m0, double m1, double v0, double v1,
+                    double* __restrict__ part) {
+    const int t = threadIdx.x;
+    const long long cell = blockIdx.x;
+    const int nq = DIM == 2 ? nq1 * nq1 : nq1 * nq1 * nq1;
+    double vol = 1.0;
+    for (int d = 0; d < DIM; ++d) vol *= h;
+    double e[6] = {0, 0, 0, 0, 0, 0};
+    for (int q = t; q < nq; q += 64) {
+        int rq = q;
+        double wq = vol;
+        for (int d = 0; d < DIM; ++d) {
+            wq *= tb.w[rq % nq1];
+            rq /= nq1;
+        }
+        const double s = s_qp[cell * nq + q];
+        const double* a = acc + (cell * nq + q) * (long long)tt.ntq * 2;
+        for (int k = 0; k < tt.ntq; ++k) {
+            const double w = tt.w[k] * wq;
+            const double M = a[2 * k] / n_tot;
+            const double V = (a[2 * k + 1] - n_tot * M * M) / (n_tot - 1.0);
+            const double ph = tt.theta[k] * s;
+            const double p2 = ph * ph;
+            const double d0 = M - m0 * ph, d1 = M - m1 * ph, d2 = V - v0 * p2, d3 = V - v1 * p2;
+            e[0] += w * d0 * d0;
+            e[1] += w * d1 * d1;
+            e[2] += w * d2 * d2;
+            e[3] += w * d3 * d3;
+            e[4] += w * p2;
+            e[5] += w * p2 * p2;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const double v = wave_sum<64>(e[j]);
+        if (t == 0) part[cell * 6 + j] = v;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_load_cells(int dim, int k, Grid g, int nq1, const QTables& tb, double h, const double* f,
@@ -309,6 +440,56 @@ hipError_t launch_error_cells(int dim, int k, int nt, Grid g, int nq1, const QTa
 #undef SG_EC_T
 #undef SG_EC
     return err;
+}
+
+hipError_t launch_sample_qp_moments(int dim, int k, int nt, Grid g, int nq1, const QTables& tb, const TimeTables& tt,
+                                    int n_s, const double* u, double* acc, hipStream_t s) {
+    const int np = dim == 2 ? (k + 1) * (k + 1) : (k + 1) * (k + 1) * (k + 1);
+    const size_t lds = (size_t)n_s * nt * np * sizeof(double);
+    if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+    hipError_t err = hipErrorInvalidValue;
+#define SG_SM(D_, K_, T_)                                                                                     \
+    do {                                                                                                      \
+        auto kern = k_sample_qp_moments<D_, K_, T_>;                                                          \
+        if (lds > 64 * 1024) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+        hipLaunchKernelGGL(kern, dim3((unsigned)g.n_cells), dim3(64), lds, s, g, nq1, tb, tt, n_s, u, acc);   \
+        err = hipGetLastError();                                                                              \
+    } while (0)
+#define SG_SM_T(D_, K_)                   \
+    switch (nt) {                         \
+        case 1: SG_SM(D_, K_, 1); break;  \
+        case 2: SG_SM(D_, K_, 2); break;  \
+        case 3: SG_SM(D_, K_, 3); break;  \
+        default: SG_SM(D_, K_, 4); break; \
+    }
+    if (dim == 2) {
+        switch (k) {
+            case 1: SG_SM_T(2, 1); break;
+            case 2: SG_SM_T(2, 2); break;
+            case 3: SG_SM_T(2, 3); break;
+            default: SG_SM_T(2, 4); break;
+        }
+    } else {
+        switch (k) {
+            case 1: SG_SM_T(3, 1); break;
+            default: SG_SM_T(3, 2); break;
+        }
+    }
+#undef SG_SM_T
+#undef SG_SM
+    return err;
+}
+
+hipError_t launch_moment_errors(int dim, Grid g, int nq1, const QTables& tb, double h, const TimeTables& tt, double n_tot,
+                                const double* acc, const double* s_qp, double m0, double m1, double v0, double v1,
+                                double* part, hipStream_t s) {
+    if (dim == 2)
+        hipLaunchKernelGGL(k_moment_errors<2>, dim3((unsigned)g.n_cells), dim3(64), 0, s, g, nq1, tb, h, tt, n_tot, acc,
+                           s_qp, m0, m1, v0, v1, part);
+    else
+        hipLaunchKernelGGL(k_moment_errors<3>, dim3((unsigned)g.n_cells), dim3(64), 0, s, g, nq1, tb, h, tt, n_tot, acc,
+                           s_qp, m0, m1, v0, v1, part);
+    return hipGetLastError();
 }
 
 }  // namespace sg

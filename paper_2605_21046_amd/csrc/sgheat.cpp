@@ -129,6 +129,7 @@ struct sg_handle_s {
     DevBuf<double> zcoef, fcoef, qpart, qout, qC;
     DevBuf<double> elem_E, elem_M;             // element matrices of the patch set-up (reused)
     DevBuf<double> sepW, errC, errPart, errOut;  // separable weights, error-sum work arrays
+    DevBuf<double> momPart;                      // moment-error partial sums
     std::vector<double> hstage;
     std::vector<double> trip;                 // E[Psi_a Psi_b Psi_eps], [n_xi][n_xi][n_eps]
     int n_eps = 0;
@@ -1360,6 +1361,70 @@ sg_status sg_separable_error(sg_handle h, const double* u, int nq1, const double
                               gs_qp, h->errPart.p, s));
     SG_HIP(launch_reduce_partials(h->errPart.p, (int)l0.g.n_cells, 8, h->errOut.p, s));
     SG_HIP(hipMemcpyAsync(out, h->errOut.p, sizeof(double) * 8, hipMemcpyDeviceToHost, s));
+    SG_HIP(hipStreamSynchronize(s));
+    return SG_OK;
+}
+
+namespace {
+TimeTables make_ttables(sg_handle h, int ntq, const double* theta) {
+    TimeTables tt{};
+    tt.ntq = ntq;
+    std::vector<double> gw;
+    const std::vector<double> gq = gauss_points(ntq, &gw);
+    const std::vector<double> tn = right_radau_points(h->d.time_degree);
+    for (int k = 0; k < ntq; ++k) {
+        tt.w[k] = gw[k] * h->d.tau;
+        tt.theta[k] = theta ? theta[k] : 0.0;
+        for (int i = 0; i < h->NT; ++i) tt.v[i][k] = lagrange_value(tn, i, gq[k]);
+    }
+    return tt;
+}
+}  // namespace
+
+sg_status sg_sample_psi(sg_handle h, int n_idx, const int* alpha, double* out) {
+    if (!h || !alpha || !out || n_idx < 0) return fail(SG_EINVAL, "bad argument");
+    if (h->d.n_samples < 1) return fail(SG_EINVAL, "not a sample-batch handle");
+    const int M = h->d.n_vars;
+    for (int sm = 0; sm < h->d.n_samples; ++sm)
+        for (int j = 0; j < n_idx; ++j) {
+            double v = 1.0;
+            for (int m = 0; m < M; ++m) v *= hermite_normalized(alpha[(size_t)j * M + m], h->samples[(size_t)sm * M + m]);
+            out[(size_t)sm * n_idx + j] = v;
+        }
+    return SG_OK;
+}
+
+sg_status sg_sample_qp_moments(sg_handle h, const double* u, int nq1, int ntq, double* acc, void* hip_stream) {
+    if (!h || !u || !acc) return fail(SG_EINVAL, "null argument");
+    if (h->d.n_samples < 1) return fail(SG_EINVAL, "not a sample-batch handle");
+    if (nq1 < 1 || nq1 > kMaxQ1 || ntq < 1 || ntq > kMaxTimeQ) return fail(SG_EINVAL, "nq1 and ntq must be in 1..8");
+    if (!error_cells_supported(h->d.dim, h->d.fe_degree, h->NT))
+        return fail(SG_EUNSUPPORTED, "sample moments: 2D k <= 4 or 3D k <= 2, dG(r) with r <= 3");
+    if ((size_t)h->n_xi * h->NT * h->NP * sizeof(double) > 160 * 1024)
+        return fail(SG_EUNSUPPORTED, "sample moments: n_samples * N_t * (k+1)^d values exceed one LDS");
+    const QTables tb = make_qtables(h->d.fe_degree, nq1);
+    const TimeTables tt = make_ttables(h, ntq, nullptr);
+    SG_HIP(launch_sample_qp_moments(h->d.dim, h->d.fe_degree, h->NT, h->lv[0].g, nq1, tb, tt, h->n_xi, u, acc,
+                                    (hipStream_t)hip_stream));
+    return SG_OK;
+}
+
+sg_status sg_moment_errors(sg_handle h, const double* acc, long long n_tot, int nq1, const double* s_qp, int ntq,
+                           const double* theta, const double* mean_targets, const double* var_targets, double* out,
+                           void* hip_stream) {
+    if (!h || !acc || !s_qp || !theta || !mean_targets || !var_targets || !out) return fail(SG_EINVAL, "null argument");
+    if (n_tot < 2) return fail(SG_EINVAL, "the unbiased variance needs at least two samples");
+    if (nq1 < 1 || nq1 > kMaxQ1 || ntq < 1 || ntq > kMaxTimeQ) return fail(SG_EINVAL, "nq1 and ntq must be in 1..8");
+    const hipStream_t s = (hipStream_t)hip_stream;
+    const Level& l0 = h->lv[0];
+    const QTables tb = make_qtables(h->d.fe_degree, nq1);
+    const TimeTables tt = make_ttables(h, ntq, theta);
+    SG_TRY(h->momPart.alloc((size_t)l0.g.n_cells * 6, "moment errors"));
+    SG_TRY(h->errOut.alloc(8, "moment errors"));
+    SG_HIP(launch_moment_errors(h->d.dim, l0.g, nq1, tb, l0.h, tt, (double)n_tot, acc, s_qp, mean_targets[0],
+                                mean_targets[1], var_targets[0], var_targets[1], h->momPart.p, s));
+    SG_HIP(launch_reduce_partials(h->momPart.p, (int)l0.g.n_cells, 6, h->errOut.p, s));
+    SG_HIP(hipMemcpyAsync(out, h->errOut.p, sizeof(double) * 6, hipMemcpyDeviceToHost, s));
     SG_HIP(hipStreamSynchronize(s));
     return SG_OK;
 }

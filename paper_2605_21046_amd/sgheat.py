@@ -22,7 +22,7 @@ EXPORTS = ["sg_create", "sg_destroy", "sg_vector_length", "sg_operator_apply", "
            "gmg_vcycle", "fgmres_solve_slab", "sg_quadrature_points", "sg_node_coordinates", "sg_update_coefficients", "sg_operator_apply_T",
            "sg_slab_transfer", "sg_stiffness_form_cells", "sg_qoi_mean_var", "sg_sample_statistics", "sg_chaos_moments", "sg_gauss_points", "sg_index_set", "sg_chaos_projection",
            "sg_time_rule", "sg_time_load_weights", "sg_load_vectors", "sg_separable_vector", "sg_separable_error",
-           "sg_last_error"]
+           "sg_sample_psi", "sg_sample_qp_moments", "sg_moment_errors", "sg_last_error"]
 
 
 class SgError(RuntimeError):
@@ -84,6 +84,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sg_load_vectors.argtypes = [P, I, I, V, V, V, V]
     lib.sg_separable_vector.argtypes = [P, I, PD, V, D, V, V]
     lib.sg_separable_error.argtypes = [P, V, I, V, V, I, PD, PD, D, PD, V]
+    lib.sg_sample_psi.argtypes = [P, I, PI, PD]
+    lib.sg_sample_qp_moments.argtypes = [P, V, I, I, V, V]
+    lib.sg_moment_errors.argtypes = [P, V, ctypes.c_longlong, I, V, I, PD, PD, PD, PD, V]
     lib.sg_last_error.restype = ctypes.c_char_p
     for f in EXPORTS:
         if f != "sg_last_error":
@@ -371,6 +374,32 @@ class Problem:
         _check(_lib.sg_separable_error(self._h, _ptr(u, self.n(0), "u"), nq1, _ptr(s_qp, n_cells * nq, "s_qp"),
                                        _ptr(gs_qp, n_cells * nq * self.spec.dim, "gs_qp"), th.size, _dp(th), _dp(cc),
                                        float(C2), _dp(out), _stream(stream)))
+        return out
+
+    # --- Monte-Carlo estimators at quadrature points --------------------------------------------------
+    def sample_psi(self, alphas) -> np.ndarray:
+        a = np.ascontiguousarray(np.asarray(alphas, dtype=np.int32).reshape(-1, self.spec.n_vars))
+        out = np.zeros((self.n_samples, a.shape[0]))
+        _check(_lib.sg_sample_psi(self._h, a.shape[0], a.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(out)))
+        return out
+
+    def qp_moment_length(self, nq1, ntq) -> int:
+        return (self.spec.n_cells_1d ** self.spec.dim) * nq1 ** self.spec.dim * ntq * 2
+
+    def sample_qp_moments(self, u, nq1, ntq, acc, stream=None):
+        _check(_lib.sg_sample_qp_moments(self._h, _ptr(u, self.n(0), "u"), nq1, ntq,
+                                         _ptr(acc, self.qp_moment_length(nq1, ntq), "acc"), _stream(stream)))
+        return acc
+
+    def moment_errors(self, acc, n_tot, nq1, s_qp, theta, mean_targets, var_targets, stream=None) -> np.ndarray:
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+        mt = np.ascontiguousarray(np.asarray(mean_targets, dtype=np.float64))
+        vt = np.ascontiguousarray(np.asarray(var_targets, dtype=np.float64))
+        out = np.zeros(6)
+        n_cells = self.spec.n_cells_1d ** self.spec.dim
+        _check(_lib.sg_moment_errors(self._h, _ptr(acc, self.qp_moment_length(nq1, th.size), "acc"), int(n_tot), nq1,
+                                     _ptr(s_qp, n_cells * nq1 ** self.spec.dim, "s_qp"), th.size, _dp(th), _dp(mt),
+                                     _dp(vt), _dp(out), _stream(stream)))
         return out
 
     def vanka_smooth(self, level, b, x, sweeps=1, stream=None):
