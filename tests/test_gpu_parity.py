@@ -206,10 +206,14 @@ def test_argument_errors(torch_cuda):
         G.apply(x.float())
     with pytest.raises(sgheat.SgError):
         G.vanka_smooth(7, x, x.clone())
-    # non-affine coefficient: the operator is fine, the preconditioner is not available
+    # a coefficient list without the mean mode, and more than 512 components per cell
     w = sg_inputs.WORKLOADS["t2q2"]
     spec = sgheat.Spec(w.dim, w.n_cells_1d, w.fe_degree, w.time_degree, w.tau, w.n_vars, w.chaos_degree, w.n_levels)
     nq = (w.fe_degree + 1) ** w.dim
     coef = [np.ones((2, (w.n_cells_1d >> l) ** w.dim, nq)) for l in range(w.n_levels)]
-    with pytest.raises(sgheat.SgError):
-        sgheat.Problem(spec, [[0, 0], [2, 0]], coef)
+    with pytest.raises(sgheat.SgError, match="SG_EINVAL"):
+        sgheat.Problem(spec, [[1, 0], [2, 0]], coef)
+    big = sgheat.Spec(w.dim, w.n_cells_1d, w.fe_degree, w.time_degree, w.tau, 4, 7, w.n_levels)   # 330 modes x 2
+    coef1 = [np.ones((1, (w.n_cells_1d >> l) ** w.dim, nq)) for l in range(w.n_levels)]
+    with pytest.raises(sgheat.SgError, match="SG_EUNSUPPORTED"):
+        sgheat.Problem(big, [[0, 0, 0, 0]], coef1)
