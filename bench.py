@@ -32,12 +32,13 @@ APPLY_SOURCES = ["device_common.hpp", "kernels.hpp", "apply_impl.hpp", "apply_3d
                  "kernels_apply.hip", "kernels_misc.hip"]
 
 # HBM bytes per operator apply from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (k_apply + k_node_gather),
-# each scaled by what the same counter reads for a plain device copy of known size.  Keyed by workload
-# and by the hash of the kernel sources the counters were taken on: after any change to those
-# sources the entry no longer matches and the traffic is reported as null until it is measured again.
+# each scaled by what the same counter reads for a plain device copy of known size.  Keyed by workload,
+# by the hash of the kernel sources the counters were taken on and by the apply's cells per workgroup:
+# after any change to those the entry no longer matches and the traffic is reported as null until it
+# is measured again.
 MEASURED_TRAFFIC = {
     # profiles/sg_apply_c2_hbm_traffic.md
-    ("c2", "c65e3ee9ae8aef0e"): {"fetch_bytes": 859779665, "write_bytes": 822180009},
+    ("c2", "c65e3ee9ae8aef0e", 3): {"fetch_bytes": 859779665, "write_bytes": 822180009},
 }
 
 
@@ -281,6 +282,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient timing (16^3 cells, 10 slabs)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the occupancy-based apply tiles")
     ap.add_argument("--no-batch", action="store_true", help="skip the Monte-Carlo batch timing (256 samples, 20 slabs)")
     ap.add_argument("--only-apply", action="store_true", help="skip the solves (for profiling the apply)")
     ap.add_argument("--finite-chaos", type=int, default=-1, metavar="P",
@@ -312,6 +314,8 @@ def main():
     G = sgheat.problem_from_workload(w, sgheat.SG_FP64)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
+    tiles = G.autotune(reps=10) if not args.no_autotune else None
+    cpb = tiles["fp64_full"] if tiles else int(os.environ.get("SGHEAT_APPLY_CPB", "0")) or None
     n = G.n(0)
     print(f"[bench] {args.workload}: {n} DoFs, setup {setup_s:.2f} s", file=sys.stderr, flush=True)
 
@@ -340,7 +344,7 @@ def main():
     del xs, ys
     copy_gbs = copy_bandwidth(torch, dev)
     src_hash = apply_source_hash()
-    meas = MEASURED_TRAFFIC.get((args.workload, src_hash))
+    meas = MEASURED_TRAFFIC.get((args.workload, src_hash, cpb))
     traffic = meas["fetch_bytes"] + meas["write_bytes"] if meas else None
     print(f"[bench] device copy {copy_gbs:.0f} GB/s; apply sources {src_hash}", file=sys.stderr, flush=True)
 
@@ -356,12 +360,13 @@ def main():
                         "unit": "TFLOP/s", "frac": round(achieved_tf / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
                         "kernel": "operator apply: k_apply then k_node_gather, one stream, median of "
                                   f"{args.apply_reps} HIP-event-timed applies",
-                        "algorithmic_flops_per_apply": aflops, "source_hash": src_hash},
+                        "algorithmic_flops_per_apply": aflops, "source_hash": src_hash, "cells_per_workgroup": cpb},
            "roofline_hbm": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                             "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                             "algorithmic_bytes_per_apply": abytes,
                             "measured_frac": (round(traffic / t_apply / 1e9 / HBM_PEAK_GBS, 4) if traffic else None)},
            "copy_gbs": round(copy_gbs, 1),
+           "apply_tiles": tiles,
            "setup_s": round(setup_s, 2)}
 
     # ---- slab solves -------------------------------------------------------------------------------
@@ -399,6 +404,8 @@ def main():
         print(f"[bench] fp64 solve {res['fp64_ms']} ms, {res['fp64_iterations']} it", file=sys.stderr, flush=True)
         if not args.no_mixed:
             G32 = sgheat.problem_from_workload(w, sgheat.SG_MIXED)
+            if not args.no_autotune:
+                res["mixed_tiles"] = G32.autotune(reps=10)
             run_solves(G32, args.warmup)
             t32, i32 = run_solves(G32, args.steps)
             err = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))

@@ -288,6 +288,16 @@ sg_status sg_moment_errors(sg_handle h, const double* acc, long long n_tot, int 
                            const double* theta, const double* mean_targets, const double* var_targets, double* out,
                            void* hip_stream);
 
+/* Tile autotuner of the operator kernel: for the full operator on level 0 and the mean-block operator
+ * on every level (and their FP32 versions with SG_MIXED), times `reps` launches of the cell kernel for
+ * every feasible number of cells per workgroup (1, 2, 3, 4, 5, 6, 8, 10, 12, 16; limited by 512 threads
+ * and 160 KB of LDS per workgroup) on this handle's own sizes and keeps the fastest (median) for all
+ * later calls.  Without it the number comes from the runtime occupancy calculator.  The
+ * SGHEAT_APPLY_CPB environment variable, if set, overrides both.  cpb_out (may be NULL) receives
+ * [2 (FP64, FP32)][2 (mean, full)][n_levels] choices (0 = not tuned).  Synchronous; uses the handle's
+ * level work vectors, so no other call on the handle may run meanwhile. */
+sg_status sg_autotune(sg_handle h, int reps, int* cpb_out, void* hip_stream);
+
 /* Message for the last non-OK status returned on the calling thread ("" if none). */
 const char* sg_last_error(void);
 

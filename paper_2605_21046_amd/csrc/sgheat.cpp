@@ -130,6 +130,7 @@ struct sg_handle_s {
     DevBuf<double> elem_E, elem_M;             // element matrices of the patch set-up (reused)
     DevBuf<double> sepW, errC, errPart, errOut;  // separable weights, error-sum work arrays
     DevBuf<double> momPart;                      // moment-error partial sums
+    int tuned_cpb[2][2][16] = {};                // apply cells per workgroup from sg_autotune: [FP32][full][level]
     std::vector<double> hstage;
     std::vector<double> trip;                 // E[Psi_a Psi_b Psi_eps], [n_xi][n_xi][n_eps]
     int n_eps = 0;
@@ -682,12 +683,51 @@ ApplyOp<T> make_op(const sg_handle h, int level, bool full) {
         if (cnt == 1 && nz < 8 && h->coef_mu[k * h->d.n_vars + nz] == 1) op.mum[nz] = k;
     }
     op.cells_per_block = apply_cpb_override();
+    if (op.cells_per_block == 0 && level < 16) op.cells_per_block = h->tuned_cpb[sizeof(T) == 4][full][level];
     return op;
 }
 
 template <typename T>
 T* sbuf_as(sg_handle h) {
     return reinterpret_cast<T*>(h->sbuf.p);
+}
+
+// Time k_apply alone for every feasible cells-per-workgroup value on one level and keep the fastest
+// (median of `reps` event-timed launches each).
+template <typename T>
+sg_status autotune_apply(sg_handle h, int level, bool full, int reps, hipStream_t s) {
+    Level& lv = h->lv[level];
+    ApplyOp<T> op = make_op<T>(h, level, full);
+    T* x = Prec<T>::x(lv);
+    SG_HIP(hipMemsetAsync(x, 0, sizeof(T) * lv.len, s));
+    std::vector<hipEvent_t> ev(reps + 1);
+    for (auto& e : ev) SG_HIP(hipEventCreate(&e));
+    int best = 0;
+    float best_ms = 0.0f;
+    sg_status st = SG_OK;
+    static const int kCand[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
+    for (int cpb : kCand) {
+        if (cpb > lv.g.n) break;
+        op.cells_per_block = cpb;
+        hipError_t err = launch_apply<T>(op, x, sbuf_as<T>(h), s);
+        if (err == hipErrorInvalidConfiguration) continue;     // more threads or LDS than one workgroup has
+        if (err != hipSuccess) { st = fail(SG_EHIP, std::string("autotune: ") + hipGetErrorString(err)); break; }
+        (void)launch_apply<T>(op, x, sbuf_as<T>(h), s);
+        (void)hipEventRecord(ev[0], s);
+        for (int r = 0; r < reps; ++r) {
+            (void)launch_apply<T>(op, x, sbuf_as<T>(h), s);
+            (void)hipEventRecord(ev[r + 1], s);
+        }
+        if (hipEventSynchronize(ev[reps]) != hipSuccess) { st = fail(SG_EHIP, "autotune: event"); break; }
+        std::vector<float> t(reps);
+        for (int r = 0; r < reps; ++r) (void)hipEventElapsedTime(&t[r], ev[r], ev[r + 1]);
+        std::nth_element(t.begin(), t.begin() + reps / 2, t.end());
+        const float med = t[reps / 2];
+        if (best == 0 || med < best_ms) { best = cpb; best_ms = med; }
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (st == SG_OK && level < 16) h->tuned_cpb[sizeof(T) == 4][full][level] = best;
+    return st;
 }
 
 // y = A x (b == nullptr) or y = b - A x, for the operator described by op
@@ -1426,6 +1466,23 @@ sg_status sg_moment_errors(sg_handle h, const double* acc, long long n_tot, int 
     SG_HIP(launch_reduce_partials(h->momPart.p, (int)l0.g.n_cells, 6, h->errOut.p, s));
     SG_HIP(hipMemcpyAsync(out, h->errOut.p, sizeof(double) * 6, hipMemcpyDeviceToHost, s));
     SG_HIP(hipStreamSynchronize(s));
+    return SG_OK;
+}
+
+sg_status sg_autotune(sg_handle h, int reps, int* cpb_out, void* hip_stream) {
+    if (!h) return fail(SG_EINVAL, "null argument");
+    if (reps < 1 || reps > 1000) return fail(SG_EINVAL, "reps must be in 1..1000");
+    const hipStream_t s = (hipStream_t)hip_stream;
+    const int L = std::min(h->d.n_levels, 16);
+    SG_TRY(autotune_apply<double>(h, 0, true, reps, s));
+    for (int l = 0; l < L; ++l) SG_TRY(autotune_apply<double>(h, l, false, reps, s));
+    if (h->mixed)
+        for (int l = 0; l < L; ++l) SG_TRY(autotune_apply<float>(h, l, false, reps, s));
+    if (cpb_out)
+        for (int p = 0; p < 2; ++p)
+            for (int f = 0; f < 2; ++f)
+                for (int l = 0; l < h->d.n_levels; ++l)
+                    cpb_out[(p * 2 + f) * h->d.n_levels + l] = l < 16 ? h->tuned_cpb[p][f][l] : 0;
     return SG_OK;
 }
 

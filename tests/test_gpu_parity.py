@@ -217,3 +217,24 @@ def test_argument_errors(torch_cuda):
     coef1 = [np.ones((1, (w.n_cells_1d >> l) ** w.dim, nq)) for l in range(w.n_levels)]
     with pytest.raises(sgheat.SgError, match="SG_EUNSUPPORTED"):
         sgheat.Problem(big, [[0, 0, 0, 0]], coef1)
+
+
+@pytest.mark.parametrize("name", ["c1", "t3q2", "t2q3"])
+def test_autotuned_tiles_keep_results_bitwise(torch_cuda, name):
+    """Every thread computes one (cell, component) and the gather sums in a fixed order, so the tile
+    chosen by the autotuner must not change a single bit of the apply."""
+    torch = torch_cuda
+    w = sg_inputs.WORKLOADS[name]
+    G = _gpu(w)
+    x = torch.from_numpy(sg_inputs.uniform_vector(G.n(0), 51)).to("cuda")
+    y0 = G.apply(x).clone()
+    chosen = G.autotune(reps=3)
+    print(name, chosen, flush=True)
+    assert chosen["fp64_full"] in (1, 2, 3, 4, 5, 6, 8, 10, 12, 16)
+    y1 = G.apply(x)
+    assert torch.equal(y0, y1)
+    P = from_workload(w)
+    assert _rel_inf(y1.cpu().numpy(), P.apply_route1(x.cpu().numpy())) <= 1e-12
+    b = torch.from_numpy(sg_inputs.interior_target(w)).to("cuda")
+    _, info = G.solve(G.apply(b), rtol=1e-10)
+    assert info["converged"]
