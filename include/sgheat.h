@@ -288,6 +288,15 @@ sg_status sg_moment_errors(sg_handle h, const double* acc, long long n_tot, int 
                            const double* theta, const double* mean_targets, const double* var_targets, double* out,
                            void* hip_stream);
 
+/* Replay the V-cycle (gmg_vcycle, and the preconditioner inside fgmres_solve_slab) from a HIP graph
+ * (enable = 1) or launch it kernel by kernel (0, the default).  With the graph, each V-cycle copies r
+ * into the handle's level-0 work vector, replays the captured cycle and copies the result to z; the
+ * graph is captured on the second V-cycle after enabling (the first runs kernel by kernel) on a stream
+ * of the handle's own, and dropped by sg_update_coefficients, sg_autotune and enable = 0.  Results are
+ * bitwise those of the kernel-by-kernel cycle.  It pays for small problems, where launching the tens
+ * of kernels of a cycle costs more than running them.  Host only. */
+sg_status sg_set_vcycle_graph(sg_handle h, int enable);
+
 /* Tile autotuner of the operator kernel: for the full operator on level 0 and the mean-block operator
  * on every level (and their FP32 versions with SG_MIXED), times `reps` launches of the cell kernel for
  * every feasible number of cells per workgroup (1, 2, 3, 4, 5, 6, 8, 10, 12, 16; limited by 512 threads

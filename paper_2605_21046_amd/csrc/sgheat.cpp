@@ -131,6 +131,23 @@ struct sg_handle_s {
     DevBuf<double> sepW, errC, errPart, errOut;  // separable weights, error-sum work arrays
     DevBuf<double> momPart;                      // moment-error partial sums
     int tuned_cpb[2][2][16] = {};                // apply cells per workgroup from sg_autotune: [FP32][full][level]
+    // V-cycle replayed from a HIP graph (sg_set_vcycle_graph): captured on the level-0 work vectors
+    bool graph_on = false;
+    int graph_calls = 0;
+    hipGraph_t vgraph = nullptr;
+    hipGraphExec_t vgraph_exec = nullptr;
+    hipStream_t cap_stream = nullptr;
+    void drop_graph() {
+        if (vgraph_exec) (void)hipGraphExecDestroy(vgraph_exec);
+        if (vgraph) (void)hipGraphDestroy(vgraph);
+        vgraph_exec = nullptr;
+        vgraph = nullptr;
+        graph_calls = 0;
+    }
+    ~sg_handle_s() {
+        drop_graph();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
     std::vector<double> hstage;
     std::vector<double> trip;                 // E[Psi_a Psi_b Psi_eps], [n_xi][n_xi][n_eps]
     int n_eps = 0;
@@ -826,12 +843,56 @@ sg_status vcycle_level(sg_handle h, int l, const T* b, T* x, hipStream_t s) {
     return SG_OK;
 }
 
-sg_status vcycle(sg_handle h, const double* r, double* z, hipStream_t s) {
-    if (!h->mixed) return vcycle_level<double>(h, 0, r, z, s);
+// The V-cycle on the level-0 work vectors (b -> x), the part a graph replays.
+sg_status vcycle_fixed(sg_handle h, hipStream_t s) {
     Level& l0 = h->lv[0];
-    SG_HIP((launch_convert<double, float>(r, l0.b32.p, l0.len, s)));
-    SG_TRY(vcycle_level<float>(h, 0, l0.b32.p, l0.x32.p, s));
-    SG_HIP((launch_convert<float, double>(l0.x32.p, z, l0.len, s)));
+    if (!h->mixed) return vcycle_level<double>(h, 0, l0.b64.p, l0.x64.p, s);
+    return vcycle_level<float>(h, 0, l0.b32.p, l0.x32.p, s);
+}
+
+// Capture vcycle_fixed into a graph on the handle's own stream (nothing runs during capture).
+sg_status capture_vcycle(sg_handle h) {
+    if (!h->cap_stream) SG_HIP(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    SG_HIP(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    const sg_status st = vcycle_fixed(h, h->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+    if (st != SG_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess || !g) return fail(SG_EHIP, std::string("V-cycle capture: ") + hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(SG_EHIP, std::string("V-cycle graph: ") + hipGetErrorString(ie));
+    }
+    h->vgraph = g;
+    h->vgraph_exec = ex;
+    return SG_OK;
+}
+
+sg_status vcycle(sg_handle h, const double* r, double* z, hipStream_t s) {
+    Level& l0 = h->lv[0];
+    if (!h->graph_on) {
+        if (!h->mixed) return vcycle_level<double>(h, 0, r, z, s);
+        SG_HIP((launch_convert<double, float>(r, l0.b32.p, l0.len, s)));
+        SG_TRY(vcycle_level<float>(h, 0, l0.b32.p, l0.x32.p, s));
+        SG_HIP((launch_convert<float, double>(l0.x32.p, z, l0.len, s)));
+        return SG_OK;
+    }
+    // graph path: r into the level-0 work vector, the captured cycle, the result out
+    if (!h->mixed) SG_HIP(hipMemcpyAsync(l0.b64.p, r, sizeof(double) * l0.len, hipMemcpyDeviceToDevice, s));
+    else SG_HIP((launch_convert<double, float>(r, l0.b32.p, l0.len, s)));
+    if (h->graph_calls++ == 0) {
+        SG_TRY(vcycle_fixed(h, s));            // first call eagerly (fills the launch caches), then capture
+        SG_TRY(capture_vcycle(h));
+    } else {
+        SG_HIP(hipGraphLaunch(h->vgraph_exec, s));
+    }
+    if (!h->mixed) SG_HIP(hipMemcpyAsync(z, l0.x64.p, sizeof(double) * l0.len, hipMemcpyDeviceToDevice, s));
+    else SG_HIP((launch_convert<float, double>(l0.x32.p, z, l0.len, s)));
     return SG_OK;
 }
 
@@ -1109,6 +1170,8 @@ sg_status fgmres_solve_slab(sg_handle h, const double* b, double* x, double rtol
 sg_status sg_update_coefficients(sg_handle h, const double* coef_qp) {
     if (!h || !coef_qp) return fail(SG_EINVAL, "null argument");
     try {
+        (void)hipDeviceSynchronize();
+        h->drop_graph();                       // the graph holds the set-up's buffers and tiles
         return set_coefficients(h, coef_qp);
     } catch (const std::bad_alloc&) {
         return fail(SG_ENOMEM, "host allocation failed during the coefficient update");
@@ -1469,11 +1532,23 @@ sg_status sg_moment_errors(sg_handle h, const double* acc, long long n_tot, int 
     return SG_OK;
 }
 
+sg_status sg_set_vcycle_graph(sg_handle h, int enable) {
+    if (!h || (enable != 0 && enable != 1)) return fail(SG_EINVAL, "bad argument");
+    if (!enable) {
+        (void)hipDeviceSynchronize();
+        h->drop_graph();
+    }
+    h->graph_on = enable == 1;
+    return SG_OK;
+}
+
 sg_status sg_autotune(sg_handle h, int reps, int* cpb_out, void* hip_stream) {
     if (!h) return fail(SG_EINVAL, "null argument");
     if (reps < 1 || reps > 1000) return fail(SG_EINVAL, "reps must be in 1..1000");
     const hipStream_t s = (hipStream_t)hip_stream;
     const int L = std::min(h->d.n_levels, 16);
+    SG_HIP(hipStreamSynchronize(s));
+    h->drop_graph();                           // a captured V-cycle would keep the old tiles
     SG_TRY(autotune_apply<double>(h, 0, true, reps, s));
     for (int l = 0; l < L; ++l) SG_TRY(autotune_apply<double>(h, l, false, reps, s));
     if (h->mixed)

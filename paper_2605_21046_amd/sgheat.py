@@ -22,7 +22,7 @@ EXPORTS = ["sg_create", "sg_destroy", "sg_vector_length", "sg_operator_apply", "
            "gmg_vcycle", "fgmres_solve_slab", "sg_quadrature_points", "sg_node_coordinates", "sg_update_coefficients", "sg_operator_apply_T",
            "sg_slab_transfer", "sg_stiffness_form_cells", "sg_qoi_mean_var", "sg_sample_statistics", "sg_chaos_moments", "sg_gauss_points", "sg_index_set", "sg_chaos_projection",
            "sg_time_rule", "sg_time_load_weights", "sg_load_vectors", "sg_separable_vector", "sg_separable_error",
-           "sg_sample_psi", "sg_sample_qp_moments", "sg_moment_errors", "sg_autotune", "sg_last_error"]
+           "sg_sample_psi", "sg_sample_qp_moments", "sg_moment_errors", "sg_autotune", "sg_set_vcycle_graph", "sg_last_error"]
 
 
 class SgError(RuntimeError):
@@ -86,6 +86,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sg_separable_error.argtypes = [P, V, I, V, V, I, PD, PD, D, PD, V]
     lib.sg_sample_psi.argtypes = [P, I, PI, PD]
     lib.sg_autotune.argtypes = [P, I, PI, V]
+    lib.sg_set_vcycle_graph.argtypes = [P, I]
     lib.sg_sample_qp_moments.argtypes = [P, V, I, I, V, V]
     lib.sg_moment_errors.argtypes = [P, V, ctypes.c_longlong, I, V, I, PD, PD, PD, PD, V]
     lib.sg_last_error.restype = ctypes.c_char_p
@@ -376,6 +377,10 @@ class Problem:
                                        _ptr(gs_qp, n_cells * nq * self.spec.dim, "gs_qp"), th.size, _dp(th), _dp(cc),
                                        float(C2), _dp(out), _stream(stream)))
         return out
+
+    def set_vcycle_graph(self, enable: bool = True):
+        """Replay the V-cycle from a HIP graph (captured on first use) instead of launching its kernels."""
+        _check(_lib.sg_set_vcycle_graph(self._h, int(bool(enable))))
 
     def autotune(self, reps: int = 20, stream=None) -> dict:
         """Time the cell kernel's workgroup tiles on this handle and keep the fastest; returns the choices."""

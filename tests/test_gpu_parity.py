@@ -238,3 +238,31 @@ def test_autotuned_tiles_keep_results_bitwise(torch_cuda, name):
     b = torch.from_numpy(sg_inputs.interior_target(w)).to("cuda")
     _, info = G.solve(G.apply(b), rtol=1e-10)
     assert info["converged"]
+
+
+@pytest.mark.parametrize("name,precision", [("c1", 0), ("t3q2", 1), ("t2q3", 0)])
+def test_vcycle_graph_replays_match_the_kernel_by_kernel_cycle(torch_cuda, name, precision):
+    """Every replay of the captured V-cycle, with eager work and synchronisations between replays,
+    equals the kernel-by-kernel cycle bit for bit; so does a whole FGMRES solve."""
+    torch = torch_cuda
+    w = sg_inputs.WORKLOADS[name]
+    print(f"V-cycle graph {name} precision {precision}", flush=True)
+    G = _gpu(w, precision)
+    Gg = _gpu(w, precision)
+    Gg.set_vcycle_graph(True)
+    n = G.n(0)
+    for k in range(6):
+        r = torch.from_numpy(sg_inputs.uniform_vector(n, 60 + k)).to("cuda")
+        z0 = G.vcycle(r)
+        junk = torch.ones(1 << 20, dtype=torch.float64, device="cuda").cumsum(0)   # eager work between replays
+        z1 = Gg.vcycle(r)
+        torch.cuda.synchronize()
+        assert torch.equal(z0, z1), f"replay {k}"
+        del junk
+    b = G.apply(torch.from_numpy(sg_inputs.interior_target(w)).to("cuda"))
+    x0, i0 = G.solve(b, rtol=1e-10)
+    x1, i1 = Gg.solve(b, rtol=1e-10)
+    assert i0["iterations"] == i1["iterations"]
+    assert torch.equal(x0, x1)
+    Gg.set_vcycle_graph(False)
+    assert torch.equal(Gg.vcycle(r), G.vcycle(r))
