@@ -223,7 +223,7 @@ __device__ __forceinline__ void couple_point(T* rows, const T* crow, int q, int 
 }
 
 // Points u_q of one (cell, component) at the Gauss points are in U; W accumulates the integrand.
-template <int DIM, int K, int NT, typename T, bool MEAN, int CM, int CP>
+template <int DIM, int K, int NT, typename T, bool MEAN, int CM, int CP, bool WIDE = false>
 __device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const Tables<T>& tb, T (&U)[ipow(K + 1, DIM)],
                                            T (&W)[ipow(K + 1, DIM)], T* slot_rows, const T* slot_coef,
                                            const int* ent_g, const int* ent_c, const T* ent_w, int e0, int e1,
@@ -351,9 +351,10 @@ __device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const Tables<T
                 for (int j = 0; j < NS; ++j) F[j] = T(0);
 #pragma unroll 1
                 for (int e = e0; e < e1; ++e) {
-                    const T w = ent_w[e];
-                    const T* cp = slot_coef + ent_c[e];
-                    const T* gp = slot_rows + ent_g[e] + ti * NP;
+                    // entries from LDS, or (wide workgroups, whose LDS holds only the rows) from memory
+                    const T w = WIDE ? a.cw[e] : ent_w[e];
+                    const T* cp = slot_coef + (WIDE ? a.cmu[e] * NP : ent_c[e]);
+                    const T* gp = slot_rows + (WIDE ? a.cbeta[e] * NT * NP : ent_g[e]) + ti * NP;
 #pragma unroll
                     for (int j = 0; j < NS; ++j) {
                         const int q = (j / st) * st * N1 + s * st + (j % st);
@@ -391,9 +392,11 @@ __host__ __device__ constexpr int padded_stride(int n) {
     return n + ((1 - n) % nb + nb) % nb;
 }
 
-template <int DIM, int K, int NT, typename T, bool MEAN, int CM = 0, int CP = 0>
-__global__ void __launch_bounds__(ipow(K + 1, DIM) > 27 ? 256 : 512)
-    __attribute__((amdgpu_waves_per_eu(apply_waves_per_eu<ipow(K + 1, DIM), T>())))
+// WIDE: one cell per workgroup of up to 1024 threads (N_xi N_t > 512 components), coupling entries
+// read from memory instead of LDS.
+template <int DIM, int K, int NT, typename T, bool MEAN, int CM = 0, int CP = 0, bool WIDE = false>
+__global__ void __launch_bounds__(WIDE ? 1024 : (ipow(K + 1, DIM) > 27 ? 256 : 512))
+    __attribute__((amdgpu_waves_per_eu(WIDE ? 4 : apply_waves_per_eu<ipow(K + 1, DIM), T>())))
     k_apply(ApplyArgs<T> a, Tables<T> tb) {
     constexpr int N1 = K + 1;
     constexpr int NP = ipow(N1, DIM);
@@ -442,7 +445,7 @@ __global__ void __launch_bounds__(ipow(K + 1, DIM) > 27 ? 256 : 512)
         cl[s * CS + mu * NP + q] = (x0 + s < n) ? a.coef[mu * a.coef_mode_stride + c2 * NP + q] : T(0);
     }
     // stage the coupling entries (beta, mu, w) as LDS offsets
-    if constexpr (!MEAN && CM == 0) {
+    if constexpr (!MEAN && CM == 0 && !WIDE) {
         for (int e = t; e < a.n_ent; e += nthreads) {
             ent_w[e] = a.cw[e];
             ent_g[e] = a.cbeta[e] * NT * NP;
@@ -478,7 +481,7 @@ __global__ void __launch_bounds__(ipow(K + 1, DIM) > 27 ? 256 : 512)
     const T* const slot_coef = cl + (size_t)slot * CS;
     // values at the Gauss points, then the rest of the cell work
     sweeps_ip<DIM, N1, false>(A, tb.S);
-    apply_body<DIM, K, NT, T, MEAN, CM, CP>(a, tb, A, B, slot_rows, slot_coef, ent_g, ent_c, ent_w, e0, e1, comp, alpha,
+    apply_body<DIM, K, NT, T, MEAN, CM, CP, WIDE>(a, tb, A, B, slot_rows, slot_coef, ent_g, ent_c, ent_w, e0, e1, comp, alpha,
                                             ti, active, cc, exch, cl, SS, CS, active ? ci : 0);
 }
 
@@ -568,6 +571,38 @@ hipError_t run_apply(const ApplyOp<T>& op, const T* x, T* s_out, hipStream_t s) 
     for (int m = 0; m < 8; ++m) a.mum[m] = op.mum[m];
     const int nc = op.n_xi * NT;
     const size_t per_cell = (size_t)(padded_stride<T>(nc * NP) + padded_stride<T>(op.n_mu * NP)) * sizeof(T);
+    if (nc > MAXT) {
+        // more components than one regular workgroup: one cell per workgroup of nc <= 1024 threads (2D)
+        if constexpr (DIM == 2) {
+            auto wk = op.mean ? k_apply<DIM, K, NT, T, true, 0, 0, true> : k_apply<DIM, K, NT, T, false, 0, 0, true>;
+            ApplyArgs<T> a{};
+            a.x = x;
+            a.s = s_out;
+            a.coef = op.coef;
+            a.coef_mode_stride = op.coef_mode_stride;
+            a.cptr = op.cptr;
+            a.cbeta = op.cbeta;
+            a.cmu = op.cmu;
+            a.cw = op.cw;
+            a.n_xi = op.n_xi;
+            a.n_mu = op.n_mu;
+            a.n_ent = op.n_ent;
+            a.g = op.g;
+            a.mu0 = op.mu0;
+            for (int m = 0; m < 8; ++m) a.mum[m] = op.mum[m];
+            a.cpb = 1;
+            const size_t lds = per_cell + 16;
+            if (nc > 1024 || lds > 160 * 1024) return hipErrorInvalidConfiguration;
+            if (lds > 64 * 1024)
+                (void)hipFuncSetAttribute((const void*)wk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            const long long blocks = op.g.n_cells;
+            a.nblocks = (int)blocks;
+            hipLaunchKernelGGL(wk, dim3((unsigned)blocks), dim3(nc), lds, s, a, *op.tables);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidConfiguration;
+        }
+    }
     const size_t fixed = op.mean ? 16 : (size_t)op.n_ent * (sizeof(T) + 2 * sizeof(int)) + 16;
     const int cpb = op.cells_per_block > 0 ? op.cells_per_block : choose_cpb((const void*)kern, nc, fixed, per_cell, MAXT);
     a.cpb = cpb;

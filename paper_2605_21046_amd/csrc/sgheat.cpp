@@ -442,10 +442,18 @@ sg_status build(sg_handle h) {
     h->n_xi = h->cpl.n_xi;
     h->n_mu = d.n_coef_modes;
     h->npp = h->NT * h->NP;
-    if (h->n_xi * h->NT * 1 > 512) return fail(SG_EUNSUPPORTED, "N_xi * N_t must be <= 512");
+    // one thread per (cell, component) in the operator kernel: up to 512 threads per workgroup (256 for
+    // more than 27 points per cell), or one cell per workgroup of up to 1024 threads in 2D
+    const int nc = h->n_xi * h->NT;
+    const int maxt = h->NP > 27 ? 256 : 512;
+    const bool wide = nc > maxt;
+    if (nc > (dim == 2 ? 1024 : maxt))
+        return fail(SG_EUNSUPPORTED, dim == 2 ? "N_xi * N_t must be <= 1024 in 2D"
+                                              : (maxt == 512 ? "N_xi * N_t must be <= 512 in 3D for k <= 2"
+                                                             : "N_xi * N_t must be <= 256 in 3D for k >= 3"));
     if (h->npp > 256) return fail(SG_EUNSUPPORTED, "Vanka patches larger than 256 DoFs are not supported");
     {
-        const size_t n_ent_max = h->cpl.beta.size();
+        const size_t n_ent_max = wide ? 1 : h->cpl.beta.size();   // wide workgroups read the entries from memory
         const size_t lds_apply = (size_t)(h->n_xi * h->NT + h->n_mu) * h->NP * sizeof(double) + n_ent_max * 16;
         const size_t lds_vanka = vanka_lds_bytes(h->npp, sizeof(double));
         if (lds_apply > 160 * 1024 || lds_vanka > 160 * 1024)

@@ -213,7 +213,7 @@ def test_argument_errors(torch_cuda):
     coef = [np.ones((2, (w.n_cells_1d >> l) ** w.dim, nq)) for l in range(w.n_levels)]
     with pytest.raises(sgheat.SgError, match="SG_EINVAL"):
         sgheat.Problem(spec, [[1, 0], [2, 0]], coef)
-    big = sgheat.Spec(w.dim, w.n_cells_1d, w.fe_degree, w.time_degree, w.tau, 4, 7, w.n_levels)   # 330 modes x 2
+    big = sgheat.Spec(w.dim, w.n_cells_1d, w.fe_degree, w.time_degree, w.tau, 4, 9, w.n_levels)   # 715 modes x 2
     coef1 = [np.ones((1, (w.n_cells_1d >> l) ** w.dim, nq)) for l in range(w.n_levels)]
     with pytest.raises(sgheat.SgError, match="SG_EUNSUPPORTED"):
         sgheat.Problem(big, [[0, 0, 0, 0]], coef1)
@@ -266,3 +266,30 @@ def test_vcycle_graph_replays_match_the_kernel_by_kernel_cycle(torch_cuda, name,
     assert torch.equal(x0, x1)
     Gg.set_vcycle_graph(False)
     assert torch.equal(Gg.vcycle(r), G.vcycle(r))
+
+
+@pytest.mark.parametrize("field", ["sine", "finite"])
+def test_wide_workgroups_match_oracle(torch_cuda, field):
+    """840 components per cell (M = 4, p_xi = 6, dG(3)) exceed one regular workgroup: one cell per
+    workgroup of 840 threads, coupling entries from memory.  Apply against the oracle's Kronecker route
+    (1e-12) and an FGMRES solve whose true residual the oracle recomputes."""
+    torch = torch_cuda
+    from paper_2605_21046_amd import sgheat
+    if field == "finite":
+        w = sg_inputs.finite_chaos_workload(2, 3, 3, 8, 6, 1).base
+    else:
+        w = sg_inputs.Workload("w2", 2, 2, 3, 3, 0.05, 4, 6, 1, "sine")
+    print(f"wide workgroups {field}: {w.n_chaos} modes x {w.n_time}", flush=True)
+    G = sgheat.problem_from_workload(w)
+    P = from_workload(w)
+    assert P.n_xi * P.n_t == 840
+    x = sg_inputs.uniform_vector(P.n, 71)
+    y = G.apply(torch.from_numpy(x).to("cuda")).cpu().numpy()
+    assert _rel_inf(y, P.apply_route2(x)) <= 1e-12
+    b = 0.1 * sg_inputs.uniform_vector(P.n, 72)
+    b[P.full_boundary_mask()] = 0.0
+    xs, info = G.solve(torch.from_numpy(b).to("cuda"), rtol=1e-10, max_iter=800)
+    assert info["converged"]
+    r = b - P.apply_route2(xs.cpu().numpy())
+    assert np.linalg.norm(r) <= 1.0001e-10 * np.linalg.norm(b)
+    G.close()
