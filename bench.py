@@ -255,6 +255,50 @@ def finite_chaos_table(torch, p_max, n_cells=128, n_slabs=64, n_levels=5, march_
                         f"{done} of {n_slabs} slabs marched, M=4, q=6, eta=0.35, slab solves to rtol 1e-10", "rows": rows}
 
 
+def mc_root_n(torch, name="c7"):
+    """Monte-Carlo error split of the finite-chaos benchmark over cumulative sample windows (the first
+    k handles of 128 samples), with the observed rates r = log(E_N0 / E_N) / log(N / N0) against the
+    first window."""
+    import sg_inputs
+    from paper_2605_21046_amd.mcerrors import MCErrorStudy
+    ew = sg_inputs.MC_ERROR_WORKLOADS[name]
+    w = ew.base
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S = MCErrorStudy(ew, rtol=1e-10)
+    rows = S.run(windows=True, progress=lambda n: print(f"[bench] Monte-Carlo windows: slab {n} done", file=sys.stderr,
+                                                      flush=True))
+    torch.cuda.synchronize()
+    its = [i["iterations"] for i in S.info]
+    G = np.concatenate(S.G)
+    C2 = S.C2
+    S.close()
+    # ||phi|| over the space-time domain, from the first window (mc_mean = |g_bar - 1| ||phi||)
+    phi = rows[0]["mc_mean"] / abs(float(np.mean(G[: rows[0]["N"]])) - 1.0)
+    groups = []
+    size = rows[0]["N"]
+    while size <= len(G):
+        k = len(G) // size
+        gb = G[: k * size].reshape(k, size).mean(axis=1)
+        # pure sampling error of the mean: RMS over k disjoint groups of `size` samples, and the
+        # Hilbert-space root-N lemma's value ||phi|| sqrt(Var[G_q] / N) with Var[G_q] = C2
+        groups.append({"N": size, "groups": k, "rms_mc_mean": float(f"{phi * math.sqrt(np.mean((gb - 1.0) ** 2)):.5e}"),
+                       "lemma_rms_mc_mean": float(f"{phi * math.sqrt(C2 / size):.5e}")})
+        size *= 2
+    r0 = rows[0]
+    for r in rows[1:]:
+        for key in ["tot_mean", "mc_mean", "tot_var", "mc_var"]:
+            r[f"rate_{key}"] = round(math.log(r0[key] / r[key]) / math.log(r["N"] / r0["N"]), 4)
+    for r in rows:
+        for key in ["tot_mean", "disc_mean", "mc_mean", "tot_var", "disc_var", "mc_var"]:
+            r[key] = float(f"{r[key]:.5e}")
+    return {"workload": f"{name}: finite-chaos benchmark pathwise, 2D Q{w.fe_degree} on {w.n_cells_1d}^2 cells of (-1,1)^2, "
+                        f"dG({w.time_degree}), {ew.n_slabs} slabs (h = tau), {ew.n_samples} samples (seed {ew.seed}) in "
+                        f"handles of {ew.batch}, slab solves to rtol 1e-10",
+            "wall_s": round(time.perf_counter() - t0, 1), "iterations_per_slab": [min(its), max(its)], "windows": rows,
+            "disjoint_groups": groups}
+
+
 def copy_bandwidth(torch, dev, reps=20):
     """Achievable HBM bandwidth of a plain device copy over two disjoint 1 GiB buffer pairs."""
     n = 1 << 27
@@ -288,6 +332,8 @@ def main():
     ap.add_argument("--only-apply", action="store_true", help="skip the solves (for profiling the apply)")
     ap.add_argument("--finite-chaos", type=int, default=-1, metavar="P",
                     help="also run the finite-chaos benchmark for p_xi = 0..P at the paper's discretisation")
+    ap.add_argument("--mc-rootn", action="store_true",
+                    help="also run the Monte-Carlo error split over cumulative windows of 128..2048 samples")
     ap.add_argument("--fc-slabs", type=int, default=None, metavar="N",
                     help="march only the first N of the 64 slabs of the finite-chaos benchmark (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -438,6 +484,10 @@ def main():
 
     if args.finite_chaos >= 0:
         out["finite_chaos"] = finite_chaos_table(torch, args.finite_chaos, march_slabs=args.fc_slabs)
+
+    if args.mc_rootn:
+        out["mc_root_n"] = mc_root_n(torch)
+        print(f"[bench] Monte-Carlo root-N windows: {out['mc_root_n']['windows']}", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)

@@ -82,15 +82,26 @@ class MCErrorStudy:
         W[1:] = (g[:, None] * pm).T[:, :, None] * T[1][None, None, :]
         return W
 
-    def run(self):
-        """March every handle; returns the six errors (dict) of the estimators over all slabs."""
+    def run(self, windows: bool = False, progress=None):
+        """March every handle; returns the six errors (dict) of the estimators over all slabs, or with
+        windows=True a list of them for every cumulative window of handles (samples 1..n_k, n_k the
+        samples of the first k handles), the sampling diagnostic over growing N."""
         import torch
+        H = len(self.handles)
         us = [torch.zeros(P.n(0), dtype=torch.float64, device="cuda") for P in self.handles]
         rhs = [torch.zeros_like(u) for u in us]
-        out = np.zeros(6)
+        n_win = H if windows else 1
+        accs = [self.acc] + [torch.zeros_like(self.acc) for _ in range(n_win - 1)]
+        counts = np.cumsum([len(g) for g in self.G])
+        tg = []
+        for j in range(n_win):
+            g = np.concatenate(self.G[: j + 1]) if windows else np.concatenate(self.G)
+            tg.append((float(np.mean(g)), float(np.var(g, ddof=1))))
+        outs = [np.zeros(6) for _ in range(n_win)]
         self.info = []
         for n in range(1, self.ew.n_slabs + 1):
-            self.acc.zero_()
+            for a in accs:
+                a.zero_()
             for k, P in enumerate(self.handles):
                 if n == 1:
                     P.separable_vector(self._weights(k, n), self.V, rhs[k], beta=0.0)
@@ -101,15 +112,26 @@ class MCErrorStudy:
                 self.info.append(info)
                 if not info["converged"]:
                     raise sgheat.SgError(sgheat.SG_NOT_CONVERGED, f"slab {n} of batch {k} did not converge")
-                P.sample_qp_moments(us[k], self.nq1, self.ntq, self.acc)
+                # handle k's samples belong to every window that contains it
+                for j in (range(k, n_win) if windows else [0]):
+                    P.sample_qp_moments(us[k], self.nq1, self.ntq, accs[j])
+            if progress is not None:
+                progress(n)
             t = (n - 1) * self.ew.base.tau + self.ew.base.tau * self.st
-            out += self.handles[0].moment_errors(self.acc, self.N, self.nq1, self.s_qp, t ** 4, [1.0, self.g_bar],
-                                                 [self.C2, self.v_g])
+            for j in range(n_win):
+                n_tot = int(counts[j]) if windows else self.N
+                outs[j] += self.handles[0].moment_errors(accs[j], n_tot, self.nq1, self.s_qp, t ** 4,
+                                                         [1.0, tg[j][0]], [self.C2, tg[j][1]])
         self.last = us
-        return {"tot_mean": math.sqrt(out[0]), "disc_mean": math.sqrt(out[1]),
-                "mc_mean": abs(self.g_bar - 1.0) * math.sqrt(out[4]),
-                "tot_var": math.sqrt(out[2]), "disc_var": math.sqrt(out[3]),
-                "mc_var": abs(self.v_g - self.C2) * math.sqrt(out[5]), "N": self.N}
+        res = []
+        for j in range(n_win):
+            out, (g_bar, v_g) = outs[j], tg[j]
+            res.append({"tot_mean": math.sqrt(out[0]), "disc_mean": math.sqrt(out[1]),
+                        "mc_mean": abs(g_bar - 1.0) * math.sqrt(out[4]),
+                        "tot_var": math.sqrt(out[2]), "disc_var": math.sqrt(out[3]),
+                        "mc_var": abs(v_g - self.C2) * math.sqrt(out[5]),
+                        "N": int(counts[j]) if windows else self.N})
+        return res if windows else res[0]
 
 
 def sgheat_max_samples(n_time: int) -> int:

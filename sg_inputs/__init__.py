@@ -417,6 +417,9 @@ def mc_error_workload(n_cells_1d: int, fe_degree: int, time_degree: int, n_slabs
 MC_ERROR_WORKLOADS = {
     # 2D Q3 on 32^2 cells of (-1,1)^2 (h = 1/16), dG(3), tau = 1/16 (16 slabs), 512 samples in 4 handles
     "c6": mc_error_workload(32, 3, 3, 16, 512, 128, 12, 4),
+    # the same discretisation and draw stream with 2048 samples in 16 handles (its first 512 samples
+    # are c6's): the cumulative windows N = 128, 256, ..., 2048 give the root-N diagnostic
+    "c7": mc_error_workload(32, 3, 3, 16, 2048, 128, 12, 4),
     # small cases for the tests
     "e2": mc_error_workload(4, 3, 3, 2, 6, 3, 13, 2),
     "e3": mc_error_workload(4, 2, 1, 3, 5, 5, 14, 2),

@@ -41,6 +41,23 @@ def test_error_split_matches_oracle(torch_cuda, name):
         assert got[key] == pytest.approx(ref[key], rel=1e-10), key
 
 
+def test_cumulative_windows_match_oracle(torch_cuda):
+    """Every window of the first k handles equals the oracle's split over those samples."""
+    from paper_2605_21046_amd.mcerrors import MCErrorStudy
+    ew = sg_inputs.MC_ERROR_WORKLOADS["e2"]
+    S = MCErrorStudy(ew, rtol=1e-12)
+    rows = S.run(windows=True)
+    S.close()
+    xs = ew.samples()
+    assert [r["N"] for r in rows] == [3, 6]
+    for r in rows:
+        ref = me.error_split(ew, xs[: r["N"]])
+        for key in ["tot_mean", "disc_mean", "tot_var", "disc_var"]:
+            assert r[key] == pytest.approx(ref[key], rel=1e-8), (r["N"], key)
+        for key in ["mc_mean", "mc_var"]:
+            assert r[key] == pytest.approx(ref[key], rel=1e-10), (r["N"], key)
+
+
 def test_full_size_error_split_properties(torch_cuda):
     from paper_2605_21046_amd.mcerrors import MCErrorStudy
     ew = sg_inputs.MC_ERROR_WORKLOADS["c6"]
