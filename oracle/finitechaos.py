@@ -26,6 +26,7 @@ and the same with gradients for the H1-seminorm quantities (grad of the variance
 """
 from __future__ import annotations
 
+import itertools
 import math
 
 import numpy as np
@@ -66,7 +67,7 @@ def _tables(mesh: fem.Mesh, nq1: int):
     k = mesh.k
     v1 = np.array([[float(timebasis.lagrange_value(mesh.support, a, np.array(x))) for a in range(k + 1)] for x in pts])
     d1 = np.array([[float(timebasis.lagrange_deriv(mesh.support, a, np.array(x))) for a in range(k + 1)] for x in pts])
-    qloc = [tuple(reversed(t)) for t in __import__("itertools").product(range(nq1), repeat=mesh.dim)]
+    qloc = [tuple(reversed(t)) for t in itertools.product(range(nq1), repeat=mesh.dim)]
     loc = mesh.local_multi()
     phi = np.empty((len(qloc), len(loc)))
     dphi = np.empty((len(qloc), len(loc), mesh.dim))
