@@ -87,6 +87,13 @@ typedef struct {
                              * graded order of a single problem).                                       */
     const int* member_degree;     /* host [n_members] (copied)                                       */
     const double* member_scale;   /* host [n_members][n_coef_modes] (copied); the mu = 0 entry must be 1 */
+    int diag_blocks;        /* 0: the block-Jacobi preconditioner uses the mean block A_0 for every mode
+                             * (exact for an affine coefficient).  1: every mode alpha gets its own
+                             * diagonal block A_alpha = A_t (x) M_x + B_t (x) K_{a_alpha},
+                             * a_alpha = sum_mu [G_mu]_{alpha alpha} a_mu (for a sample batch: the
+                             * sample's coefficient), on every level: per-mode Vanka patch inverses,
+                             * residuals and coarsest-level inverses (N_xi times the memory of the
+                             * patch inverses; the coarsest level should be small).                   */
     int transpose;          /* 0: the slab operator AA; 1: its transpose AA^T (the adjoint slab
                              * problem).  Every G_mu (a triple-product matrix), M_x and K_mu is symmetric
                              * and B_t is diagonal, so AA^T is AA with A_t replaced by A_t^T; every entry

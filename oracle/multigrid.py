@@ -17,6 +17,9 @@ Readings where the paper is silent (each also listed in the design notes):
   * prolongation P = nodal interpolation of the coarse Q_k function at the fine nodes, zero on
     Dirichlet nodes, applied to each time component; restriction R = P^T;
   * coarsest level: dense LU of A_0 on its interior DoFs.
+With per-mode diagonal blocks (a non-affine coefficient, where [G_mu]_{alpha alpha} != 0 for even mu),
+mode alpha gets its own hierarchy built the same way from A_alpha = A_t (x) M_x +
+sum_mu [G_mu]_{alpha alpha} B_t (x) K_mu on every level.
 Vectors here hold one stochastic mode: layout [i][node], length N_t N_x.
 """
 from __future__ import annotations
@@ -30,11 +33,12 @@ from .slab import SlabProblem
 
 
 class Level:
-    def __init__(self, prob: SlabProblem):
+    def __init__(self, prob: SlabProblem, block: int | None = None):
+        """The mean block A_0, or with block = alpha the diagonal block A_alpha."""
         self.prob = prob
         self.mesh = prob.mesh
         self.n_t = prob.n_t
-        self.A0 = prob.mean_block()
+        self.A0 = prob.mean_block() if block is None else prob.diagonal_block(block)
         self.bdof = np.tile(prob.bmask, self.n_t)          # Dirichlet DoFs of one mode
         self.ndof = self.A0.shape[0]
         mult = np.zeros(self.mesh.n_nodes)
@@ -89,8 +93,8 @@ def prolongation(fine: Level, coarse: Level) -> sp.csr_matrix:
 class Hierarchy:
     """Levels 0 (finest) .. L-1 (coarsest)."""
 
-    def __init__(self, problems: list[SlabProblem], pre=1, post=1, omega=1.0):
-        self.levels = [Level(p) for p in problems]
+    def __init__(self, problems: list[SlabProblem], pre=1, post=1, omega=1.0, block: int | None = None):
+        self.levels = [Level(p, block) for p in problems]
         self.P = [prolongation(self.levels[l], self.levels[l + 1]) for l in range(len(problems) - 1)]
         self.pre, self.post, self.omega = pre, post, omega
 
@@ -126,3 +130,20 @@ def hierarchy_from_workload(w, coef_fn=None) -> Hierarchy:
     from .slab import from_workload
     probs = [from_workload(w, l, coef_fn) for l in range(w.n_levels)]
     return Hierarchy(probs, w.pre_smooth, w.post_smooth, w.vanka_omega)
+
+
+class BlockHierarchies:
+    """Block-Jacobi over the modes with each mode's own diagonal block on every level."""
+
+    def __init__(self, problems: list[SlabProblem], pre=1, post=1, omega=1.0):
+        self.h = [Hierarchy(problems, pre, post, omega, block=a) for a in range(problems[0].n_xi)]
+
+    def vcycle(self, r_all: np.ndarray, n_xi: int) -> np.ndarray:
+        R = r_all.reshape(n_xi, -1)
+        return np.concatenate([self.h[a].vcycle_mode(R[a]) for a in range(n_xi)])
+
+
+def block_hierarchies_from_workload(w, coef_fn=None) -> BlockHierarchies:
+    from .slab import from_workload
+    probs = [from_workload(w, l, coef_fn) for l in range(w.n_levels)]
+    return BlockHierarchies(probs, w.pre_smooth, w.post_smooth, w.vanka_omega)

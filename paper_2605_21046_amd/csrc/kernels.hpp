@@ -94,6 +94,10 @@ inline size_t vanka_lds_bytes(int npp, size_t elem) { return (size_t)((npp + 3) 
 template <typename T>
 hipError_t launch_vanka_cells(int dim, int k, int nt, Grid g, int n_xi, const T* invT, const T* r, T* s_out,
                               hipStream_t s);
+// the same with one inverse per (mode, cell): invT [n_xi][n_cells][n_p][n_p]
+template <typename T>
+hipError_t launch_vanka_cells_modes(int dim, int k, int nt, Grid g, int n_xi, const T* invT, const T* r, T* s_out,
+                                    hipStream_t s);
 
 // ---- transfers ---------------------------------------------------------------------------------------
 // One 1D pass along `dir`: out[c][.., o, ..] (+)= sum_w tw[o*width + w] in[c][.., tidx[o*width + w], ..]
@@ -105,7 +109,7 @@ hipError_t launch_transfer_1d(int dim, int ncomp, const int* in_dims, const int*
 // ---- coarsest level ------------------------------------------------------------------------------
 // x = b, then on interior DoFs x[alpha][dof_r] = sum_l AinvT[l][r] b[alpha][dof_l] in FP64.
 template <typename T>
-hipError_t launch_coarse_solve(const double* AinvT, int nint, const int* dofs, int n_xi,
+hipError_t launch_coarse_solve(const double* AinvT, long long inv_stride, int nint, const int* dofs, int n_xi,
                                long long mode_len, const T* b, T* x, hipStream_t s);
 
 // ---- vector kernels (FP64 unless noted) -----------------------------------------------------------

@@ -203,11 +203,12 @@ __global__ void __launch_bounds__(256)
 
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_coarse_solve(const double* __restrict__ AinvT, int nint, const int* __restrict__ dofs, long long mode_len,
-                   const T* __restrict__ b, T* __restrict__ x) {
+    k_coarse_solve(const double* __restrict__ AinvT_all, long long inv_stride, int nint, const int* __restrict__ dofs,
+                   long long mode_len, const T* __restrict__ b, T* __restrict__ x) {
     extern __shared__ unsigned char smem_raw[];
     double* bl = reinterpret_cast<double*>(smem_raw);   // [nint]
     const int al = blockIdx.y;
+    const double* AinvT = AinvT_all + al * inv_stride;    // one inverse per mode, or one shared (stride 0)
     const T* bm = b + al * mode_len;
     for (int l = threadIdx.x; l < nint; l += blockDim.x) bl[l] = (double)bm[dofs[l]];
     __syncthreads();
@@ -435,16 +436,16 @@ hipError_t launch_cell_dot(int dim, int k, Grid g, int ncomp, const double* lam,
 }
 
 template <typename T>
-hipError_t launch_coarse_solve(const double* AinvT, int nint, const int* dofs, int n_xi, long long mode_len,
-                               const T* b, T* x, hipStream_t s) {
+hipError_t launch_coarse_solve(const double* AinvT, long long inv_stride, int nint, const int* dofs, int n_xi,
+                               long long mode_len, const T* b, T* x, hipStream_t s) {
     const long long n = mode_len * n_xi;
     hipLaunchKernelGGL(k_copy<T>, dim3(grid_for(n, 256)), dim3(256), 0, s, b, x, n);
     const size_t lds = (size_t)nint * sizeof(double);
     if (lds > 160 * 1024 || n_xi > 65535) return hipErrorInvalidConfiguration;
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute((const void*)k_coarse_solve<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_coarse_solve<T>, dim3((nint + 255) / 256, n_xi), dim3(256), lds, s, AinvT, nint, dofs, mode_len,
-                       b, x);
+    hipLaunchKernelGGL(k_coarse_solve<T>, dim3((nint + 255) / 256, n_xi), dim3(256), lds, s, AinvT, inv_stride, nint,
+                       dofs, mode_len, b, x);
     return hipGetLastError();
 }
 
@@ -514,10 +515,10 @@ template hipError_t launch_node_gather<double>(GatherOp, int, int, Grid, int, co
                                                const double*, double*, double, hipStream_t);
 template hipError_t launch_node_gather<float>(GatherOp, int, int, Grid, int, const float*, const float*, const float*,
                                               float*, float, hipStream_t);
-template hipError_t launch_coarse_solve<double>(const double*, int, const int*, int, long long, const double*, double*,
-                                                hipStream_t);
-template hipError_t launch_coarse_solve<float>(const double*, int, const int*, int, long long, const float*, float*,
-                                               hipStream_t);
+template hipError_t launch_coarse_solve<double>(const double*, long long, int, const int*, int, long long,
+                                                const double*, double*, hipStream_t);
+template hipError_t launch_coarse_solve<float>(const double*, long long, int, const int*, int, long long, const float*,
+                                               float*, hipStream_t);
 template hipError_t launch_convert<double, float>(const double*, float*, long long, hipStream_t);
 template hipError_t launch_convert<float, double>(const float*, double*, long long, hipStream_t);
 template hipError_t launch_convert<double, double>(const double*, double*, long long, hipStream_t);

@@ -620,6 +620,90 @@ hipError_t launch_patch_invert(int dim, int k, int nt, Grid g, const double* E, 
     return hipErrorInvalidValue;
 }
 
+// Per-mode diagonal blocks: c_{K,alpha} = A_{alpha,K}^{-1} R_K r_alpha with one inverse per (mode, cell),
+// one workgroup per (cell, mode), one thread per patch row: a dense matrix-vector product reading the
+// transposed inverse column by column (consecutive rows in consecutive lanes).
+template <int DIM, int K, int NT, typename T>
+__global__ void __launch_bounds__(256)
+    k_vanka_cells_modes(Grid g, const T* __restrict__ invT, const T* __restrict__ r, T* __restrict__ s_out) {
+    constexpr int N1 = K + 1;
+    constexpr int NP = ipow(N1, DIM);
+    constexpr int NPP = NT * NP;
+    __shared__ T rp[NPP];
+    const long long cell = blockIdx.x;
+    const int al = blockIdx.y;
+    const int t = threadIdx.x;
+    const long long nn = g.n_nodes;
+    int cc[3] = {0, 0, 0};
+    {
+        long long rr = cell;
+        for (int d = 0; d < DIM; ++d) { cc[d] = (int)(rr % g.n); rr /= g.n; }
+    }
+    const int nb1 = g.n * N1;
+    long long nbn = 1;
+    for (int d = 0; d < DIM; ++d) nbn *= nb1;
+    long long src = 0, dst = 0;
+    if (t < NPP) {
+        const int p = t % NP, ti = t / NP;
+        bool live = true;
+        long long m = 1, bm = 1;
+        for (int d = 0; d < DIM; ++d) {
+            const int a = (p / ipow(N1, d)) % N1;
+            const int id = cc[d] * K + a;
+            live &= (id != 0) & (id != g.n1 - 1);
+            src += id * m;
+            dst += (long long)(cc[d] * N1 + a) * bm;
+            m *= g.n1;
+            bm *= nb1;
+        }
+        src += ((long long)al * NT + ti) * nn;
+        dst += ((long long)al * NT + ti) * nbn;
+        rp[t] = live ? r[src] : T(0);
+    }
+    __syncthreads();
+    if (t < NPP) {
+        const T* c = invT + ((long long)al * g.n_cells + cell) * (NPP * NPP) + t;
+        T acc = T(0);
+#pragma unroll 8
+        for (int j = 0; j < NPP; ++j) acc += c[(long long)j * NPP] * rp[j];
+        s_out[dst] = acc;
+    }
+}
+
+template <int DIM, typename T>
+hipError_t vanka_modes_k(int k, int nt, Grid g, int n_xi, const T* invT, const T* r, T* s_out, hipStream_t s) {
+    const dim3 grid((unsigned)g.n_cells, (unsigned)n_xi);
+#define SG_VM(K_, T_)                                                                                         \
+    if (k == K_ && nt == T_) {                                                                                \
+        constexpr int npp = T_ * ipow(K_ + 1, DIM);                                                           \
+        if constexpr (npp <= 256) {                                                                           \
+            hipLaunchKernelGGL((k_vanka_cells_modes<DIM, K_, T_, T>), grid, dim3((npp + 63) / 64 * 64), 0, s, \
+                               g, invT, r, s_out);                                                            \
+            return hipGetLastError();                                                                         \
+        } else {                                                                                              \
+            return hipErrorInvalidValue;                                                                      \
+        }                                                                                                     \
+    }
+#define SG_VM_K(K_) SG_VM(K_, 1) SG_VM(K_, 2) SG_VM(K_, 3) SG_VM(K_, 4)
+    SG_VM_K(1) SG_VM_K(2) SG_VM_K(3) SG_VM_K(4)
+#undef SG_VM_K
+#undef SG_VM
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_vanka_cells_modes(int dim, int k, int nt, Grid g, int n_xi, const T* invT, const T* r, T* s_out,
+                                    hipStream_t s) {
+    if (dim == 2) return vanka_modes_k<2, T>(k, nt, g, n_xi, invT, r, s_out, s);
+    if (dim == 3) return vanka_modes_k<3, T>(k, nt, g, n_xi, invT, r, s_out, s);
+    return hipErrorInvalidValue;
+}
+
+template hipError_t launch_vanka_cells_modes<double>(int, int, int, Grid, int, const double*, const double*, double*,
+                                                     hipStream_t);
+template hipError_t launch_vanka_cells_modes<float>(int, int, int, Grid, int, const float*, const float*, float*,
+                                                    hipStream_t);
+
 template <typename T>
 hipError_t launch_vanka_cells(int dim, int k, int nt, Grid g, int n_xi, const T* invT, const T* r, T* s_out,
                               hipStream_t s) {

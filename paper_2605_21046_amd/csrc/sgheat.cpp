@@ -108,6 +108,14 @@ struct sg_handle_s {
     DevBuf<int> cptr, cbeta, cmu, cptr_m, cbeta_m, cmu_m;
     DevBuf<double> cw64, cw_m64;
     DevBuf<float> cw32, cw_m32;
+    // per-mode diagonal blocks (desc.diag_blocks): weights dw[alpha][mu] = [G_mu]_{alpha alpha} and the
+    // diagonal coupling lists of the block operator
+    bool diag = false;
+    std::vector<double> dw;
+    DevBuf<int> cptr_d, cbeta_d, cmu_d;
+    DevBuf<double> cw_d64, acomb;
+    DevBuf<float> cw_d32;
+    int n_ent_d = 0;
     // coarsest level
     int nint = 0;
     DevBuf<double> coarse_invT;
@@ -199,6 +207,7 @@ sg_status validate(const sg_problem_desc* d) {
     if (d->n_members < 0 || (d->n_members > 0 && (!d->member_degree || !d->member_scale)))
         return fail(SG_EINVAL, "member_degree / member_scale missing");
     if (d->n_members > 0 && d->n_samples > 0) return fail(SG_EINVAL, "n_samples and n_members are exclusive");
+    if (d->diag_blocks != 0 && d->diag_blocks != 1) return fail(SG_EINVAL, "diag_blocks must be 0 or 1");
     return SG_OK;
 }
 
@@ -252,15 +261,17 @@ sg_status set_coefficients(sg_handle h, const double* coef_qp) {
         }
     }
     size_t coef_off = 0;
+    std::vector<std::vector<double>> c64_levels(h->diag ? L : 0);   // host copies for the per-mode blocks
     for (int l = 0; l < L; ++l) {
         Level& lv = h->lv[l];
         // coefficients, pre-scaled by the Gauss weight and h^(d-2)
         const size_t per_mode = (size_t)lv.g.n_cells * h->NP;
-        const int nm = (l == 0) ? h->n_mu : 1;
+        const bool all_modes = (l == 0) || h->diag;   // per-mode blocks need every mode on every level
+        const int nm = all_modes ? h->n_mu : 1;
         std::vector<double> c64((size_t)nm * per_mode);
         const double hs = std::pow(lv.h, dim - 2);
         for (int mi = 0; mi < nm; ++mi) {
-            const int mu = (l == 0) ? mi : h->cpl.mu0;
+            const int mu = all_modes ? mi : h->cpl.mu0;
             const double* src = coef_qp + coef_off + (size_t)mu * per_mode;
             for (size_t c = 0; c < (size_t)lv.g.n_cells; ++c)
                 for (int q = 0; q < h->NP; ++q) {
@@ -270,6 +281,7 @@ sg_status set_coefficients(sg_handle h, const double* coef_qp) {
                 }
         }
         coef_off += (size_t)h->n_mu * per_mode;
+        if (h->diag) c64_levels[l] = c64;
         SG_TRY(lv.coef64.upload(c64.data(), c64.size(), "coefficients"));
         if (h->mixed) {
             std::vector<float> c32(c64.begin(), c64.end());
@@ -302,15 +314,32 @@ sg_status set_coefficients(sg_handle h, const double* coef_qp) {
             const double vol = std::pow(lv.h, dim);
             for (double& v : Mel) v *= vol;
             SG_TRY(Me.upload(Mel.data(), Mel.size(), "element matrices"));
-            const double* c0 = lv.coef64.p + (l == 0 ? (size_t)h->cpl.mu0 * lv.g.n_cells * h->NP : 0);
-            SG_HIP(launch_elem_stiffness(dim, k, lv.g, c0, et, E.p, nullptr));
             const size_t ninv = (size_t)lv.g.n_cells * h->npp * h->npp;
             const bool want32 = h->mixed && l < L - 1;
-            SG_TRY(lv.inv64.alloc(ninv, "patch inverses"));
-            if (want32) SG_TRY(lv.inv32.alloc(ninv, "patch inverses"));
-            SG_HIP(launch_patch_invert(dim, k, h->NT, lv.g, E.p, Me.p, pt, lv.inv64.p, want32 ? lv.inv32.p : nullptr,
-                                       status.p, nullptr));
-            SG_HIP(hipDeviceSynchronize());
+            const int nblk = h->diag ? h->n_xi : 1;             // one set of patch inverses per mode
+            SG_TRY(lv.inv64.alloc(ninv * nblk, "patch inverses"));
+            if (want32) SG_TRY(lv.inv32.alloc(ninv * nblk, "patch inverses"));
+            const size_t per_mode = (size_t)lv.g.n_cells * h->NP;
+            std::vector<double> acomb(h->diag ? per_mode : 0);
+            for (int a = 0; a < nblk; ++a) {
+                const double* c0 = lv.coef64.p + ((l == 0 || h->diag) ? (size_t)h->cpl.mu0 * per_mode : 0);
+                if (h->diag) {
+                    // a_alpha = sum_mu [G_mu]_{alpha alpha} a_mu at this level's Gauss points (pre-scaled)
+                    std::fill(acomb.begin(), acomb.end(), 0.0);
+                    for (int mi = 0; mi < h->n_mu; ++mi) {
+                        const double wv = h->dw[(size_t)a * h->n_mu + mi];
+                        if (wv == 0.0) continue;
+                        const double* src = c64_levels[l].data() + (size_t)mi * per_mode;
+                        for (size_t q = 0; q < per_mode; ++q) acomb[q] += wv * src[q];
+                    }
+                    SG_TRY(h->acomb.upload(acomb.data(), acomb.size(), "block coefficient"));
+                    c0 = h->acomb.p;
+                }
+                SG_HIP(launch_elem_stiffness(dim, k, lv.g, c0, et, E.p, nullptr));
+                SG_HIP(launch_patch_invert(dim, k, h->NT, lv.g, E.p, Me.p, pt, lv.inv64.p + a * ninv,
+                                           want32 ? lv.inv32.p + a * ninv : nullptr, status.p, nullptr));
+                SG_HIP(hipDeviceSynchronize());
+            }
         }
         int st = 0;
         SG_HIP(hipMemcpy(&st, status.p, sizeof(int), hipMemcpyDeviceToHost));
@@ -339,11 +368,27 @@ sg_status set_coefficients(sg_handle h, const double* coef_qp) {
         const int ni = (int)inodes.size();
         h->nint = ni * h->NT;
         if (h->nint > 12000) return fail(SG_EINVAL, "coarsest level too large for the dense solve; add levels");
-        std::vector<double> A((size_t)h->nint * h->nint, 0.0);
-        const double* c0 = coef_qp;
+        const int nblk = h->diag ? h->n_xi : 1;                   // one coarsest inverse per mode
+        if (h->diag && (double)nblk * h->nint * h->nint * 8.0 > 16e9)
+            return fail(SG_EUNSUPPORTED, "per-mode coarsest-level inverses need more than 16 GB; add levels");
         size_t off = 0;
         for (int l = 0; l < L - 1; ++l) off += (size_t)h->n_mu * h->lv[l].g.n_cells * h->NP;
-        c0 += off + (size_t)h->cpl.mu0 * lc.g.n_cells * h->NP;
+        const size_t cper = (size_t)lc.g.n_cells * h->NP;
+        std::vector<double> craw(h->diag ? cper : 0);
+        if (h->nint > 0) SG_TRY(h->coarse_invT.alloc((size_t)nblk * h->nint * h->nint, "coarse inverse"));
+        for (int blk = 0; blk < nblk; ++blk) {
+        std::vector<double> A((size_t)h->nint * h->nint, 0.0);
+        const double* c0 = coef_qp + off + (size_t)h->cpl.mu0 * cper;
+        if (h->diag) {
+            std::fill(craw.begin(), craw.end(), 0.0);
+            for (int mi = 0; mi < h->n_mu; ++mi) {
+                const double wv = h->dw[(size_t)blk * h->n_mu + mi];
+                if (wv == 0.0) continue;
+                const double* src = coef_qp + off + (size_t)mi * cper;
+                for (size_t q = 0; q < cper; ++q) craw[q] += wv * src[q];
+            }
+            c0 = craw.data();
+        }
         const double vol = std::pow(lc.h, dim), hs = std::pow(lc.h, dim - 2);
         // reference stiffness integrands Kref[q][a][b] = w_q h^(d-2) sum_e dphi_a/dx_e dphi_b/dx_e (x_q)
         const int NP = h->NP;
@@ -404,11 +449,12 @@ sg_status set_coefficients(sg_handle h, const double* coef_qp) {
             SG_TRY(col.alloc(h->nint, "coarse pivots"));
             SG_TRY(perm.alloc(h->nint, "coarse pivots"));
             SG_TRY(status.upload(&zero, 1, "status"));
-            SG_TRY(h->coarse_invT.alloc((size_t)h->nint * h->nint, "coarse inverse"));
-            SG_HIP(launch_dense_invert(Ad.p, h->nint, col.p, perm.p, status.p, h->coarse_invT.p, nullptr));
+            SG_HIP(launch_dense_invert(Ad.p, h->nint, col.p, perm.p, status.p,
+                                       h->coarse_invT.p + (size_t)blk * h->nint * h->nint, nullptr));
             int st = 0;
             SG_HIP(hipMemcpy(&st, status.p, sizeof(int), hipMemcpyDeviceToHost));
             if (st) return fail(SG_ESINGULAR, "coarsest-level matrix is singular");
+        }
         }
         std::vector<int> dofs(h->nint);
         for (int i = 0; i < h->NT; ++i)
@@ -493,6 +539,33 @@ sg_status build(sg_handle h) {
         SG_TRY(h->cmu_m.upload(mm.data(), mm.size(), "coupling"));
         SG_TRY(h->cw_m64.upload(wm.data(), wm.size(), "coupling"));
         SG_TRY(h->cw_m32.upload(wm32.data(), wm32.size(), "coupling"));
+        h->diag = d.diag_blocks == 1;
+        if (h->diag) {
+            // the (alpha, alpha) entry of every (alpha, mu) row: the diagonal block's coefficient weights
+            h->dw.assign((size_t)h->n_xi * h->n_mu, 0.0);
+            std::vector<int> pd(1, 0), bd, md;
+            std::vector<double> wd;
+            for (int a = 0; a < h->n_xi; ++a)
+                for (int mi = 0; mi < h->n_mu; ++mi) {
+                    const int row = a * h->n_mu + mi;
+                    for (int e = h->cpl.ptr[row]; e < h->cpl.ptr[row + 1]; ++e)
+                        if (h->cpl.beta[e] == a) h->dw[(size_t)a * h->n_mu + mi] += h->cpl.w[e];
+                    const double wv = h->dw[(size_t)a * h->n_mu + mi];
+                    if (wv != 0.0) {
+                        bd.push_back(a);
+                        md.push_back(mi);
+                        wd.push_back(wv);
+                    }
+                    pd.push_back((int)bd.size());
+                }
+            h->n_ent_d = (int)bd.size();
+            std::vector<float> wd32(wd.begin(), wd.end());
+            SG_TRY(h->cptr_d.upload(pd.data(), pd.size(), "diagonal coupling"));
+            SG_TRY(h->cbeta_d.upload(bd.data(), bd.size(), "diagonal coupling"));
+            SG_TRY(h->cmu_d.upload(md.data(), md.size(), "diagonal coupling"));
+            SG_TRY(h->cw_d64.upload(wd.data(), wd.size(), "diagonal coupling"));
+            SG_TRY(h->cw_d32.upload(wd32.data(), wd32.size(), "diagonal coupling"));
+        }
     }
 
     // 1D tables
@@ -631,6 +704,7 @@ struct Prec<double> {
     static const double* coef(const Level& l) { return l.coef64.p; }
     static const double* cw(const sg_handle h) { return h->cw64.p; }
     static const double* cwm(const sg_handle h) { return h->cw_m64.p; }
+    static const double* cwd(const sg_handle h) { return h->cw_d64.p; }
     static const double* inv(const Level& l) { return l.inv64.p; }
     static double* b(Level& l) { return l.b64.p; }
     static double* x(Level& l) { return l.x64.p; }
@@ -646,6 +720,7 @@ struct Prec<float> {
     static const float* coef(const Level& l) { return l.coef32.p; }
     static const float* cw(const sg_handle h) { return h->cw32.p; }
     static const float* cwm(const sg_handle h) { return h->cw_m32.p; }
+    static const float* cwd(const sg_handle h) { return h->cw_d32.p; }
     static const float* inv(const Level& l) { return l.inv32.p; }
     static float* b(Level& l) { return l.b32.p; }
     static float* x(Level& l) { return l.x32.p; }
@@ -687,7 +762,7 @@ ApplyOp<T> make_op(const sg_handle h, int level, bool full) {
         op.cw = Prec<T>::cw(h);
     } else {
         op.n_mu = 1;
-        op.coef = Prec<T>::coef(lv) + (level == 0 ? (size_t)h->cpl.mu0 * op.coef_mode_stride : 0);
+        op.coef = Prec<T>::coef(lv) + ((level == 0 || h->diag) ? (size_t)h->cpl.mu0 * op.coef_mode_stride : 0);
         op.cptr = h->cptr_m.p;
         op.cbeta = h->cbeta_m.p;
         op.cmu = h->cmu_m.p;
@@ -712,6 +787,23 @@ ApplyOp<T> make_op(const sg_handle h, int level, bool full) {
     return op;
 }
 
+// The operator of the preconditioner's diagonal blocks on one level: the mean block I (x) A_0, or with
+// per-mode blocks the block-diagonal operator diag_alpha(A_alpha) (the (alpha, alpha) coupling entries).
+template <typename T>
+ApplyOp<T> make_block_op(const sg_handle h, int level) {
+    if (!h->diag) return make_op<T>(h, level, false);
+    ApplyOp<T> op = make_op<T>(h, level, true);
+    op.cptr = h->cptr_d.p;
+    op.cbeta = h->cbeta_d.p;
+    op.cmu = h->cmu_d.p;
+    op.cw = Prec<T>::cwd(h);
+    op.n_ent = h->n_ent_d;
+    op.affine = false;
+    op.cells_per_block = apply_cpb_override();
+    if (op.cells_per_block == 0 && level < 16) op.cells_per_block = h->tuned_cpb[sizeof(T) == 4][0][level];
+    return op;
+}
+
 template <typename T>
 T* sbuf_as(sg_handle h) {
     return reinterpret_cast<T*>(h->sbuf.p);
@@ -722,7 +814,7 @@ T* sbuf_as(sg_handle h) {
 template <typename T>
 sg_status autotune_apply(sg_handle h, int level, bool full, int reps, hipStream_t s) {
     Level& lv = h->lv[level];
-    ApplyOp<T> op = make_op<T>(h, level, full);
+    ApplyOp<T> op = full ? make_op<T>(h, level, true) : make_block_op<T>(h, level);
     T* x = Prec<T>::x(lv);
     SG_HIP(hipMemsetAsync(x, 0, sizeof(T) * lv.len, s));
     std::vector<hipEvent_t> ev(reps + 1);
@@ -767,7 +859,7 @@ sg_status op_apply(sg_handle h, const ApplyOp<T>& op, const T* x, T* y, const T*
 template <typename T>
 sg_status smooth_level(sg_handle h, int l, const T* b, T* x, int sweeps, bool x_is_zero, hipStream_t s) {
     Level& lv = h->lv[l];
-    const ApplyOp<T> op = make_op<T>(h, l, false);
+    const ApplyOp<T> op = make_block_op<T>(h, l);
     const T* inv = Prec<T>::inv(lv);
     for (int it = 0; it < sweeps; ++it) {
         const T* r = b;   // with x = 0 the residual b - A_0 x is b itself
@@ -775,7 +867,10 @@ sg_status smooth_level(sg_handle h, int l, const T* b, T* x, int sweeps, bool x_
             SG_TRY(op_apply<T>(h, op, x, Prec<T>::r(lv), b, s));
             r = Prec<T>::r(lv);
         }
-        SG_HIP(launch_vanka_cells<T>(h->d.dim, h->d.fe_degree, h->NT, lv.g, h->n_xi, inv, r, sbuf_as<T>(h), s));
+        if (h->diag)
+            SG_HIP(launch_vanka_cells_modes<T>(h->d.dim, h->d.fe_degree, h->NT, lv.g, h->n_xi, inv, r, sbuf_as<T>(h), s));
+        else
+            SG_HIP(launch_vanka_cells<T>(h->d.dim, h->d.fe_degree, h->NT, lv.g, h->n_xi, inv, r, sbuf_as<T>(h), s));
         SG_HIP(launch_node_gather<T>(GATHER_VANKA, h->d.dim, h->d.fe_degree, lv.g, h->n_xi * h->NT, sbuf_as<T>(h),
                                      nullptr, b, x, (T)h->d.vanka_omega, s));
     }
@@ -835,13 +930,14 @@ sg_status vcycle_level(sg_handle h, int l, const T* b, T* x, hipStream_t s) {
     const int L = h->d.n_levels;
     Level& lv = h->lv[l];
     if (l == L - 1) {
-        SG_HIP(launch_coarse_solve<T>(h->coarse_invT.p, h->nint, h->coarse_dofs.p, h->n_xi, (long long)h->NT * lv.g.n_nodes,
+        SG_HIP(launch_coarse_solve<T>(h->coarse_invT.p, h->diag ? (long long)h->nint * h->nint : 0, h->nint,
+                                      h->coarse_dofs.p, h->n_xi, (long long)h->NT * lv.g.n_nodes,
                                       b, x, s));
         return SG_OK;
     }
     SG_HIP(launch_fill<T>(x, T(0), lv.len, s));
     SG_TRY(smooth_level<T>(h, l, b, x, h->d.pre_smooth, true, s));
-    const ApplyOp<T> op = make_op<T>(h, l, false);
+    const ApplyOp<T> op = make_block_op<T>(h, l);
     SG_TRY(op_apply<T>(h, op, x, Prec<T>::r(lv), b, s));
     Level& lc = h->lv[l + 1];
     SG_TRY(restrict_to<T>(h, l, Prec<T>::r(lv), Prec<T>::b(lc), s));

@@ -26,13 +26,13 @@ from . import sgheat
 class FiniteChaosRun:
     """One stochastic degree p_xi of the benchmark (an sg_inputs.FiniteChaosWorkload)."""
 
-    def __init__(self, fw, precision=sgheat.SG_FP64, rtol: float = 1e-10, max_iter: int = 2000):
+    def __init__(self, fw, precision=sgheat.SG_FP64, rtol: float = 1e-10, max_iter: int = 2000, diag_blocks: int = 0):
         import torch
         import sg_inputs
         self.fw = fw
         w = fw.base
         self.rtol, self.max_iter = rtol, max_iter
-        self.P = sgheat.problem_from_workload(w, precision)
+        self.P = sgheat.problem_from_workload(w, precision, diag_blocks=diag_blocks)
         self.spec = self.P.spec
         self.nq1 = w.fe_degree + 3
         self.ntq = w.time_degree + 3

@@ -26,14 +26,16 @@ from . import sgheat
 class MCErrorStudy:
     """One sg_inputs.MCErrorWorkload."""
 
-    def __init__(self, ew, precision=sgheat.SG_FP64, rtol: float = 1e-10, max_iter: int = 500, samples=None):
+    def __init__(self, ew, precision=sgheat.SG_FP64, rtol: float = 1e-10, max_iter: int = 500, samples=None,
+                 diag_blocks: int = 0):
         import torch
         import sg_inputs
         self.ew = ew
         w = ew.base
         self.rtol, self.max_iter = rtol, max_iter
         self.spec = sgheat.Spec(w.dim, w.n_cells_1d, w.fe_degree, w.time_degree, w.tau, w.n_vars, 0, w.n_levels,
-                                w.lo, w.hi, w.pre_smooth, w.post_smooth, w.vanka_omega, w.fgmres_restart)
+                                w.lo, w.hi, w.pre_smooth, w.post_smooth, w.vanka_omega, w.fgmres_restart,
+                                diag_blocks=diag_blocks)
         mus, coef = sg_inputs.coef_qp_levels(w, lambda lvl: sgheat.quadrature_points(self.spec, lvl))
         xs = ew.samples() if samples is None else np.asarray(samples, dtype=np.float64)
         self.N = len(xs)

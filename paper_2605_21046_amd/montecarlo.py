@@ -24,7 +24,8 @@ from . import sgheat
 class SampleBatch:
     """The slab sequences of one sg_inputs.SampleWorkload (or of explicit samples)."""
 
-    def __init__(self, sw, samples=None, rtol: float = 1e-10, max_iter: int = 500, precision=sgheat.SG_FP64):
+    def __init__(self, sw, samples=None, rtol: float = 1e-10, max_iter: int = 500, precision=sgheat.SG_FP64,
+                 diag_blocks: int = 0):
         import torch
         import sg_inputs
         self.sw = sw
@@ -32,7 +33,8 @@ class SampleBatch:
         self.samples = np.ascontiguousarray(sw.samples() if samples is None else samples, dtype=np.float64)
         self.rtol, self.max_iter = rtol, max_iter
         self.spec = sgheat.Spec(w.dim, w.n_cells_1d, w.fe_degree, w.time_degree, w.tau, w.n_vars, 0, w.n_levels,
-                                w.lo, w.hi, w.pre_smooth, w.post_smooth, w.vanka_omega, w.fgmres_restart)
+                                w.lo, w.hi, w.pre_smooth, w.post_smooth, w.vanka_omega, w.fgmres_restart,
+                                diag_blocks=diag_blocks)
         mus, coef = sg_inputs.coef_qp_levels(w, lambda lvl: sgheat.quadrature_points(self.spec, lvl))
         self.P = sgheat.Problem(self.spec, mus, coef, precision, samples=self.samples)
         self.n_s, self.n_t, self.n_x = self.P.shape

@@ -41,7 +41,7 @@ class ProblemDesc(ctypes.Structure):
                 ("fgmres_restart", ctypes.c_int), ("precision", ctypes.c_int), ("n_samples", ctypes.c_int),
                 ("samples", ctypes.POINTER(ctypes.c_double)), ("n_members", ctypes.c_int),
                 ("member_degree", ctypes.POINTER(ctypes.c_int)), ("member_scale", ctypes.POINTER(ctypes.c_double)),
-                ("transpose", ctypes.c_int)]
+                ("diag_blocks", ctypes.c_int), ("transpose", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -123,12 +123,13 @@ class Spec:
     vanka_omega: float = 1.0
     fgmres_restart: int = 30
     transpose: int = 0
+    diag_blocks: int = 0
 
 
 def _desc(spec, precision=SG_FP64):
     d = ProblemDesc()
     for name in ["dim", "n_cells_1d", "fe_degree", "time_degree", "n_vars", "chaos_degree", "n_levels",
-                 "pre_smooth", "post_smooth", "fgmres_restart", "transpose"]:
+                 "pre_smooth", "post_smooth", "fgmres_restart", "transpose", "diag_blocks"]:
         setattr(d, name, int(getattr(spec, name)))
     for name in ["lo", "hi", "tau", "vanka_omega"]:
         setattr(d, name, float(getattr(spec, name)))

@@ -457,3 +457,36 @@ def test_fgmres_matches_direct_solve(name):
     xd = spla.spsolve(P.assemble_full().tocsc(), b)
     assert np.linalg.norm(xd - xs) <= 1e-12 * np.linalg.norm(xs)
     assert np.linalg.norm(x - xd) <= 1e-6 * np.linalg.norm(xd)
+
+
+def test_diagonal_blocks_of_an_affine_coefficient_are_the_mean_block():
+    """[G_{e_m}]_{alpha alpha} = 0, so every per-mode hierarchy equals the mean-block one."""
+    from oracle import multigrid
+    w = sg_inputs.WORKLOADS["t2q2"]
+    H = multigrid.hierarchy_from_workload(w)
+    B = multigrid.block_hierarchies_from_workload(w)
+    P = from_workload(w)
+    r = np.random.default_rng(4).standard_normal(P.n)
+    assert np.allclose(B.vcycle(r, P.n_xi), H.vcycle(r, P.n_xi), rtol=0, atol=1e-13 * np.abs(r).max())
+
+
+def test_diagonal_block_is_the_galerkin_projection_at_fixed_mode():
+    """For the non-affine finite-chaos coefficient A_alpha differs from A_0 exactly by
+    sum_mu [G_mu]_{alpha alpha} B_t (x) K_mu over mu != 0, with [G_{2 e_k}]_{alpha alpha} = sqrt(2) alpha_k
+    (E[He_2/sqrt2 psi_a^2] = sqrt(2) a) and zero for mu = e_k + e_l."""
+    import scipy.sparse as sp
+    fw = sg_inputs.finite_chaos_workload(2, 2, 1, 2, 2, 1)
+    P = from_workload(fw.base)
+    for a, alpha in enumerate(P.index_set):
+        D = (P.diagonal_block(a) - P.mean_block()).toarray()
+        ref = np.zeros_like(D)
+        for mu, K in zip(P.coef_mu, P.K):
+            if max(mu) == 2 and sum(mu) == 2:
+                k = int(np.argmax(mu))
+                g = math.sqrt(2.0) * alpha[k]
+                Bk = sp.kron(sp.csr_matrix(P.Bt), K).toarray()
+                ref += g * Bk
+        bm = np.tile(P.bmask, P.n_t)
+        ref[bm, :] = 0.0
+        ref[:, bm] = 0.0
+        assert np.allclose(D, ref, rtol=0, atol=1e-12)
