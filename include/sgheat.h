@@ -129,7 +129,8 @@ sg_status sg_vector_length(sg_handle h, int level, long long* n);
 sg_status sg_operator_apply(sg_handle h, const double* x, double* y, void* hip_stream);
 
 /* `sweeps` additive Vanka sweeps on the mean block I_xi (x) A_0 of level `level`, A_0 =
- * A_t (x) M_x + B_t (x) K_{a_0} (Remark solver-matrix-free-sg):
+ * A_t (x) M_x + B_t (x) K_{a_0} (Remark solver-matrix-free-sg), or with desc.diag_blocks = 1 on the
+ * block-diagonal operator diag_alpha(A_alpha) with each mode's own patch inverses:
  *     x <- x + omega sum_K R_K^T W_K A_{0,K}^{-1} R_K (b - A_0 x),   then x_D = b_D on Dirichlet DoFs.
  * b and x are FP64 on every level; with SG_MIXED the sweep runs in FP32 internally for level 0 and
  * the levels above the coarsest.  x is updated in place.  Asynchronous on the stream. */
@@ -139,6 +140,7 @@ sg_status sg_vanka_smooth(sg_handle h, int level, const double* b, double* x, in
  * mean-based diagonal block (every diagonal block equals A_0 for an affine coefficient; for a
  * non-affine coefficient set, such as the finite-chaos benchmark's, the diagonal blocks differ and A_0
  * stands in for all of them, so FGMRES needs more iterations but converges to the same solution).
+ * With desc.diag_blocks = 1 each mode alpha is cycled with its own block A_alpha instead.
  * FP64 interface; FP32 inside with SG_MIXED.  Asynchronous on the stream. */
 sg_status gmg_vcycle(sg_handle h, const double* r, double* z, void* hip_stream);
 
