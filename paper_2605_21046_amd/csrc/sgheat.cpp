@@ -377,84 +377,84 @@ sg_status set_coefficients(sg_handle h, const double* coef_qp) {
         std::vector<double> craw(h->diag ? cper : 0);
         if (h->nint > 0) SG_TRY(h->coarse_invT.alloc((size_t)nblk * h->nint * h->nint, "coarse inverse"));
         for (int blk = 0; blk < nblk; ++blk) {
-        std::vector<double> A((size_t)h->nint * h->nint, 0.0);
-        const double* c0 = coef_qp + off + (size_t)h->cpl.mu0 * cper;
-        if (h->diag) {
-            std::fill(craw.begin(), craw.end(), 0.0);
-            for (int mi = 0; mi < h->n_mu; ++mi) {
-                const double wv = h->dw[(size_t)blk * h->n_mu + mi];
-                if (wv == 0.0) continue;
-                const double* src = coef_qp + off + (size_t)mi * cper;
-                for (size_t q = 0; q < cper; ++q) craw[q] += wv * src[q];
-            }
-            c0 = craw.data();
-        }
-        const double vol = std::pow(lc.h, dim), hs = std::pow(lc.h, dim - 2);
-        // reference stiffness integrands Kref[q][a][b] = w_q h^(d-2) sum_e dphi_a/dx_e dphi_b/dx_e (x_q)
-        const int NP = h->NP;
-        std::vector<double> Kref((size_t)NP * NP * NP);
-        for (int q = 0; q < NP; ++q) {
-            double wq = hs;
-            for (int dd = 0, qq = q; dd < dim; ++dd, qq /= N1) wq *= gw[qq % N1];
-            for (int a = 0; a < NP; ++a)
-                for (int b = 0; b < NP; ++b) {
-                    double gsum = 0.0;
-                    for (int e = 0; e < dim; ++e) {
-                        double va = 1.0, vb = 1.0;
-                        for (int dd = 0, qq = q, aa = a, bb = b; dd < dim; ++dd, qq /= N1, aa /= N1, bb /= N1) {
-                            va *= (dd == e ? Dn : S)[(qq % N1) * N1 + aa % N1];
-                            vb *= (dd == e ? Dn : S)[(qq % N1) * N1 + bb % N1];
-                        }
-                        gsum += va * vb;
-                    }
-                    Kref[((size_t)q * NP + a) * NP + b] = wq * gsum;
+            std::vector<double> A((size_t)h->nint * h->nint, 0.0);
+            const double* c0 = coef_qp + off + (size_t)h->cpl.mu0 * cper;
+            if (h->diag) {
+                std::fill(craw.begin(), craw.end(), 0.0);
+                for (int mi = 0; mi < h->n_mu; ++mi) {
+                    const double wv = h->dw[(size_t)blk * h->n_mu + mi];
+                    if (wv == 0.0) continue;
+                    const double* src = coef_qp + off + (size_t)mi * cper;
+                    for (size_t q = 0; q < cper; ++q) craw[q] += wv * src[q];
                 }
-        }
-        std::vector<double> Ke((size_t)NP * NP);
-        for (long long cell = 0; cell < lc.g.n_cells; ++cell) {
-            int cc[3] = {0, 0, 0};
-            long long r = cell;
-            for (int dd = 0; dd < dim; ++dd) { cc[dd] = r % n; r /= n; }
-            std::vector<int> nodes(NP);
-            for (int a = 0; a < NP; ++a) {
-                long long node = 0, mul = 1;
-                for (int dd = 0, aa = a; dd < dim; ++dd, aa /= N1) { node += (cc[dd] * k + aa % N1) * mul; mul *= n1; }
-                nodes[a] = interior_node[node];
+                c0 = craw.data();
             }
-            std::fill(Ke.begin(), Ke.end(), 0.0);
+            const double vol = std::pow(lc.h, dim), hs = std::pow(lc.h, dim - 2);
+            // reference stiffness integrands Kref[q][a][b] = w_q h^(d-2) sum_e dphi_a/dx_e dphi_b/dx_e (x_q)
+            const int NP = h->NP;
+            std::vector<double> Kref((size_t)NP * NP * NP);
             for (int q = 0; q < NP; ++q) {
-                const double cq = c0[cell * NP + q];
-                const double* kr = &Kref[(size_t)q * NP * NP];
-                for (size_t ab = 0; ab < (size_t)NP * NP; ++ab) Ke[ab] += cq * kr[ab];
-            }
-            for (int a = 0; a < h->NP; ++a) {
-                if (nodes[a] < 0) continue;
-                for (int b = 0; b < h->NP; ++b) {
-                    if (nodes[b] < 0) continue;
-                    const double m = Me1[(size_t)a * h->NP + b] * vol, kv = Ke[(size_t)a * h->NP + b];
-                    for (int i = 0; i < h->NT; ++i)
-                        for (int j = 0; j < h->NT; ++j) {
-                            const size_t row = (size_t)i * ni + nodes[a], col = (size_t)j * ni + nodes[b];
-                            A[row * h->nint + col] += h->At[i * h->NT + j] * m + (i == j ? h->Bt[i] * kv : 0.0);
+                double wq = hs;
+                for (int dd = 0, qq = q; dd < dim; ++dd, qq /= N1) wq *= gw[qq % N1];
+                for (int a = 0; a < NP; ++a)
+                    for (int b = 0; b < NP; ++b) {
+                        double gsum = 0.0;
+                        for (int e = 0; e < dim; ++e) {
+                            double va = 1.0, vb = 1.0;
+                            for (int dd = 0, qq = q, aa = a, bb = b; dd < dim; ++dd, qq /= N1, aa /= N1, bb /= N1) {
+                                va *= (dd == e ? Dn : S)[(qq % N1) * N1 + aa % N1];
+                                vb *= (dd == e ? Dn : S)[(qq % N1) * N1 + bb % N1];
+                            }
+                            gsum += va * vb;
                         }
+                        Kref[((size_t)q * NP + a) * NP + b] = wq * gsum;
+                    }
+            }
+            std::vector<double> Ke((size_t)NP * NP);
+            for (long long cell = 0; cell < lc.g.n_cells; ++cell) {
+                int cc[3] = {0, 0, 0};
+                long long r = cell;
+                for (int dd = 0; dd < dim; ++dd) { cc[dd] = r % n; r /= n; }
+                std::vector<int> nodes(NP);
+                for (int a = 0; a < NP; ++a) {
+                    long long node = 0, mul = 1;
+                    for (int dd = 0, aa = a; dd < dim; ++dd, aa /= N1) { node += (cc[dd] * k + aa % N1) * mul; mul *= n1; }
+                    nodes[a] = interior_node[node];
+                }
+                std::fill(Ke.begin(), Ke.end(), 0.0);
+                for (int q = 0; q < NP; ++q) {
+                    const double cq = c0[cell * NP + q];
+                    const double* kr = &Kref[(size_t)q * NP * NP];
+                    for (size_t ab = 0; ab < (size_t)NP * NP; ++ab) Ke[ab] += cq * kr[ab];
+                }
+                for (int a = 0; a < h->NP; ++a) {
+                    if (nodes[a] < 0) continue;
+                    for (int b = 0; b < h->NP; ++b) {
+                        if (nodes[b] < 0) continue;
+                        const double m = Me1[(size_t)a * h->NP + b] * vol, kv = Ke[(size_t)a * h->NP + b];
+                        for (int i = 0; i < h->NT; ++i)
+                            for (int j = 0; j < h->NT; ++j) {
+                                const size_t row = (size_t)i * ni + nodes[a], col = (size_t)j * ni + nodes[b];
+                                A[row * h->nint + col] += h->At[i * h->NT + j] * m + (i == j ? h->Bt[i] * kv : 0.0);
+                            }
+                    }
                 }
             }
-        }
-        // Gauss-Jordan inverse on the device (the matrix is a few thousand rows at most)
-        if (h->nint > 0) {
-            DevBuf<double> Ad, col;
-            DevBuf<int> perm, status;
-            int zero = 0;
-            SG_TRY(Ad.upload(A.data(), A.size(), "coarse matrix"));
-            SG_TRY(col.alloc(h->nint, "coarse pivots"));
-            SG_TRY(perm.alloc(h->nint, "coarse pivots"));
-            SG_TRY(status.upload(&zero, 1, "status"));
-            SG_HIP(launch_dense_invert(Ad.p, h->nint, col.p, perm.p, status.p,
-                                       h->coarse_invT.p + (size_t)blk * h->nint * h->nint, nullptr));
-            int st = 0;
-            SG_HIP(hipMemcpy(&st, status.p, sizeof(int), hipMemcpyDeviceToHost));
-            if (st) return fail(SG_ESINGULAR, "coarsest-level matrix is singular");
-        }
+            // Gauss-Jordan inverse on the device (the matrix is a few thousand rows at most)
+            if (h->nint > 0) {
+                DevBuf<double> Ad, col;
+                DevBuf<int> perm, status;
+                int zero = 0;
+                SG_TRY(Ad.upload(A.data(), A.size(), "coarse matrix"));
+                SG_TRY(col.alloc(h->nint, "coarse pivots"));
+                SG_TRY(perm.alloc(h->nint, "coarse pivots"));
+                SG_TRY(status.upload(&zero, 1, "status"));
+                SG_HIP(launch_dense_invert(Ad.p, h->nint, col.p, perm.p, status.p,
+                                           h->coarse_invT.p + (size_t)blk * h->nint * h->nint, nullptr));
+                int st = 0;
+                SG_HIP(hipMemcpy(&st, status.p, sizeof(int), hipMemcpyDeviceToHost));
+                if (st) return fail(SG_ESINGULAR, "coarsest-level matrix is singular");
+            }
         }
         std::vector<int> dofs(h->nint);
         for (int i = 0; i < h->NT; ++i)
