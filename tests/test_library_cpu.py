@@ -74,3 +74,68 @@ def test_null_arguments_are_rejected():
     assert sgheat._lib.gmg_vcycle(None, None, None, None) == -1
     assert sgheat._lib.sg_vanka_smooth(None, 0, None, None, 1, None) == -1
     assert sgheat._lib.fgmres_solve_slab(None, None, None, 1e-8, 10, None, None) == -1
+
+
+@pytest.mark.parametrize("field,value", [("diag_blocks", 2), ("transpose", 2), ("n_samples", -1), ("n_samples", 3),
+                                         ("n_members", 2), ("n_members", -1)])
+def test_create_rejects_invalid_batch_fields(field, value):
+    """Sample and member batches need their host arrays; flags take 0 or 1 (all checked before any
+    device work)."""
+    sgheat = _lib()
+    d, keep = _desc(**{field: value})
+    h = ctypes.c_void_p()
+    assert sgheat._lib.sg_create(ctypes.byref(d), ctypes.byref(h)) == -1 and not h.value
+
+
+def test_samples_and_members_are_exclusive():
+    sgheat = _lib()
+    xs = (ctypes.c_double * 4)(0.1, 0.2, 0.3, 0.4)
+    deg = (ctypes.c_int * 1)(1)
+    sc = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
+    d, keep = _desc(n_samples=2, n_members=1)
+    d.samples = ctypes.cast(xs, ctypes.POINTER(ctypes.c_double))
+    d.member_degree = ctypes.cast(deg, ctypes.POINTER(ctypes.c_int))
+    d.member_scale = ctypes.cast(sc, ctypes.POINTER(ctypes.c_double))
+    h = ctypes.c_void_p()
+    assert sgheat._lib.sg_create(ctypes.byref(d), ctypes.byref(h)) == -1
+    assert b"exclusive" in sgheat._lib.sg_last_error()
+
+
+def test_null_handles_are_rejected_by_every_entry_point():
+    sgheat = _lib()
+    L = sgheat._lib
+    assert L.sg_sample_statistics(None, None, None, None, None) == -1
+    assert L.sg_chaos_moments(None, None, None, None, None) == -1
+    assert L.sg_index_set(None, None) == -1
+    assert L.sg_chaos_projection(None, 0, None, None, None) == -1
+    assert L.sg_time_rule(None, 4, None, None) == -1
+    assert L.sg_time_load_weights(None, 4, 1, None, None) == -1
+    assert L.sg_load_vectors(None, 4, 1, None, None, None, None) == -1
+    assert L.sg_separable_vector(None, 1, None, None, 0.0, None, None) == -1
+    assert L.sg_separable_error(None, None, 4, None, None, 4, None, None, 0.0, None, None) == -1
+    assert L.sg_sample_psi(None, 1, None, None) == -1
+    assert L.sg_sample_qp_moments(None, None, 4, 4, None, None) == -1
+    assert L.sg_moment_errors(None, None, 2, 4, None, 4, None, None, None, None, None) == -1
+    assert L.sg_autotune(None, 5, None, None) == -1
+    assert L.sg_set_vcycle_graph(None, 1) == -1
+    assert L.sg_update_coefficients(None, None) == -1
+    assert L.sg_qoi_mean_var(None, None, 1.0, 1.0, None, None, None) == -1
+
+
+@pytest.mark.parametrize("nq1", [1, 4, 6])
+def test_gauss_points_of_any_order_match_the_rule(nq1):
+    """sg_gauss_points against the nq1-point Gauss-Legendre rule mapped to every cell (host only)."""
+    sgheat = _lib()
+    w = sg_inputs.finite_chaos_workload(4, 3, 3, 8, 0, 2).base
+    spec = sgheat.Spec(w.dim, w.n_cells_1d, w.fe_degree, w.time_degree, w.tau, w.n_vars, 0, w.n_levels, w.lo, w.hi)
+    pts = sgheat.gauss_points(spec, 1, nq1)
+    g, _ = np.polynomial.legendre.leggauss(nq1)
+    g = 0.5 * (g + 1.0)
+    n = w.n_cells_1d >> 1
+    h = (w.hi - w.lo) / n
+    for c in [0, n * n - 1, n + 1]:
+        cx, cy = c % n, c // n
+        for q in range(nq1 * nq1):
+            qx, qy = q % nq1, q // nq1
+            assert abs(pts[c, q, 0] - (w.lo + h * (cx + g[qx]))) < 1e-15
+            assert abs(pts[c, q, 1] - (w.lo + h * (cy + g[qy]))) < 1e-15
