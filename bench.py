@@ -255,7 +255,7 @@ def finite_chaos_table(torch, p_max, n_cells=128, n_slabs=64, n_levels=5, march_
                         f"{done} of {n_slabs} slabs marched, M=4, q=6, eta=0.35, slab solves to rtol 1e-10", "rows": rows}
 
 
-def mc_root_n(torch, name="c7", diag_blocks=0):
+def mc_root_n(torch, name="c7", diag_blocks=1):
     """Monte-Carlo error split of the finite-chaos benchmark over cumulative sample windows (the first
     k handles of 128 samples), with the observed rates r = log(E_N0 / E_N) / log(N / N0) against the
     first window."""
@@ -335,8 +335,8 @@ def main():
                     help="also run the finite-chaos benchmark for p_xi = 0..P at the paper's discretisation")
     ap.add_argument("--mc-rootn", action="store_true",
                     help="also run the Monte-Carlo error split over cumulative windows of 128..2048 samples")
-    ap.add_argument("--diag-blocks", action="store_true",
-                    help="per-mode / per-sample diagonal blocks in the preconditioner of the --mc-rootn leg")
+    ap.add_argument("--mc-mean-block", action="store_true",
+                    help="precondition every sample of the --mc-rootn leg with the mean block instead of its own")
     ap.add_argument("--fc-slabs", type=int, default=None, metavar="N",
                     help="march only the first N of the 64 slabs of the finite-chaos benchmark (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -489,7 +489,7 @@ def main():
         out["finite_chaos"] = finite_chaos_table(torch, args.finite_chaos, march_slabs=args.fc_slabs)
 
     if args.mc_rootn:
-        out["mc_root_n"] = mc_root_n(torch, diag_blocks=int(args.diag_blocks))
+        out["mc_root_n"] = mc_root_n(torch, diag_blocks=0 if args.mc_mean_block else 1)
         print(f"[bench] Monte-Carlo root-N windows: {out['mc_root_n']['windows']}", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:

@@ -2,8 +2,9 @@
 samples, the estimators at the space-time quadrature points and their error split (Section 5).
 
 Host orchestration over the slab library (libsgheat.so); every vector-sized step runs in its kernels.
-The samples are split into sample-batch handles (at most 512 / N_t samples each); each handle
-marches its samples slab by slab with the pathwise forcing
+The samples are split into sample-batch handles (at most 512 / N_t samples each; by default each
+sample is preconditioned with its own diagonal block, since the squared-Gaussian coefficient varies
+strongly between samples); each handle marches its samples slab by slab with the pathwise forcing
     F_s^(n) = G_q(xi_s) ( T1^(n) (x) m + sum_mu Psi_mu(xi_s) T2^(n) (x) k_mu )
 (sg_separable_vector over the loads of sg_load_vectors, on top of the transfer JJ U^(n-1)), and after
 every slab the handles add their samples' values and squares at the quadrature points into one array
@@ -27,7 +28,7 @@ class MCErrorStudy:
     """One sg_inputs.MCErrorWorkload."""
 
     def __init__(self, ew, precision=sgheat.SG_FP64, rtol: float = 1e-10, max_iter: int = 500, samples=None,
-                 diag_blocks: int = 0):
+                 diag_blocks: int = 1):
         import torch
         import sg_inputs
         self.ew = ew
