@@ -307,7 +307,8 @@ sg_status sg_moment_errors(sg_handle h, const double* acc, long long n_tot, int 
 sg_status sg_set_vcycle_graph(sg_handle h, int enable);
 
 /* Tile autotuner of the operator kernel: for the full operator on level 0 and the mean-block operator
- * on every level (and their FP32 versions with SG_MIXED), times `reps` launches of the cell kernel for
+ * on every level (and their FP32 versions with SG_MIXED), times `reps` launches of the cell kernel and
+ * its node gather for
  * every feasible number of cells per workgroup (1, 2, 3, 4, 5, 6, 8, 10, 12, 16; limited by 512 threads
  * and 160 KB of LDS per workgroup) on this handle's own sizes and keeps the fastest (median) for all
  * later calls.  Without it the number comes from the runtime occupancy calculator.  The

@@ -49,6 +49,7 @@ struct ApplyArgs {
     int nblocks;
     int mu0;              // position of mu = 0 in the coefficient list
     int mum[8];           // position of mu = e_m (m = 1..M) in the coefficient list, -1 if absent
+    int merge;            // 1: sum the x faces shared by the workgroup's cells before storing
 };
 
 // out[.., o, ..] (+)= sum_i M(o, i) in[.., i, ..] along direction DIR of an N1^DIM point block;
@@ -129,6 +130,35 @@ __device__ __forceinline__ void store_broken(T* __restrict__ s, const T (&Y)[ipo
             mul *= nb1;
         }
         s[base + off] = Y[p] * scale;
+    }
+}
+
+// Store into the x-merged layout: along x the broken index is seg (cpb k + 1) + (local x node of the
+// segment), n k + segs entries in all (no more than the n (k + 1) of the per-cell layout), so the faces
+// shared by the cells of one segment appear once; y and z as in store_broken.
+// write_face: this cell also stores its x = k face (the last cell of the segment).
+template <int DIM, int K, typename T>
+__device__ __forceinline__ void store_merged(T* __restrict__ s, const T (&Y)[ipow(K + 1, DIM)], const int* cc, int n,
+                                             int comp, int seg, int segs, int cpb, int slot, bool write_face) {
+    constexpr int N1 = K + 1;
+    const long long nb1 = (long long)n * N1;
+    const long long sw = (long long)cpb * K + 1;       // broken x entries of a full segment
+    const long long nbx = (long long)n * K + segs;     // all x entries (the last segment may be shorter)
+    long long base = comp;
+#pragma unroll
+    for (int d = DIM - 1; d >= 1; --d) base = base * nb1 + (long long)cc[d] * N1;
+    base = base * nbx + seg * sw + (long long)slot * K;
+#pragma unroll
+    for (int p = 0; p < ipow(N1, DIM); ++p) {
+        const int ax = p % N1;
+        if (ax == K && !write_face) continue;
+        long long off = ax, mul = nbx;
+#pragma unroll
+        for (int d = 1; d < DIM; ++d) {
+            off += ((p / ipow(N1, d)) % N1) * mul;
+            mul *= nb1;
+        }
+        s[base + off] = Y[p];
     }
 }
 
@@ -373,9 +403,8 @@ __device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const Tables<T
         }
     }
 
-    // integrate back to the nodes and store the cell-local result
+    // integrate back to the nodes (the caller scales by B_t and stores)
     sweeps_ip<DIM, N1, true>(W, tb.S);
-    if (active) store_broken<DIM, K, T>(a.s, W, bt_of<NT>(tb, ti), cc, a.g.n, comp);
 }
 
 // Minimum resident waves per SIMD the register allocator must allow (more waves hide the LDS and
@@ -483,6 +512,32 @@ __global__ void __launch_bounds__(WIDE ? 1024 : (ipow(K + 1, DIM) > 27 ? 256 : 5
     sweeps_ip<DIM, N1, false>(A, tb.S);
     apply_body<DIM, K, NT, T, MEAN, CM, CP, WIDE>(a, tb, A, B, slot_rows, slot_coef, ent_g, ent_c, ent_w, e0, e1, comp, alpha,
                                             ti, active, cc, exch, cl, SS, CS, active ? ci : 0);
+
+    const T scale = bt_of<NT>(tb, ti);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) B[p] *= scale;
+    if constexpr (!WIDE) {
+        if (a.merge) {
+            // x faces shared by consecutive cells of the segment: the upper cell adds the lower cell's
+            // x = k face (the same two-term sum the gather would form) and the lower one skips it
+            constexpr int NS = NP / N1;
+            __syncthreads();                              // the exchange rows are free again
+            T* const mine = slot_rows + comp * NP;
+#pragma unroll
+            for (int j = 0; j < NS; ++j) mine[j] = B[j * N1 + K];
+            __syncthreads();
+            if (slot > 0) {
+                const T* const prev = mine - SS;
+#pragma unroll
+                for (int j = 0; j < NS; ++j) B[j * N1] = prev[j] + B[j * N1];
+            }
+            if (active)
+                store_merged<DIM, K, T>(a.s, B, cc, n, comp, lb % segs, segs, cpb, slot,
+                                        slot == cpb - 1 || x0 + slot == n - 1);
+            return;
+        }
+    }
+    if (active) store_broken<DIM, K, T>(a.s, B, T(1), cc, n, comp);
 }
 
 // Cells per workgroup: the largest number of busy lanes per CU, with the number of resident
@@ -591,6 +646,8 @@ hipError_t run_apply(const ApplyOp<T>& op, const T* x, T* s_out, hipStream_t s) 
             a.mu0 = op.mu0;
             for (int m = 0; m < 8; ++m) a.mum[m] = op.mum[m];
             a.cpb = 1;
+            a.merge = 0;
+            if (op.used_cpb) *op.used_cpb = 1;
             const size_t lds = per_cell + 16;
             if (nc > 1024 || lds > 160 * 1024) return hipErrorInvalidConfiguration;
             if (lds > 64 * 1024)
@@ -606,6 +663,8 @@ hipError_t run_apply(const ApplyOp<T>& op, const T* x, T* s_out, hipStream_t s) 
     const size_t fixed = op.mean ? 16 : (size_t)op.n_ent * (sizeof(T) + 2 * sizeof(int)) + 16;
     const int cpb = op.cells_per_block > 0 ? op.cells_per_block : choose_cpb((const void*)kern, nc, fixed, per_cell, MAXT);
     a.cpb = cpb;
+    a.merge = op.merge && cpb > 1;
+    if (op.used_cpb) *op.used_cpb = cpb;
     const int threads = nc * cpb;
     const size_t lds = fixed + per_cell * cpb;
     if (threads > MAXT || lds > 160 * 1024) return hipErrorInvalidConfiguration;

@@ -51,11 +51,15 @@ __global__ void k_transfer_1d(int dim, long long total, int i0, int i1, int o0, 
 template <typename T, int OP, int DIM, int K>
 __global__ void __launch_bounds__(256)
     k_node_gather(Grid g, const T* __restrict__ s_in, const T* __restrict__ x, const T* __restrict__ b,
-                  T* __restrict__ out, T omega) {
+                  T* __restrict__ out, T omega, unsigned sx) {
     constexpr int N1 = K + 1;
     const unsigned n1 = g.n1, nc = g.n;
     const unsigned nb1 = nc * N1;
-    unsigned nbn = nb1;
+    // x: segments of sx node intervals (sx = K: one cell), sx + 1 broken entries each except a shorter
+    // last one: (n1 - 1) + nsx entries in all
+    const unsigned nsx = (n1 - 1 + sx - 1) / sx;
+    const unsigned nbx = (n1 - 1) + nsx;
+    unsigned nbn = nbx;
     if (DIM >= 2) nbn *= nb1;
     if (DIM == 3) nbn *= nb1;
     const unsigned nn = (unsigned)g.n_nodes;
@@ -74,14 +78,16 @@ __global__ void __launch_bounds__(256)
             const unsigned i = (d == DIM - 1) ? r : r % n1;
             r /= n1;
             bnd |= (i == 0) | (i == n1 - 1);
-            const unsigned c = i / K;
-            if (i % K == 0 && i > 0 && i < n1 - 1) {
-                lo[d] = (c - 1) * N1 + K;
-                hi[d] = c * N1;
+            const unsigned sl = d == 0 ? sx : (unsigned)K;      // segment length along d
+            const unsigned ns = d == 0 ? nsx : nc;               // segments along d
+            const unsigned c = i / sl;
+            if (i % sl == 0 && i > 0 && i < n1 - 1) {
+                lo[d] = (c - 1) * (sl + 1) + sl;
+                hi[d] = c * (sl + 1);
                 whi[d] = T(1);
             } else {
-                const unsigned cl = c < nc ? c : nc - 1;
-                lo[d] = cl * N1 + (i - cl * K);
+                const unsigned cl = c < ns ? c : ns - 1;
+                lo[d] = cl * (sl + 1) + (i - cl * sl);
                 hi[d] = lo[d];
             }
         }
@@ -97,12 +103,12 @@ __global__ void __launch_bounds__(256)
         T sum = T(0);
         T cnt = T(1);
         if (DIM == 2) {
-            const unsigned y0 = lo[1] * nb1, y1 = hi[1] * nb1;
+            const unsigned y0 = lo[1] * nbx, y1 = hi[1] * nbx;
             sum = (sc[y0 + lo[0]] + whi[0] * sc[y0 + hi[0]]) + whi[1] * (sc[y1 + lo[0]] + whi[0] * sc[y1 + hi[0]]);
             cnt = (T(1) + whi[0]) * (T(1) + whi[1]);
         } else {
-            const unsigned z0 = lo[2] * nb1 * nb1, z1 = hi[2] * nb1 * nb1;
-            const unsigned y0 = lo[1] * nb1, y1 = hi[1] * nb1;
+            const unsigned z0 = lo[2] * nb1 * nbx, z1 = hi[2] * nb1 * nbx;
+            const unsigned y0 = lo[1] * nbx, y1 = hi[1] * nbx;
             const T s00 = sc[z0 + y0 + lo[0]] + whi[0] * sc[z0 + y0 + hi[0]];
             const T s01 = sc[z0 + y1 + lo[0]] + whi[0] * sc[z0 + y1 + hi[0]];
             const T s10 = sc[z1 + y0 + lo[0]] + whi[0] * sc[z1 + y0 + hi[0]];
@@ -385,11 +391,12 @@ hipError_t launch_transfer_1d(int dim, int ncomp, const int* in_dims, const int*
 
 template <typename T>
 hipError_t launch_node_gather(GatherOp op, int dim, int k, Grid g, int ncomp, const T* s_in, const T* x, const T* b,
-                              T* out, T omega, hipStream_t s) {
-    if (ncomp > 65535 || g.n_nodes > 0x7fffffffLL || k < 1 || k > 4) return hipErrorInvalidConfiguration;
+                              T* out, T omega, int sx, hipStream_t s) {
+    if (ncomp > 65535 || g.n_nodes > 0x7fffffffLL || k < 1 || k > 4 || sx < k || sx % k) return hipErrorInvalidConfiguration;
     const unsigned bx = std::min<long long>((g.n_nodes + 255) / 256, 4096);
     const dim3 grid(bx, ncomp), block(256);
-#define SG_NG(OP_, D_, K_) hipLaunchKernelGGL((k_node_gather<T, OP_, D_, K_>), grid, block, 0, s, g, s_in, x, b, out, omega)
+#define SG_NG(OP_, D_, K_) \
+    hipLaunchKernelGGL((k_node_gather<T, OP_, D_, K_>), grid, block, 0, s, g, s_in, x, b, out, omega, (unsigned)sx)
 #define SG_NG_K(OP_, D_)                          \
     switch (k) {                                  \
         case 1: SG_NG(OP_, D_, 1); break;         \
@@ -512,9 +519,9 @@ template hipError_t launch_transfer_1d<double>(int, int, const int*, const int*,
 template hipError_t launch_transfer_1d<float>(int, int, const int*, const int*, int, const int*, const float*, int,
                                               const float*, float*, bool, hipStream_t);
 template hipError_t launch_node_gather<double>(GatherOp, int, int, Grid, int, const double*, const double*,
-                                               const double*, double*, double, hipStream_t);
+                                               const double*, double*, double, int, hipStream_t);
 template hipError_t launch_node_gather<float>(GatherOp, int, int, Grid, int, const float*, const float*, const float*,
-                                              float*, float, hipStream_t);
+                                              float*, float, int, hipStream_t);
 template hipError_t launch_coarse_solve<double>(const double*, long long, int, const int*, int, long long,
                                                 const double*, double*, hipStream_t);
 template hipError_t launch_coarse_solve<float>(const double*, long long, int, const int*, int, long long, const float*,

@@ -784,6 +784,8 @@ ApplyOp<T> make_op(const sg_handle h, int level, bool full) {
     }
     op.cells_per_block = apply_cpb_override();
     if (op.cells_per_block == 0 && level < 16) op.cells_per_block = h->tuned_cpb[sizeof(T) == 4][full][level];
+    op.merge = 1;
+    op.used_cpb = nullptr;
     return op;
 }
 
@@ -809,8 +811,8 @@ T* sbuf_as(sg_handle h) {
     return reinterpret_cast<T*>(h->sbuf.p);
 }
 
-// Time k_apply alone for every feasible cells-per-workgroup value on one level and keep the fastest
-// (median of `reps` event-timed launches each).
+// Time the operator (cell kernel + gather) for every feasible cells-per-workgroup value on one level
+// and keep the fastest (median of `reps` event-timed launches each).
 template <typename T>
 sg_status autotune_apply(sg_handle h, int level, bool full, int reps, hipStream_t s) {
     Level& lv = h->lv[level];
@@ -826,13 +828,22 @@ sg_status autotune_apply(sg_handle h, int level, bool full, int reps, hipStream_
     for (int cpb : kCand) {
         if (cpb > lv.g.n) break;
         op.cells_per_block = cpb;
+        // the cell kernel and its gather together (the merged layout's gain is in the gather)
+        int used = 1;
+        op.used_cpb = &used;
         hipError_t err = launch_apply<T>(op, x, sbuf_as<T>(h), s);
         if (err == hipErrorInvalidConfiguration) continue;     // more threads or LDS than one workgroup has
         if (err != hipSuccess) { st = fail(SG_EHIP, std::string("autotune: ") + hipGetErrorString(err)); break; }
-        (void)launch_apply<T>(op, x, sbuf_as<T>(h), s);
+        const int sx = apply_segment(op, used);
+        auto once = [&]() {
+            (void)launch_apply<T>(op, x, sbuf_as<T>(h), s);
+            (void)launch_node_gather<T>(GATHER_SET, op.dim, op.k, op.g, h->n_xi * h->NT, sbuf_as<T>(h), x, nullptr,
+                                        Prec<T>::r(lv), T(0), sx, s);
+        };
+        once();
         (void)hipEventRecord(ev[0], s);
         for (int r = 0; r < reps; ++r) {
-            (void)launch_apply<T>(op, x, sbuf_as<T>(h), s);
+            once();
             (void)hipEventRecord(ev[r + 1], s);
         }
         if (hipEventSynchronize(ev[reps]) != hipSuccess) { st = fail(SG_EHIP, "autotune: event"); break; }
@@ -850,9 +861,12 @@ sg_status autotune_apply(sg_handle h, int level, bool full, int reps, hipStream_
 // y = A x (b == nullptr) or y = b - A x, for the operator described by op
 template <typename T>
 sg_status op_apply(sg_handle h, const ApplyOp<T>& op, const T* x, T* y, const T* b, hipStream_t s) {
-    SG_HIP(launch_apply<T>(op, x, sbuf_as<T>(h), s));
+    ApplyOp<T> o = op;
+    int cpb = 1;
+    o.used_cpb = &cpb;
+    SG_HIP(launch_apply<T>(o, x, sbuf_as<T>(h), s));
     SG_HIP(launch_node_gather<T>(b ? GATHER_RESIDUAL : GATHER_SET, op.dim, op.k, op.g, h->n_xi * h->NT, sbuf_as<T>(h), x,
-                                 b, y, T(0), s));
+                                 b, y, T(0), apply_segment(o, cpb), s));
     return SG_OK;
 }
 
@@ -872,7 +886,7 @@ sg_status smooth_level(sg_handle h, int l, const T* b, T* x, int sweeps, bool x_
         else
             SG_HIP(launch_vanka_cells<T>(h->d.dim, h->d.fe_degree, h->NT, lv.g, h->n_xi, inv, r, sbuf_as<T>(h), s));
         SG_HIP(launch_node_gather<T>(GATHER_VANKA, h->d.dim, h->d.fe_degree, lv.g, h->n_xi * h->NT, sbuf_as<T>(h),
-                                     nullptr, b, x, (T)h->d.vanka_omega, s));
+                                     nullptr, b, x, (T)h->d.vanka_omega, h->d.fe_degree, s));
     }
     return SG_OK;
 }
@@ -1028,14 +1042,17 @@ sg_status zero_coef(sg_handle h, hipStream_t s) {
 // Level-0 operator variant: time tables `tb`, coefficient modes `coef` (the mean mode alone when
 // !full); cell-local results go to sbuf and, with y, are gathered into y.
 sg_status variant_apply(sg_handle h, const Tables<double>* tb, const double* coef, bool full, const double* x,
-                        double* y, GatherOp gop, hipStream_t s) {
+                        double* y, GatherOp gop, hipStream_t s, bool per_cell = false) {
     ApplyOp<double> op = make_op<double>(h, 0, full);
     op.tables = tb;
     op.coef = coef;
+    op.merge = per_cell ? 0 : 1;     // per-cell results (for cell-wise forms) need the unmerged layout
+    int cpb = 1;
+    op.used_cpb = &cpb;
     SG_HIP(launch_apply<double>(op, x, h->sbuf.p, s));
     if (y)
         SG_HIP(launch_node_gather<double>(gop, h->d.dim, h->d.fe_degree, h->lv[0].g, h->n_xi * h->NT, h->sbuf.p, x,
-                                          nullptr, y, 0.0, s));
+                                          nullptr, y, 0.0, apply_segment(op, cpb), s));
     return SG_OK;
 }
 
@@ -1332,7 +1349,7 @@ sg_status sg_stiffness_form_cells(sg_handle h, int mu_index, const double* coef_
     SG_HIP(hipMemcpyAsync(dst, h->hstage.data(), per_mode * sizeof(double), hipMemcpyHostToDevice, s));
     const std::vector<double> no_mass((size_t)h->NT * h->NT, 0.0);
     const Tables<double> tb = tables_with(h, no_mass);
-    SG_TRY(variant_apply(h, &tb, h->fcoef.p, !mean, u, nullptr, GATHER_SET, s));
+    SG_TRY(variant_apply(h, &tb, h->fcoef.p, !mean, u, nullptr, GATHER_SET, s, true));
     SG_HIP(launch_cell_dot(dim, h->d.fe_degree, l0.g, h->n_xi * h->NT, lam, h->sbuf.p, out, s));
     SG_HIP(hipStreamSynchronize(s));   // the host staging array is reused by the next call
     return SG_OK;
@@ -1518,7 +1535,7 @@ sg_status sg_load_vectors(sg_handle h, int nq1, int n_fields, const double* fval
         SG_HIP(launch_load_cells(h->d.dim, h->d.fe_degree, l0.g, nq1, tb, l0.h, fval ? fval + off : nullptr,
                                  fgrad ? fgrad + off * h->d.dim : nullptr, nf, h->sbuf.p, s));
         SG_HIP(launch_node_gather<double>(GATHER_INTERIOR, h->d.dim, h->d.fe_degree, l0.g, nf, h->sbuf.p, nullptr,
-                                          nullptr, out + (long long)f0 * l0.g.n_nodes, 0.0, s));
+                                          nullptr, out + (long long)f0 * l0.g.n_nodes, 0.0, h->d.fe_degree, s));
     }
     return SG_OK;
 }
