@@ -421,6 +421,36 @@ __host__ __device__ constexpr int padded_stride(int n) {
     return n + ((1 - n) % nb + nb) % nb;
 }
 
+// Position of thread t of workgroup b: its cell slot and component, the workgroup's segment of cpb
+// cells along x (segs per cell row; rows in the XCD-local tiled order) and the cell's coordinates.
+template <int DIM>
+struct ApplyPos {
+    int slot, comp, seg, segs, x0;
+    bool active;
+    long long cell0;   // first cell of the segment
+    int cc[3];
+};
+template <int DIM, typename T>
+__device__ __forceinline__ ApplyPos<DIM> apply_position(const ApplyArgs<T>& a, int cpb, int t, int b) {
+    ApplyPos<DIM> P;
+    const int n = a.g.n;
+    P.slot = t % cpb;
+    P.comp = t / cpb;
+    P.segs = (n + cpb - 1) / cpb;
+    const int lb = xcd_position(b, a.nblocks);
+    P.seg = lb % P.segs;
+    P.x0 = P.seg * cpb;
+    P.cell0 = (long long)tiled_row<DIM>(lb / P.segs, n) * n + P.x0;
+    P.active = P.x0 + P.slot < n;
+    long long r = P.active ? P.cell0 + P.slot : 0;
+    P.cc[0] = P.cc[1] = P.cc[2] = 0;
+    for (int d = 0; d < DIM; ++d) {
+        P.cc[d] = (int)(r % n);
+        r /= n;
+    }
+    return P;
+}
+
 // WIDE: one cell per workgroup of up to 1024 threads (N_xi N_t > 512 components), coupling entries
 // read from memory instead of LDS.
 template <int DIM, int K, int NT, typename T, bool MEAN, int CM = 0, int CP = 0, bool WIDE = false>
@@ -442,28 +472,16 @@ __global__ void __launch_bounds__(WIDE ? 1024 : (ipow(K + 1, DIM) > 27 ? 256 : 5
 
     const int t = threadIdx.x;
     const int nthreads = NC * cpb;                           // the workgroup size
-    const int slot = t % cpb;
-    const int comp = t / cpb;
+    const ApplyPos<DIM> P = apply_position<DIM>(a, cpb, t, blockIdx.x);
+    const int slot = P.slot, comp = P.comp, x0 = P.x0;
     const int alpha = comp / NT;
     const int ti = comp % NT;
-    // workgroup -> (cell row, segment of cpb cells along x); rows in the XCD-local tiled order
     const int n = a.g.n, n1 = a.g.n1;
-    const int segs = (n + cpb - 1) / cpb;
-    const int lb = xcd_position(blockIdx.x, a.nblocks);
-    const int x0 = (lb % segs) * cpb;
-    const long long cell0 = (long long)tiled_row<DIM>(lb / segs, n) * n + x0;
+    const long long cell0 = P.cell0;
     const long long ci = cell0 + slot;
-    const bool active = x0 + slot < n;
+    const bool active = P.active;
     const long long nn = a.g.n_nodes;
-
-    int cc[3] = {0, 0, 0};
-    {
-        long long r = active ? ci : 0;
-        for (int d = 0; d < DIM; ++d) {
-            cc[d] = (int)(r % n);
-            r /= n;
-        }
-    }
+    const int* const cc = P.cc;
 
     // stage the coefficient values of this block's cells (contiguous in memory)
     for (int idx = t; idx < a.n_mu * NP * cpb; idx += nthreads) {
@@ -513,7 +531,14 @@ __global__ void __launch_bounds__(WIDE ? 1024 : (ipow(K + 1, DIM) > 27 ? 256 : 5
     apply_body<DIM, K, NT, T, MEAN, CM, CP, WIDE>(a, tb, A, B, slot_rows, slot_coef, ent_g, ent_c, ent_w, e0, e1, comp, alpha,
                                             ti, active, cc, exch, cl, SS, CS, active ? ci : 0);
 
-    const T scale = bt_of<NT>(tb, ti);
+    // Register-resident chaos coupling on cells of up to 27 points: the position is formed again from
+    // opaque copies of the ids, since the first one, kept alive across the cell work, would take
+    // registers at its peak (and be spilled to scratch memory).  The other variants keep it (their
+    // register allocation does as well or better with it).
+    int t2 = threadIdx.x, b2 = blockIdx.x;
+    if constexpr (CM > 0 && NP <= 27) asm volatile("" : "+v"(t2), "+s"(b2));
+    const ApplyPos<DIM> E = apply_position<DIM>(a, cpb, t2, b2);
+    const T scale = bt_of<NT>(tb, E.comp % NT);
 #pragma unroll
     for (int p = 0; p < NP; ++p) B[p] *= scale;
     if constexpr (!WIDE) {
@@ -522,22 +547,22 @@ __global__ void __launch_bounds__(WIDE ? 1024 : (ipow(K + 1, DIM) > 27 ? 256 : 5
             // x = k face (the same two-term sum the gather would form) and the lower one skips it
             constexpr int NS = NP / N1;
             __syncthreads();                              // the exchange rows are free again
-            T* const mine = slot_rows + comp * NP;
+            T* const mine = exch + (size_t)E.slot * SS + E.comp * NP;
 #pragma unroll
             for (int j = 0; j < NS; ++j) mine[j] = B[j * N1 + K];
             __syncthreads();
-            if (slot > 0) {
+            if (E.slot > 0) {
                 const T* const prev = mine - SS;
 #pragma unroll
                 for (int j = 0; j < NS; ++j) B[j * N1] = prev[j] + B[j * N1];
             }
-            if (active)
-                store_merged<DIM, K, T>(a.s, B, cc, n, comp, lb % segs, segs, cpb, slot,
-                                        slot == cpb - 1 || x0 + slot == n - 1);
+            if (E.active)
+                store_merged<DIM, K, T>(a.s, B, E.cc, a.g.n, E.comp, E.seg, E.segs, cpb, E.slot,
+                                        E.slot == cpb - 1 || E.x0 + E.slot == a.g.n - 1);
             return;
         }
     }
-    if (active) store_broken<DIM, K, T>(a.s, B, T(1), cc, n, comp);
+    if (E.active) store_broken<DIM, K, T>(a.s, B, T(1), E.cc, a.g.n, E.comp);
 }
 
 // Cells per workgroup: the largest number of busy lanes per CU, with the number of resident
