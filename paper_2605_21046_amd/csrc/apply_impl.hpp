@@ -252,6 +252,15 @@ __device__ __forceinline__ void couple_point(T* rows, const T* crow, int q, int 
     }
 }
 
+// Makes the values opaque to the compiler at this point, so the arithmetic that forms them is done
+// here: left alone, the compiler sinks the integration of every direction to the end of the cell
+// work, past the barriers, and keeps all the flux values it reads live until then (register spills).
+template <int N, typename T>
+__device__ __forceinline__ void pin_values(T (&W)[N]) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) asm volatile("" : "+v"(W[q]));
+}
+
 // Points u_q of one (cell, component) at the Gauss points are in U; W accumulates the integrand.
 template <int DIM, int K, int NT, typename T, bool MEAN, int CM, int CP, bool WIDE = false>
 __device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const Tables<T>& tb, T (&U)[ipow(K + 1, DIM)],
@@ -355,6 +364,7 @@ __device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const Tables<T
                     for (int o = 0; o < N1; ++o) W[base + o * st] += tb.D[s * N1 + o] * f;
                 }
             }
+            pin_values(W);
         }
     } else {
         __syncthreads();
@@ -399,6 +409,7 @@ __device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const Tables<T
                     for (int o = 0; o < N1; ++o) W[base + o * st] += tb.D[s * N1 + o] * F[j];
                 }
             }
+            pin_values(W);
             __syncthreads();
         }
     }
