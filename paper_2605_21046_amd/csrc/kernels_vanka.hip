@@ -319,7 +319,9 @@ __global__ void __launch_bounds__(vanka_threads(DIM, K, NT))
     constexpr int KS = (NPP + 3) / 4;     // k-steps
     constexpr int KP = KS * 4;            // rows of the LDS tile (zero beyond n_p)
     constexpr int LR = (KP + 63) / 64 * 64;
-    constexpr int PF = KS < 16 ? KS : 16; // B fragments in flight
+    // B fragments in flight: 16, or 8 for patches of more than 128 rows (whose three accumulator
+    // tiles and gather registers leave no room for 16 within the 3-waves-per-SIMD budget)
+    constexpr int PF = KS < 16 ? KS : (NPP > 128 ? 8 : 16);
     constexpr int NG = vanka_threads(DIM, K, NT) / LR;   // gather groups
     constexpr int LDR = kVankaLdr;
     constexpr int GB = (LDR + NG - 1) / NG;               // gathered values per thread and pass
