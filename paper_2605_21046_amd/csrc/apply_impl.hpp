@@ -296,6 +296,7 @@ __device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const Tables<T
         for (int d = 0; d < DIM; ++d) wq *= tb.w[(q / ipow(N1, d)) % N1];
         W[q] *= wq;
     }
+    pin_values(W);
 
     if constexpr (MEAN) {
         // mean block: flux = a_0(x_q) * d u / d x_dir, all in registers
@@ -321,6 +322,7 @@ __device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const Tables<T
 #pragma unroll
                     for (int o = 0; o < N1; ++o) W[base + o * st] += tb.D[s * N1 + o] * F[j];
                 }
+                pin_values(W);
             }
         }
     } else if constexpr (CM > 0) {
@@ -419,10 +421,12 @@ __device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const Tables<T
 }
 
 // Minimum resident waves per SIMD the register allocator must allow (more waves hide the LDS and
-// barrier latency of the exchange phases).
-template <int NP, typename T>
+// barrier latency of the exchange phases).  The FP64 mean block of cells up to 27 points fits the
+// 168 registers of 3 waves without spilling (with its integration pinned slice by slice); the
+// coupled FP64 kernels need about 210 and keep 2.
+template <int NP, typename T, bool MEAN>
 constexpr int apply_waves_per_eu() {
-    return NP > 27 ? 1 : (sizeof(T) == 8 ? 2 : 3);
+    return NP > 27 ? 1 : (sizeof(T) == 8 && !MEAN ? 2 : 3);
 }
 
 // Per-slot LDS strides padded so consecutive slots start on different banks.
@@ -466,7 +470,7 @@ __device__ __forceinline__ ApplyPos<DIM> apply_position(const ApplyArgs<T>& a, i
 // read from memory instead of LDS.
 template <int DIM, int K, int NT, typename T, bool MEAN, int CM = 0, int CP = 0, bool WIDE = false>
 __global__ void __launch_bounds__(WIDE ? 1024 : (ipow(K + 1, DIM) > 27 ? 256 : 512))
-    __attribute__((amdgpu_waves_per_eu(WIDE ? 4 : apply_waves_per_eu<ipow(K + 1, DIM), T>())))
+    __attribute__((amdgpu_waves_per_eu(WIDE ? 4 : apply_waves_per_eu<ipow(K + 1, DIM), T, MEAN>())))
     k_apply(ApplyArgs<T> a, Tables<T> tb) {
     constexpr int N1 = K + 1;
     constexpr int NP = ipow(N1, DIM);
