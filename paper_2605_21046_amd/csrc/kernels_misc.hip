@@ -14,21 +14,22 @@ namespace sg {
 
 namespace {
 
-template <typename T>
-__global__ void k_transfer_1d(int dim, long long total, int i0, int i1, int o0, int o1, int o2, int dir,
+// I: index type, unsigned 32-bit when every index of the pass fits (the launcher checks), so the
+// per-element divisions are 32-bit ones; long long otherwise.
+template <typename T, typename I>
+__global__ void k_transfer_1d(int dim, I total, int i0, int i1, int o0, int o1, int o2, int dir,
                               const int* __restrict__ tidx, const T* __restrict__ tw, int width,
                               const T* __restrict__ in, T* __restrict__ out, bool accumulate,
-                              long long in_comp, long long out_comp) {
-    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
-         idx += (long long)gridDim.x * blockDim.x) {
-        long long r = idx;
-        const int x0 = r % o0;
-        r /= o0;
-        const int x1 = r % o1;
-        r /= o1;
+                              I in_comp, I out_comp) {
+    for (I idx = blockIdx.x * (I)blockDim.x + threadIdx.x; idx < total; idx += (I)gridDim.x * blockDim.x) {
+        I r = idx;
+        const int x0 = (int)(r % (I)o0);
+        r /= (I)o0;
+        const int x1 = (int)(r % (I)o1);
+        r /= (I)o1;
         int x2 = 0;
-        if (dim == 3) { x2 = r % o2; r /= o2; }
-        const long long c = r;
+        if (dim == 3) { x2 = (int)(r % (I)o2); r /= (I)o2; }
+        const I c = r;
         const int o = dir == 0 ? x0 : (dir == 1 ? x1 : x2);
         T acc = T(0);
         for (int w = 0; w < width; ++w) {
@@ -38,7 +39,7 @@ __global__ void k_transfer_1d(int dim, long long total, int i0, int i1, int o0, 
             const int y0 = dir == 0 ? src : x0;
             const int y1 = dir == 1 ? src : x1;
             const int y2 = dir == 2 ? src : x2;
-            acc += wt * in[c * in_comp + ((long long)y2 * i1 + y1) * i0 + y0];
+            acc += wt * in[c * in_comp + ((I)y2 * (I)i1 + (I)y1) * (I)i0 + (I)y0];
         }
         if (accumulate) out[idx] += acc;
         else out[idx] = acc;
@@ -383,9 +384,17 @@ hipError_t launch_transfer_1d(int dim, int ncomp, const int* in_dims, const int*
     long long out_comp = (long long)out_dims[0] * out_dims[1] * (dim == 3 ? out_dims[2] : 1);
     long long in_comp = (long long)in_dims[0] * in_dims[1] * (dim == 3 ? in_dims[2] : 1);
     const long long total = out_comp * ncomp;
-    hipLaunchKernelGGL(k_transfer_1d<T>, dim3(grid_for(total, 256, 65536)), dim3(256), 0, s, dim, total, in_dims[0],
-                       in_dims[1], out_dims[0], out_dims[1], dim == 3 ? out_dims[2] : 1, dir, tidx, tw, width, in, out,
-                       accumulate, in_comp, out_comp);
+    const unsigned grid = grid_for(total, 256, 65536);
+    // 32-bit indices when the output loop (with one grid stride of headroom) and the input fit in 2^31
+    const bool narrow = total + (long long)grid * 256 < (1LL << 31) && in_comp * ncomp < (1LL << 31);
+    if (narrow)
+        hipLaunchKernelGGL((k_transfer_1d<T, unsigned>), dim3(grid), dim3(256), 0, s, dim, (unsigned)total, in_dims[0],
+                           in_dims[1], out_dims[0], out_dims[1], dim == 3 ? out_dims[2] : 1, dir, tidx, tw, width, in,
+                           out, accumulate, (unsigned)in_comp, (unsigned)out_comp);
+    else
+        hipLaunchKernelGGL((k_transfer_1d<T, long long>), dim3(grid), dim3(256), 0, s, dim, total, in_dims[0],
+                           in_dims[1], out_dims[0], out_dims[1], dim == 3 ? out_dims[2] : 1, dir, tidx, tw, width, in,
+                           out, accumulate, in_comp, out_comp);
     return hipGetLastError();
 }
 
