@@ -14,22 +14,94 @@ namespace sg {
 
 namespace {
 
-// I: index type, unsigned 32-bit when every index of the pass fits (the launcher checks), so the
-// per-element divisions are 32-bit ones; long long otherwise.
-template <typename T, typename I>
-__global__ void k_transfer_1d(int dim, I total, int i0, int i1, int o0, int o1, int o2, int dir,
+// Quotient by an invariant divisor d (1 <= d < 2^32) with one high multiply, after Granlund and
+// Montgomery, "Division by invariant integers using multiplication" (PLDI 1994): with
+// l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1, floor(n / d) equals
+// (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0), t = floor(m n / 2^32), for every 32-bit n.
+struct FastDiv {
+    unsigned d, m;
+    int s1, s2;
+};
+FastDiv make_fastdiv(unsigned d) {
+    int l = 0;
+    while ((1ull << l) < d) ++l;
+    const unsigned long long m = ((1ull << 32) * ((1ull << l) - d)) / d + 1;
+    return {d, (unsigned)m, l < 1 ? l : 1, l > 1 ? l - 1 : 0};
+}
+__device__ __forceinline__ unsigned fast_quot(const FastDiv& f, unsigned n) {
+    const unsigned t = __umulhi(f.m, n);
+    return (t + ((n - t) >> f.s1)) >> f.s2;
+}
+
+// One 1D transfer pass, one output element per thread.  Narrow form: every index of the pass fits
+// in 31 bits (the launcher checks) and the divisions by the output extents use FastDiv.  W > 0: the
+// band width as a compile-time constant, so the W table entries and inputs of an element are loaded
+// together, unconditionally (every table entry holds a valid index), before the sum; the sum runs
+// over w in order and skips zero weights, the same arithmetic as the runtime-width loop (W = 0),
+// where each load waits for the weight test of its term.
+template <typename T, int W>
+__global__ void k_transfer_1d_narrow(int dim, unsigned total, int i0, int i1, FastDiv f0, FastDiv f1, FastDiv f2,
+                                     int dir, const int* __restrict__ tidx, const T* __restrict__ tw, int width,
+                                     const T* __restrict__ in, T* __restrict__ out, bool accumulate, unsigned in_comp) {
+    const unsigned istr = dir == 0 ? 1u : (dir == 1 ? (unsigned)i0 : (unsigned)i0 * (unsigned)i1);
+    for (unsigned idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
+        unsigned r = idx;
+        unsigned q = fast_quot(f0, r);
+        const int x0 = (int)(r - q * f0.d);
+        r = q;
+        q = fast_quot(f1, r);
+        const int x1 = (int)(r - q * f1.d);
+        r = q;
+        int x2 = 0;
+        if (dim == 3) {
+            q = fast_quot(f2, r);
+            x2 = (int)(r - q * f2.d);
+            r = q;
+        }
+        const unsigned c = r;
+        const int o = dir == 0 ? x0 : (dir == 1 ? x1 : x2);
+        // input offset of the element with its coordinate along dir set to 0
+        const unsigned ib = c * in_comp + ((unsigned)(dir == 2 ? 0 : x2) * (unsigned)i1 + (unsigned)(dir == 1 ? 0 : x1)) *
+                                              (unsigned)i0 + (unsigned)(dir == 0 ? 0 : x0);
+        T acc = T(0);
+        if constexpr (W > 0) {
+            T wt[W], v[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                wt[w] = tw[o * W + w];
+                v[w] = in[ib + (unsigned)tidx[o * W + w] * istr];
+            }
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                if (wt[w] != T(0)) acc += wt[w] * v[w];
+        } else {
+            for (int w = 0; w < width; ++w) {
+                const T wt = tw[o * width + w];
+                if (wt == T(0)) continue;
+                acc += wt * in[ib + (unsigned)tidx[o * width + w] * istr];
+            }
+        }
+        if (accumulate) out[idx] += acc;
+        else out[idx] = acc;
+    }
+}
+
+// The same with 64-bit indices, for passes whose indices do not fit the narrow form.
+template <typename T>
+__global__ void k_transfer_1d(int dim, long long total, int i0, int i1, int o0, int o1, int o2, int dir,
                               const int* __restrict__ tidx, const T* __restrict__ tw, int width,
                               const T* __restrict__ in, T* __restrict__ out, bool accumulate,
-                              I in_comp, I out_comp) {
-    for (I idx = blockIdx.x * (I)blockDim.x + threadIdx.x; idx < total; idx += (I)gridDim.x * blockDim.x) {
-        I r = idx;
-        const int x0 = (int)(r % (I)o0);
-        r /= (I)o0;
-        const int x1 = (int)(r % (I)o1);
-        r /= (I)o1;
+                              long long in_comp) {
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+         idx += (long long)gridDim.x * blockDim.x) {
+        long long r = idx;
+        const int x0 = r % o0;
+        r /= o0;
+        const int x1 = r % o1;
+        r /= o1;
         int x2 = 0;
-        if (dim == 3) { x2 = (int)(r % (I)o2); r /= (I)o2; }
-        const I c = r;
+        if (dim == 3) { x2 = r % o2; r /= o2; }
+        const long long c = r;
         const int o = dir == 0 ? x0 : (dir == 1 ? x1 : x2);
         T acc = T(0);
         for (int w = 0; w < width; ++w) {
@@ -39,7 +111,7 @@ __global__ void k_transfer_1d(int dim, I total, int i0, int i1, int o0, int o1, 
             const int y0 = dir == 0 ? src : x0;
             const int y1 = dir == 1 ? src : x1;
             const int y2 = dir == 2 ? src : x2;
-            acc += wt * in[c * in_comp + ((I)y2 * (I)i1 + (I)y1) * (I)i0 + (I)y0];
+            acc += wt * in[c * in_comp + ((long long)y2 * i1 + y1) * i0 + y0];
         }
         if (accumulate) out[idx] += acc;
         else out[idx] = acc;
@@ -387,14 +459,26 @@ hipError_t launch_transfer_1d(int dim, int ncomp, const int* in_dims, const int*
     const unsigned grid = grid_for(total, 256, 65536);
     // 32-bit indices when the output loop (with one grid stride of headroom) and the input fit in 2^31
     const bool narrow = total + (long long)grid * 256 < (1LL << 31) && in_comp * ncomp < (1LL << 31);
-    if (narrow)
-        hipLaunchKernelGGL((k_transfer_1d<T, unsigned>), dim3(grid), dim3(256), 0, s, dim, (unsigned)total, in_dims[0],
-                           in_dims[1], out_dims[0], out_dims[1], dim == 3 ? out_dims[2] : 1, dir, tidx, tw, width, in,
-                           out, accumulate, (unsigned)in_comp, (unsigned)out_comp);
-    else
-        hipLaunchKernelGGL((k_transfer_1d<T, long long>), dim3(grid), dim3(256), 0, s, dim, total, in_dims[0],
-                           in_dims[1], out_dims[0], out_dims[1], dim == 3 ? out_dims[2] : 1, dir, tidx, tw, width, in,
-                           out, accumulate, in_comp, out_comp);
+    if (narrow) {
+        const FastDiv f0 = make_fastdiv((unsigned)out_dims[0]), f1 = make_fastdiv((unsigned)out_dims[1]),
+                      f2 = make_fastdiv(dim == 3 ? (unsigned)out_dims[2] : 1u);
+#define SG_TR(W_)                                                                                              \
+    hipLaunchKernelGGL((k_transfer_1d_narrow<T, W_>), dim3(grid), dim3(256), 0, s, dim, (unsigned)total, in_dims[0], \
+                       in_dims[1], f0, f1, f2, dir, tidx, tw, width, in, out, accumulate, (unsigned)in_comp)
+        switch (width) {
+            case 2: SG_TR(2); break;
+            case 3: SG_TR(3); break;
+            case 4: SG_TR(4); break;
+            case 5: SG_TR(5); break;
+            case 6: SG_TR(6); break;
+            case 7: SG_TR(7); break;
+            default: SG_TR(0); break;
+        }
+#undef SG_TR
+    } else
+        hipLaunchKernelGGL(k_transfer_1d<T>, dim3(grid), dim3(256), 0, s, dim, total, in_dims[0], in_dims[1],
+                           out_dims[0], out_dims[1], dim == 3 ? out_dims[2] : 1, dir, tidx, tw, width, in, out,
+                           accumulate, in_comp);
     return hipGetLastError();
 }
 
