@@ -280,29 +280,54 @@ __global__ void __launch_bounds__(256)
     if (threadIdx.x == 0) out[cell] = sh[0];
 }
 
+constexpr int kCoarseModes = 2;   // modes per workgroup when every mode uses the same inverse
+constexpr int kCoarseWaves = 8;   // waves per workgroup, each summing one range of l
+
+// x[al][dofs[r]] = sum_l AinvT[l][r] b[al][dofs[l]].  A workgroup takes 64 rows r (one per lane) and
+// mb modes (kCoarseModes, or 1 when every mode has its own inverse), so one load of the inverse
+// serves mb modes; its kCoarseWaves waves take consecutive ranges of l, and the range sums are added
+// in wave order.
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64 * kCoarseWaves)
     k_coarse_solve(const double* __restrict__ AinvT_all, long long inv_stride, int nint, const int* __restrict__ dofs,
-                   long long mode_len, const T* __restrict__ b, T* __restrict__ x) {
+                   int n_xi, int mb, long long mode_len, const T* __restrict__ b, T* __restrict__ x) {
     extern __shared__ unsigned char smem_raw[];
-    double* bl = reinterpret_cast<double*>(smem_raw);   // [nint]
-    const int al = blockIdx.y;
-    const double* AinvT = AinvT_all + al * inv_stride;    // one inverse per mode, or one shared (stride 0)
-    const T* bm = b + al * mode_len;
-    for (int l = threadIdx.x; l < nint; l += blockDim.x) bl[l] = (double)bm[dofs[l]];
-    __syncthreads();
-    const int row = blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= nint) return;
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-    int l = 0;
-    for (; l + 3 < nint; l += 4) {
-        acc0 += AinvT[(long long)l * nint + row] * bl[l];
-        acc1 += AinvT[(long long)(l + 1) * nint + row] * bl[l + 1];
-        acc2 += AinvT[(long long)(l + 2) * nint + row] * bl[l + 2];
-        acc3 += AinvT[(long long)(l + 3) * nint + row] * bl[l + 3];
+    double* bl = reinterpret_cast<double*>(smem_raw);     // [mb][nint]
+    double* part = bl + (size_t)mb * nint;                 // [kCoarseWaves][mb][64]
+    const int m0 = blockIdx.y * mb;
+    const int nm = min(mb, n_xi - m0);
+    for (int i = threadIdx.x; i < mb * nint; i += blockDim.x) {
+        const int m = i / nint, l = i - m * nint;
+        bl[i] = m < nm ? (double)b[(m0 + m) * mode_len + dofs[l]] : 0.0;
     }
-    for (; l < nint; ++l) acc0 += AinvT[(long long)l * nint + row] * bl[l];
-    x[al * mode_len + dofs[row]] = (T)((acc0 + acc1) + (acc2 + acc3));
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int row = blockIdx.x * 64 + lane;
+    const int rc = min(row, nint - 1);
+    const double* A = AinvT_all + (long long)m0 * inv_stride;   // inv_stride 0: one inverse for all modes
+    const int range = (nint + kCoarseWaves - 1) / kCoarseWaves;
+    const int l0 = wv * range, l1 = min(nint, l0 + range);
+    double acc[kCoarseModes];
+#pragma unroll
+    for (int m = 0; m < kCoarseModes; ++m) acc[m] = 0.0;
+#pragma unroll 4
+    for (int l = l0; l < l1; ++l) {
+        const double a = A[(long long)l * nint + rc];
+#pragma unroll
+        for (int m = 0; m < kCoarseModes; ++m)
+            if (m < mb) acc[m] += a * bl[m * nint + l];
+    }
+#pragma unroll
+    for (int m = 0; m < kCoarseModes; ++m)
+        if (m < mb) part[(wv * mb + m) * 64 + lane] = acc[m];
+    __syncthreads();
+    if (wv == 0 && row < nint) {
+        for (int m = 0; m < nm; ++m) {
+            double sum = 0.0;
+            for (int w = 0; w < kCoarseWaves; ++w) sum += part[(w * mb + m) * 64 + lane];
+            x[(m0 + m) * mode_len + dofs[row]] = (T)sum;
+        }
+    }
 }
 
 template <typename T>
@@ -540,12 +565,17 @@ hipError_t launch_coarse_solve(const double* AinvT, long long inv_stride, int ni
                                long long mode_len, const T* b, T* x, hipStream_t s) {
     const long long n = mode_len * n_xi;
     hipLaunchKernelGGL(k_copy<T>, dim3(grid_for(n, 256)), dim3(256), 0, s, b, x, n);
-    const size_t lds = (size_t)nint * sizeof(double);
-    if (lds > 160 * 1024 || n_xi > 65535) return hipErrorInvalidConfiguration;
+    // modes per workgroup: kCoarseModes when they share the inverse and the LDS (160 KB) holds them
+    int mb = inv_stride ? 1 : kCoarseModes;
+    auto lds_of = [&](int m) { return (size_t)m * nint * sizeof(double) + (size_t)kCoarseWaves * m * 64 * sizeof(double); };
+    while (mb > 1 && lds_of(mb) > 160 * 1024) --mb;
+    const size_t lds = lds_of(mb);
+    const int gy = (n_xi + mb - 1) / mb;
+    if (nint < 1 || lds > 160 * 1024 || gy > 65535) return hipErrorInvalidConfiguration;
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute((const void*)k_coarse_solve<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_coarse_solve<T>, dim3((nint + 255) / 256, n_xi), dim3(256), lds, s, AinvT, inv_stride, nint,
-                       dofs, mode_len, b, x);
+    hipLaunchKernelGGL(k_coarse_solve<T>, dim3((nint + 63) / 64, gy), dim3(64 * kCoarseWaves), lds, s, AinvT, inv_stride,
+                       nint, dofs, n_xi, mb, mode_len, b, x);
     return hipGetLastError();
 }
 
