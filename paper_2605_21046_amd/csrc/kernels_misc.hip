@@ -497,6 +497,8 @@ hipError_t launch_transfer_1d(int dim, int ncomp, const int* in_dims, const int*
             case 5: SG_TR(5); break;
             case 6: SG_TR(6); break;
             case 7: SG_TR(7); break;
+            case 11: SG_TR(11); break;    // restriction of Q3 (fine nodes per coarse vertex)
+            case 13: SG_TR(13); break;    // restriction of Q4
             default: SG_TR(0); break;
         }
 #undef SG_TR
