@@ -79,6 +79,7 @@ WORKLOADS = {
     "t3q2": Workload("t3q2", 3, 4, 2, 1, 0.05, 3, 2, 2, "sine"),
     "t3q3": Workload("t3q3", 3, 2, 3, 2, 0.05, 2, 2, 1, "sine"),
     "t3q4": Workload("t3q4", 3, 2, 4, 1, 0.05, 2, 1, 1, "sine"),
+    "t2q4": Workload("t2q4", 2, 4, 4, 1, 0.02, 2, 2, 2, "sine"),
     # many chaos modes (70) on a small mesh: strips of modes in the Vanka kernel
     "t2q2p4": Workload("t2q2p4", 2, 4, 2, 1, 0.02, 4, 4, 2, "sine"),
 }

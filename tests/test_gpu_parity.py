@@ -22,7 +22,7 @@ from oracle.slab import from_workload
 
 pytestmark = pytest.mark.gpu
 
-SMALL = ["c1", "t2q1", "t2q2", "t2q3", "t3q1", "t3q2", "t3q3", "t3q4", "t2q2p4"]
+SMALL = ["c1", "t2q1", "t2q2", "t2q3", "t2q4", "t3q1", "t3q2", "t3q3", "t3q4", "t2q2p4"]
 
 
 @pytest.fixture(scope="module")
@@ -98,7 +98,7 @@ def test_apply_full_size_sampled_rows(torch_cuda, name):
     assert np.abs(got - ref).max() <= 1e-12 * scale
 
 
-@pytest.mark.parametrize("name", ["c1", "t2q1", "t2q3", "t3q2", "t3q3", "t2q2p4"])
+@pytest.mark.parametrize("name", ["c1", "t2q1", "t2q3", "t2q4", "t3q2", "t3q3", "t2q2p4"])
 def test_vanka_matches_oracle(torch_cuda, name):
     torch = torch_cuda
     w = sg_inputs.WORKLOADS[name]
@@ -115,7 +115,7 @@ def test_vanka_matches_oracle(torch_cuda, name):
         assert _rel_inf(xg.cpu().numpy(), ref) <= 1e-11, level
 
 
-@pytest.mark.parametrize("name", ["c1", "t2q2", "t2q3", "t3q1", "t3q2", "t2q2p4"])
+@pytest.mark.parametrize("name", ["c1", "t2q2", "t2q3", "t2q4", "t3q1", "t3q2", "t2q2p4"])
 def test_vcycle_matches_oracle(torch_cuda, name):
     torch = torch_cuda
     w = sg_inputs.WORKLOADS[name]
