@@ -8,30 +8,12 @@
 // them in a fixed order.
 #include <algorithm>
 
+#include "fastdiv.hpp"
 #include "kernels.hpp"
 
 namespace sg {
 
 namespace {
-
-// Quotient by an invariant divisor d (1 <= d < 2^32) with one high multiply, after Granlund and
-// Montgomery, "Division by invariant integers using multiplication" (PLDI 1994): with
-// l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1, floor(n / d) equals
-// (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0), t = floor(m n / 2^32), for every 32-bit n.
-struct FastDiv {
-    unsigned d, m;
-    int s1, s2;
-};
-FastDiv make_fastdiv(unsigned d) {
-    int l = 0;
-    while ((1ull << l) < d) ++l;
-    const unsigned long long m = ((1ull << 32) * ((1ull << l) - d)) / d + 1;
-    return {d, (unsigned)m, l < 1 ? l : 1, l > 1 ? l - 1 : 0};
-}
-__device__ __forceinline__ unsigned fast_quot(const FastDiv& f, unsigned n) {
-    const unsigned t = __umulhi(f.m, n);
-    return (t + ((n - t) >> f.s1)) >> f.s2;
-}
 
 // One 1D transfer pass, one output element per thread.  Narrow form: every index of the pass fits
 // in 31 bits (the launcher checks) and the divisions by the output extents use FastDiv.  W > 0: the
