@@ -52,7 +52,7 @@ def apply_source_hash() -> str:
 
 
 def apply_model(w):
-    """Algorithmic bytes and flops of one operator apply (definitions in the design doc).
+    """Algorithmic bytes and flops of one operator apply.
 
     bytes: read x, write y (8 B per DoF each) and read the coefficient at the quadrature points.
     flops: sum-factorised evaluation as implemented (FMA = 2 flops): per cell and component
@@ -343,8 +343,8 @@ def main():
                     help="only run a plain 512 MiB device copy 5 times (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(it has no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -44,7 +44,7 @@ typedef enum {
     SG_ENOMEM = -2,         /* device or host allocation failed */
     SG_EHIP = -3,           /* a HIP runtime call failed; the message names it */
     SG_ESINGULAR = -4,      /* a Vanka patch matrix or the coarsest-level matrix is singular */
-    SG_EUNSUPPORTED = -5    /* valid request this build does not implement (e.g. too many components per cell) */
+    SG_EUNSUPPORTED = -5    /* valid request the library does not implement (e.g. too many components per cell) */
 } sg_status;
 
 typedef enum {
