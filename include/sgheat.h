@@ -49,7 +49,7 @@ typedef enum {
 
 typedef enum {
     SG_FP64 = 0,            /* every step in FP64 */
-    SG_MIXED = 1            /* V-cycle and Vanka in FP32 on fine levels, FP64 coarsest LU, FP64 outer FGMRES */
+    SG_MIXED = 1            /* V-cycle and Vanka in FP32 on fine levels, FP64 coarsest-level inverse, FP64 outer FGMRES */
 } sg_precision;
 
 /* Problem description (all arrays are HOST memory, copied by sg_create). */
@@ -112,10 +112,15 @@ typedef struct {
     double work_proxy;      /* N_SG,slab * preconditioner calls (eq. work-proxy)                     */
 } sg_solve_info;
 
-/* Build the handle: copies the description, builds the chaos coupling lists, time matrices, 1D
- * tables and level data, uploads coefficients, forms and inverts every Vanka patch matrix on the
- * device (LU with partial pivoting) and the coarsest-level matrix on the host.  Synchronous.
- * Returns SG_EINVAL for inconsistent descriptions, SG_ESINGULAR for a singular patch. */
+/* Build the handle for one slab problem (Problem tensor-product-slab-system: the description fixes
+ * the spatial mesh and Q_k space, the dG(r) slab of length tau, the chaos index set and the active
+ * coefficient modes of eq. local_rhs_tensor; the multigrid fields configure the block-Jacobi
+ * preconditioner of Remark solver-matrix-free-sg).  Copies the description, builds the chaos
+ * coupling lists, time matrices, 1D tables and level data, uploads the coefficients, forms every
+ * Vanka patch matrix and inverts it on the device (Gauss-Jordan elimination with partial pivoting in
+ * FP64), and inverts the coarsest-level matrix on the device the same way.  Synchronous.
+ * Returns SG_EINVAL for inconsistent descriptions (a multi-index listed twice in coef_mu included),
+ * SG_ESINGULAR for a singular patch or coarsest-level matrix. */
 sg_status sg_create(const sg_problem_desc* desc, sg_handle* out);
 
 /* Release every device and host resource of the handle.  NULL is accepted. */
@@ -136,16 +141,18 @@ sg_status sg_operator_apply(sg_handle h, const double* x, double* y, void* hip_s
  * the levels above the coarsest.  x is updated in place.  Asynchronous on the stream. */
 sg_status sg_vanka_smooth(sg_handle h, int level, const double* b, double* x, int sweeps, void* hip_stream);
 
-/* z = one V-cycle for (I_xi (x) A_0) z = r: the stochastic block-Jacobi preconditioner with the
- * mean-based diagonal block (every diagonal block equals A_0 for an affine coefficient; for a
+/* z = one V-cycle for (I_xi (x) A_0) z = r (Remark solver-matrix-free-sg: one geometric-multigrid
+ * cycle with the space-time Vanka smoother per stochastic diagonal block, applied matrix-free): the
+ * stochastic block-Jacobi preconditioner with the mean-based diagonal block (every diagonal block equals A_0 for an affine coefficient; for a
  * non-affine coefficient set, such as the finite-chaos benchmark's, the diagonal blocks differ and A_0
  * stands in for all of them, so FGMRES needs more iterations but converges to the same solution).
  * With desc.diag_blocks = 1 each mode alpha is cycled with its own block A_alpha instead.
  * FP64 interface; FP32 inside with SG_MIXED.  Asynchronous on the stream. */
 sg_status gmg_vcycle(sg_handle h, const double* r, double* z, void* hip_stream);
 
-/* Solve AA x = b by right-preconditioned flexible GMRES (restart fgmres_restart, CGS2,
- * preconditioner gmg_vcycle) starting from the x passed in, until ||b - AA x||_2 / ||b||_2 <= rtol
+/* Solve the slab system AA x = b (Problem tensor-product-slab-system) by right-preconditioned
+ * flexible GMRES with the block-Jacobi multigrid preconditioner of Remark solver-matrix-free-sg
+ * (restart fgmres_restart, CGS2, preconditioner gmg_vcycle) starting from the x passed in, until ||b - AA x||_2 / ||b||_2 <= rtol
  * (true residual) or max_iter iterations.  Synchronises the stream (Krylov scalars go to the host).
  * `info` may be NULL.  Returns SG_NOT_CONVERGED if the tolerance was not reached. */
 sg_status fgmres_solve_slab(sg_handle h, const double* b, double* x, double rtol, int max_iter,

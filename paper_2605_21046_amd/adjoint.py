@@ -23,6 +23,14 @@ import numpy as np
 from . import sgheat
 
 
+class Checkpoint:
+    """State of one forward sweep: its parameters, slab-end traces, final slab vector and dJ/dU."""
+
+    def __init__(self, theta, a0, traces, u_last, grad_u):
+        self.theta, self.a0 = theta, a0
+        self.traces, self.u_last, self.grad_u = traces, u_last, grad_u
+
+
 class SlabSequence:
     """Forward and adjoint sweeps of one sg_inputs.AdjointWorkload on the GPU."""
 
@@ -47,6 +55,7 @@ class SlabSequence:
         self.ones_qp = np.ones(self.qp[0].shape[:2])
         self.G = self.GT = None
         self.stats = {}
+        self.checkpoint = None
 
     def _boundary_mask(self) -> np.ndarray:
         n1 = self.w.n_cells_1d * self.w.fe_degree + 1
@@ -72,7 +81,8 @@ class SlabSequence:
         else:
             self.G.update_coefficients(coef)
             self.GT.update_coefficients(coef)
-        self.theta = np.asarray(theta, dtype=np.float64)
+        self.theta = np.asarray(theta, dtype=np.float64).copy()
+        self.a0 = np.asarray(a0_cells, dtype=np.float64).copy()
 
     def close(self):
         for P in (self.G, self.GT):
@@ -118,10 +128,20 @@ class SlabSequence:
         self.grad_u = self._zeros()
         EQ, VQ = self.G.qoi_mean_var(u, 1.0, 1.0, grad=self.grad_u)
         self.J = EQ + VQ
+        # everything backward() needs, kept apart from the next forward sweep's state
+        self.checkpoint = Checkpoint(self.theta, self.a0, self.traces, self.u_last, self.grad_u)
         return self.J, EQ, VQ
 
-    def backward(self):
-        """Adjoint sweep after forward(); returns (dJ/dtheta [M], dJ/da0 [n_cells])."""
+    def backward(self, checkpoint=None):
+        """Adjoint sweep; returns (dJ/dtheta [M], dJ/da0 [n_cells]) at the parameters of `checkpoint`
+        (a forward() result; default: the latest one).  If another forward sweep ran since, the
+        coefficients of that checkpoint are set again before the sweep."""
+        ck = self.checkpoint if checkpoint is None else checkpoint
+        if ck is None:
+            raise RuntimeError("backward() needs a forward() sweep first")
+        if not (np.array_equal(ck.theta, self.theta) and np.array_equal(ck.a0, self.a0)):
+            self.set_parameters(ck.theta, ck.a0)
+        self.traces, self.u_last, self.grad_u = ck.traces, ck.u_last, ck.grad_u
         M = self.w.n_vars
         dth = np.zeros(M)
         n_cells = self.qp[0].shape[0]
@@ -169,12 +189,13 @@ def make_function():
         def forward(ctx, theta, a0, seq):
             J, _, _ = seq.forward(theta.detach().cpu().numpy(), a0.detach().cpu().numpy())
             ctx.seq = seq
+            ctx.checkpoint = seq.checkpoint      # backward uses this sweep's state, not the latest one
             ctx.dtypes = (theta.dtype, theta.device, a0.dtype, a0.device)
             return torch.tensor(J, dtype=torch.float64)
 
         @staticmethod
         def backward(ctx, gJ):
-            dth, da0 = ctx.seq.backward()
+            dth, da0 = ctx.seq.backward(ctx.checkpoint)
             tdt, tdev, adt, adev = ctx.dtypes
             g = float(gJ)
             return (torch.as_tensor(g * dth, dtype=tdt, device=tdev), torch.as_tensor(g * da0, dtype=adt, device=adev),

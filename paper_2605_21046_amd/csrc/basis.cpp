@@ -190,11 +190,15 @@ bool check_modes(int M, int n_mu, const int* mu, Coupling* out, std::string* err
             if (mu[k * M + m] < 0) { *err = "negative entry in coef_mu"; return false; }
             deg += mu[k * M + m];
         }
-        if (deg == 0) {
-            if (out->mu0 >= 0) { *err = "coef_mu lists mu = 0 twice"; return false; }
-            out->mu0 = k;
-        }
+        if (deg == 0 && out->mu0 < 0) out->mu0 = k;
         if (deg > 1) out->affine = false;
+        // a repeated multi-index would be summed by the coupling lists but not by the register-resident
+        // affine path, which keeps one coefficient row per e_m: reject it
+        for (int j = 0; j < k; ++j) {
+            bool same = true;
+            for (int m = 0; m < M && same; ++m) same = mu[j * M + m] == mu[k * M + m];
+            if (same) { *err = deg == 0 ? "coef_mu lists mu = 0 twice" : "coef_mu lists a multi-index twice"; return false; }
+        }
     }
     if (out->mu0 < 0) { *err = "coef_mu must contain mu = 0"; return false; }
     return true;

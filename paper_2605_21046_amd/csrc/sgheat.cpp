@@ -346,7 +346,8 @@ sg_status set_coefficients(sg_handle h, const double* coef_qp) {
         if (st) return fail(SG_ESINGULAR, "a Vanka patch matrix is singular");
     }
 
-    // coarsest level: dense A_0 on interior DoFs, inverted on the host
+    // coarsest level: dense A_0 on interior DoFs, assembled on the host and inverted on the device
+    // (Gauss-Jordan elimination with partial pivoting, FP64)
     {
         const Level& lc = h->lv[L - 1];
         const int n = lc.g.n, n1 = lc.g.n1;

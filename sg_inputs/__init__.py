@@ -82,6 +82,10 @@ WORKLOADS = {
     "t2q4": Workload("t2q4", 2, 4, 4, 1, 0.02, 2, 2, 2, "sine"),
     # many chaos modes (70) on a small mesh: strips of modes in the Vanka kernel
     "t2q2p4": Workload("t2q2p4", 2, 4, 2, 1, 0.02, 4, 4, 2, "sine"),
+    # the discretisations of the two 3D benchmark workloads (same k, r, M, p_xi, field and tau = h) on
+    # small meshes whose cell counts per direction are not multiples of the apply's tile widths
+    "t3c2": Workload("t3c2", 3, 10, 2, 1, 1.0 / 10, 4, 3, 2, "sine"),
+    "t3c3": Workload("t3c3", 3, 5, 3, 2, 1.0 / 5, 3, 4, 1, "sine"),
 }
 
 

@@ -160,6 +160,30 @@ def test_autograd_function_returns_the_adjoint_gradient(torch_cuda):
     assert np.max(np.abs(a0.grad.numpy() - da0)) <= 1e-7 * np.max(np.abs(da0))
 
 
+def test_autograd_backward_after_a_second_forward(torch_cuda):
+    """Two evaluations of J before backward: each backward returns the gradient at its own
+    parameters (the second forward moved the handles' coefficients and checkpoints)."""
+    from paper_2605_21046_amd.adjoint import SlabSequence, make_function
+    torch = torch_cuda
+    aw = sg_inputs.ADJOINT_WORKLOADS["a2"]
+    seq = SlabSequence(aw, rtol=1e-12)
+    f = make_function()
+    th1 = torch.tensor(aw.theta0(), dtype=torch.float64, requires_grad=True)
+    a01 = torch.tensor(aw.a0_cells0(), dtype=torch.float64, requires_grad=True)
+    th2 = torch.tensor(1.7 * aw.theta0(), dtype=torch.float64, requires_grad=True)
+    a02 = torch.tensor(aw.a0_cells0() + 0.1, dtype=torch.float64, requires_grad=True)
+    J1 = f.apply(th1, a01, seq)
+    J2 = f.apply(th2, a02, seq)
+    J1.backward()
+    J2.backward()
+    seq.close()
+    for th, a0, J in ((th1, a01, J1), (th2, a02, J2)):
+        Jo, _, dth, da0 = adj.gradient(aw, th.detach().numpy(), a0.detach().numpy())
+        assert float(J) == pytest.approx(Jo, rel=1e-9)
+        assert np.max(np.abs(th.grad.numpy() - dth)) <= 1e-7 * np.max(np.abs(dth))
+        assert np.max(np.abs(a0.grad.numpy() - da0)) <= 1e-7 * np.max(np.abs(da0))
+
+
 def test_full_size_gradient_against_central_differences(torch_cuda):
     """16^3 cells, 10 slabs, 20 modes: the adjoint gradient against central differences of J."""
     from paper_2605_21046_amd.adjoint import SlabSequence

@@ -22,7 +22,7 @@ from oracle.slab import from_workload
 
 pytestmark = pytest.mark.gpu
 
-SMALL = ["c1", "t2q1", "t2q2", "t2q3", "t2q4", "t3q1", "t3q2", "t3q3", "t3q4", "t2q2p4"]
+SMALL = ["c1", "t2q1", "t2q2", "t2q3", "t2q4", "t3q1", "t3q2", "t3q3", "t3q4", "t2q2p4", "t3c2", "t3c3"]
 
 
 @pytest.fixture(scope="module")
@@ -98,7 +98,7 @@ def test_apply_full_size_sampled_rows(torch_cuda, name):
     assert np.abs(got - ref).max() <= 1e-12 * scale
 
 
-@pytest.mark.parametrize("name", ["c1", "t2q1", "t2q3", "t2q4", "t3q2", "t3q3", "t2q2p4"])
+@pytest.mark.parametrize("name", ["c1", "t2q1", "t2q3", "t2q4", "t3q2", "t3q3", "t2q2p4", "t3c2"])
 def test_vanka_matches_oracle(torch_cuda, name):
     torch = torch_cuda
     w = sg_inputs.WORKLOADS[name]
@@ -115,7 +115,7 @@ def test_vanka_matches_oracle(torch_cuda, name):
         assert _rel_inf(xg.cpu().numpy(), ref) <= 1e-11, level
 
 
-@pytest.mark.parametrize("name", ["c1", "t2q2", "t2q3", "t2q4", "t3q1", "t3q2", "t2q2p4"])
+@pytest.mark.parametrize("name", ["c1", "t2q2", "t2q3", "t2q4", "t3q1", "t3q2", "t2q2p4", "t3c2"])
 def test_vcycle_matches_oracle(torch_cuda, name):
     torch = torch_cuda
     w = sg_inputs.WORKLOADS[name]
@@ -152,24 +152,37 @@ def test_fgmres_solves_to_tolerance(torch_cuda, name):
     print(name, info)
 
 
+@pytest.mark.timeout(400)
 @pytest.mark.parametrize("name", ["c2", "c3"])
 def test_full_size_solves(torch_cuda, name):
     """The benchmark workloads at full size (c2: 19.2M DoFs, c3: 40.8M), properties that hold at any
     size: b = AA x* with x* random on the interior; the FP64 and the mixed-precision FGMRES-GMG solves
-    reach a true relative residual <= 1e-8 (checked with a fresh apply), recover x* to the conditioning
-    of the slab operator, and take no more than 12 iterations (9 on c2 and 10 on c3 with the current
-    kernels; the bound leaves room for rounding-order changes, not for a weaker preconditioner)."""
+    reach a true relative residual <= 1e-8, recover x* to the conditioning of the slab operator, and
+    take no more than 12 iterations (9 on c2 and 10 on c3 with the current kernels; the bound leaves
+    room for rounding-order changes, not for a weaker preconditioner).
+
+    On c2 the oracle forms b = AA x* and recomputes both true residuals with its own operator
+    (route 2, sparse matrices times the mode/time block), so a wrong GPU operator cannot pass; on c3
+    (where the oracle's assembly alone takes over a minute) b and the residual come from the GPU
+    apply, which the sampled-row and small-mesh parity tests check against the oracle."""
     torch = torch_cuda
     w = sg_inputs.WORKLOADS[name]
     print(f"full-size {name} solves", flush=True)
-    xs = _to_gpu(torch, sg_inputs.interior_target(w))
+    xs_np = sg_inputs.interior_target(w)
+    xs = _to_gpu(torch, xs_np)
+    P = from_workload(w) if name == "c2" else None
+    b_np = P.apply_route2(xs_np) if P is not None else None
     out = {}
     for precision in (0, 1):
         G = _gpu(w, precision)
-        b = G.apply(xs)
+        b = _to_gpu(torch, b_np) if P is not None else G.apply(xs)
         x, info = G.solve(b, rtol=1e-8, max_iter=60)
-        r = b - G.apply(x)
-        rel = (torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b)).item()
+        if P is not None:
+            xn = x.cpu().numpy()
+            rel = np.linalg.norm(b_np - P.apply_route2(xn)) / np.linalg.norm(b_np)
+        else:
+            r = b - G.apply(x)
+            rel = (torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b)).item()
         err = (torch.linalg.vector_norm(x - xs) / torch.linalg.vector_norm(xs)).item()
         G.close()
         print(f"precision {precision}: {info['iterations']} iterations, residual {rel:.3e}, error {err:.3e}",

@@ -139,3 +139,17 @@ def test_gauss_points_of_any_order_match_the_rule(nq1):
             qx, qy = q % nq1, q // nq1
             assert abs(pts[c, q, 0] - (w.lo + h * (cx + g[qx]))) < 1e-15
             assert abs(pts[c, q, 1] - (w.lo + h * (cy + g[qy]))) < 1e-15
+
+
+@pytest.mark.parametrize("mus", [(0, 0, 1, 0, 1, 0), (0, 0, 0, 0, 0, 1), (0, 0, 1, 0, 0, 1, 1, 0)])
+def test_create_rejects_repeated_coefficient_modes(mus):
+    """A multi-index listed twice in coef_mu (mu = 0 or e_m) is rejected before any device work: the
+    coupling lists would sum the two rows, the register-resident affine path would keep only one."""
+    sgheat = _lib()
+    d, keep = _desc()
+    arr = (ctypes.c_int * len(mus))(*mus)
+    d.n_coef_modes = len(mus) // 2
+    d.coef_mu = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int))
+    h = ctypes.c_void_p()
+    assert sgheat._lib.sg_create(ctypes.byref(d), ctypes.byref(h)) == -1 and not h.value
+    assert b"twice" in sgheat._lib.sg_last_error()
