@@ -5,11 +5,17 @@ One JSON line on stdout:
   * value = SG operator apply throughput in GDoF/s (N_DoF / median apply time) on the 3D workload
     "Q2 on 32^3 cells, dG(1), M = 4, p_xi = 3" (19,223,750 DoFs), timed over rotating input/output
     pairs so the 256 MB Infinity Cache cannot hold them;
-  * roofline = the apply against the FP64 peak (its arithmetic intensity is above the ridge), with
-    roofline_hbm against 8 TB/s and the HBM traffic measured by rocprofv3 counters;
+  * roofline = the apply against the 8 TB/s HBM peak: algorithmic bytes (read x, write y, read the
+    coefficient at the quadrature points) over the apply time, with the HBM bytes rocprofv3's
+    FETCH_SIZE / WRITE_SIZE counters measured for the same kernels (`traffic`);
+    roofline_fp64 = the same apply against the FP64 peak with the flop count of the sum-factorised
+    method (even-odd 1D contractions), not the count of the code as written;
   * solve = FGMRES-GMG slab solve time to a true relative residual of 1e-8, FP64 and mixed; a step is
     one FP64 slab solve (FGMRES + V-cycles + Vanka + applies: the whole path);
-  * cpu_baseline = the FP64 CPU oracle's apply on a reduced mesh of the same discretisation.
+  * c3 = the same apply and solve figures for "Q3 on 24^3 cells, dG(2), M = 3, p_xi = 4"
+    (40,846,785 DoFs), where the mixed-precision solve is to beat the FP64 one;
+  * cpu_baseline = the FP64 CPU oracle's apply on the full 3D Q2 workload, one thread and all of
+    this process's cores.
 All inputs are synthetic and seeded.
 """
 from __future__ import annotations
@@ -54,27 +60,32 @@ def apply_source_hash() -> str:
 def apply_model(w):
     """Algorithmic bytes and flops of one operator apply.
 
-    bytes: read x, write y (8 B per DoF each) and read the coefficient at the quadrature points.
-    flops: sum-factorised evaluation as implemented (FMA = 2 flops): per cell and component
-           4 d (k+1)^(d+1) FMAs for interpolation, derivatives and their transposes, N_t + 1 per
-           point for the mass term, and 3 flops per coupling entry per point and direction.
+    bytes: what the method must move: read x, write y (8 B per DoF each) and read the coefficient at
+           the quadrature points (the geometry of a uniform Cartesian mesh is implicit).
+    flops: the sum-factorised method with even-odd decomposition of the 1D contractions (FMA = 2 flops):
+           per cell and component 4 d (k+1)^(d+1) for interpolating values and gradients to the
+           quadrature points and integrating back, and per cell and point the quadrature-point work
+           2 d N_t (N_xi + nnz_G) (chaos coupling of the gradient: G_0 = I plus the off-diagonal
+           entries of the G_{e_m}) + 2 N_t^2 N_xi (time coupling of the mass term) + 2 d N_t N_xi
+           (coefficient scaling).  flops_plain is the same without the even-odd halving.
     """
     d, k, nt = w.dim, w.fe_degree, w.n_time
     n1 = k + 1
     npnt = n1 ** d
     cells = w.n_cells_1d ** d
     nxi = w.n_chaos
-    # affine coefficient: G_0 = I (N_xi entries); G_{e_m} pairs alpha with alpha + e_m, which exists for
-    # every alpha of total degree <= p_xi - 1, in both orders
+    # affine coefficient: G_{e_m} pairs alpha with alpha + e_m, which exists for every alpha of total
+    # degree <= p_xi - 1, in both orders
     M, p = w.n_vars, w.chaos_degree
-    nnz = nxi + (2 * M * math.comb(M + p - 1, p - 1) if p >= 1 else 0)
+    nnz_off = 2 * M * math.comb(M + p - 1, p - 1) if p >= 1 else 0
     n_mu = M + 1
     n_dof = w.n_dofs(0)
     bytes_ = 8 * 2 * n_dof + 8 * n_mu * cells * npnt
-    per_cell_comp = 2 * 4 * d * n1 ** (d + 1) + npnt * (2 * nt + 1)
-    coupling = 3 * d * npnt * nnz * nt          # summed over all components of a cell
-    flops = cells * (nxi * nt * per_cell_comp + coupling)
-    return n_dof, bytes_, flops
+    sweeps = 4 * d * n1 ** (d + 1)
+    point = npnt * (2 * d * nt * (nxi + nnz_off) + 2 * nt * nt * nxi + 2 * d * nt * nxi)
+    flops = cells * (nxi * nt * sweeps + point)
+    flops_plain = cells * (nxi * nt * 2 * sweeps + point)
+    return n_dof, bytes_, flops, flops_plain
 
 
 def _cpu_model() -> str:
@@ -88,32 +99,98 @@ def _cpu_model() -> str:
     return "unknown"
 
 
-def _time_oracle_apply(P, x, seconds_target, max_reps=50):
+def _host_threads() -> int:
+    """Cores this process may use (the GPU machine gives one GPU's share of 16)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def _time_oracle_apply(P, x, seconds_target, max_reps=50, min_reps=1):
     P.apply_route2(x)
     t0 = time.perf_counter()
     reps = 0
     while True:
         P.apply_route2(x)
         reps += 1
-        if time.perf_counter() - t0 > seconds_target or reps >= max_reps:
+        if reps >= max_reps or (reps >= min_reps and time.perf_counter() - t0 > seconds_target):
             break
     return (time.perf_counter() - t0) / reps, reps
 
 
-def cpu_baseline(w, seconds_target=15.0):
-    """The oracle's route-2 apply (scipy sparse x dense blocks), single thread, on a reduced mesh of
-    the same discretisation; assembly is not timed (as on the GPU).  Also times the oracle on the
-    small 2D workload c1 at full size: its apply and a direct sparse solve of the slab system."""
+def _oracle_apply_threaded(P, x, nthreads):
+    """The oracle's route-2 apply split over row blocks of the node dimension, one block per thread:
+    Y[rows] = (M_x[rows] X)(I (x) A_t)^T + sum_mu (K_mu[rows] X)(G_mu (x) B_t)^T.  Each row is computed
+    by the same sequence of operations as in the single-threaded route 2, so the result is the same;
+    returns a closure that performs one apply (the row slices are cut once, outside the timing)."""
+    from concurrent.futures import ThreadPoolExecutor
+    bm = P.full_boundary_mask()
+    edges = np.linspace(0, P.n_x, nthreads + 1).astype(int)
+    blocks = [(r0, r1, P.Mx[r0:r1], [K[r0:r1] for K in P.K]) for r0, r1 in zip(edges[:-1], edges[1:])]
+    TA = np.kron(np.eye(P.n_xi), P.At)
+    TG = [np.kron(G, P.Bt) for G in P.G]
+    Y = np.empty((P.n_x, P.n_xi * P.n_t))
+    pool = ThreadPoolExecutor(nthreads)
+
+    def one():
+        xin = np.where(bm, 0.0, x)
+        X = xin.reshape(P.n_xi * P.n_t, P.n_x).T
+
+        def work(blk):
+            r0, r1, M, Ks = blk
+            acc = (M @ X) @ TA.T
+            for K, T in zip(Ks, TG):
+                acc = acc + (K @ X) @ T.T
+            Y[r0:r1] = acc
+
+        list(pool.map(work, blocks))
+        y = Y.T.reshape(-1).copy()
+        y[bm] = x[bm]
+        return y
+
+    return one, pool
+
+
+def cpu_baseline(w, seconds_target=6.0, extra=()):
+    """The oracle's route-2 apply (scipy sparse x dense blocks) at full size on the GPU host's cores:
+    one thread, and all the cores this process may use (row blocks of the node dimension in a thread
+    pool); assembly is not timed (as on the GPU).  Also the oracle on the small 2D workload c1: its
+    apply and a direct sparse solve of the slab system.  `extra`: more workloads timed the same way."""
     from threadpoolctl import threadpool_limits
     import scipy.sparse.linalg as spla
     import sg_inputs
     from oracle.slab import from_workload
-    n_small = 12 if w.dim == 3 else 64
-    ws = w.with_(n_cells_1d=n_small, n_levels=1)
+    nthr = _host_threads()
+    out = {"unit": "GDoF/s", "kind": "oracle", "host_threads": nthr, "cpu_model": _cpu_model(),
+           "os_cpu_count": os.cpu_count()}
+    for k, wk in enumerate((w,) + tuple(extra)):
+        with threadpool_limits(limits=1):
+            P = from_workload(wk)
+            x = sg_inputs.uniform_vector(P.n, sg_inputs.SEED_APPLY_INPUT)
+            dt1, reps1 = _time_oracle_apply(P, x, seconds_target, max_reps=5)
+            one, pool = _oracle_apply_threaded(P, x, nthr)
+            one()
+            t0 = time.perf_counter()
+            repsn = 0
+            while repsn < 3 or (time.perf_counter() - t0 < seconds_target and repsn < 20):
+                one()
+                repsn += 1
+            dtn = (time.perf_counter() - t0) / repsn
+            pool.shutdown()
+        entry = {"workload": wk.name, "n_dofs": P.n, "gdofs_1thread": round(P.n / dt1 / 1e9, 5), "reps_1thread": reps1,
+                 "gdofs_all_threads": round(P.n / dtn / 1e9, 5), "reps_all_threads": repsn}
+        if k == 0:
+            out.update({"value": entry["gdofs_all_threads"], "cores": nthr,
+                        "sample": f"route-2 Kronecker apply (scipy CSR x dense) of the full {wk.name} workload "
+                                  f"({P.n} DoFs), {repsn} applies on {nthr} threads (row blocks) and {reps1} on one, "
+                                  f"assembly excluded"})
+            out[wk.name] = entry
+        else:
+            out[wk.name] = entry
+        del P, x
     with threadpool_limits(limits=1):
-        P = from_workload(ws)
-        x = sg_inputs.uniform_vector(P.n, sg_inputs.SEED_APPLY_INPUT)
-        dt, reps = _time_oracle_apply(P, x, seconds_target)
         c1 = sg_inputs.WORKLOADS["c1"]
         P1 = from_workload(c1)
         x1 = sg_inputs.uniform_vector(P1.n, sg_inputs.SEED_APPLY_INPUT)
@@ -123,11 +200,9 @@ def cpu_baseline(w, seconds_target=15.0):
         t0 = time.perf_counter()
         spla.spsolve(A1, b1)
         t_sp = time.perf_counter() - t0
-    return {"value": P.n / dt / 1e9, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
-            "sample": f"route-2 Kronecker apply (scipy CSR x dense), same k/r/M/p_xi on {n_small}^{w.dim} cells "
-                      f"({P.n} DoFs), {reps} applies, assembly excluded, 1 thread of {os.cpu_count()} "
-                      f"({_cpu_model()})",
-            "c1_apply_gdofs": round(P1.n / dt1 / 1e9, 5), "c1_spsolve_s": round(t_sp, 4)}
+    out["c1_apply_gdofs_1thread"] = round(P1.n / dt1 / 1e9, 5)
+    out["c1_spsolve_s"] = round(t_sp, 4)
+    return out
 
 
 def adjoint_timing(torch, name="c5", reps=2):
@@ -318,6 +393,116 @@ def copy_bandwidth(torch, dev, reps=20):
     return 2 * 8 * n / t / 1e9
 
 
+def run_workload(torch, dev, stream, sgheat, sg_inputs, w, args, src_hash):
+    """One workload: set-up, apply tiles, the operator apply over rotating (x, y) pairs (median of
+    HIP-event-timed applies on the library's stream) with its HBM and FP64 rooflines, then the FP64 and
+    mixed-precision slab solves to a true relative residual of 1e-8."""
+    name = w.name
+    t_setup = time.perf_counter()
+    G = sgheat.problem_from_workload(w, sgheat.SG_FP64)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_setup
+    tiles = G.autotune(reps=10) if not args.no_autotune else None
+    cpb = tiles["fp64_full"] if tiles else int(os.environ.get("SGHEAT_APPLY_CPB", "0")) or None
+    n = G.n(0)
+    print(f"[bench] {name}: {n} DoFs, setup {setup_s:.2f} s", file=sys.stderr, flush=True)
+
+    n_dof, abytes, aflops, aflops_plain = apply_model(w)
+    pairs = max(1, math.ceil(1.2e9 / (16 * n)))
+    xs = [torch.from_numpy(sg_inputs.uniform_vector(n, sg_inputs.SEED_APPLY_INPUT + 100 * i)).to(dev)
+          for i in range(pairs)]
+    ys = [torch.empty_like(xs[0]) for _ in range(pairs)]
+    for i in range(5):
+        G.apply(xs[i % pairs], ys[i % pairs])
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.apply_reps + 1)]
+    evs[0].record(stream)
+    for i in range(args.apply_reps):
+        G.apply(xs[i % pairs], ys[i % pairs])
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per_apply = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.apply_reps)]) / 1e3
+    t_apply = float(np.median(per_apply))
+    gdofs = n_dof / t_apply / 1e9
+    achieved_gbs = abytes / t_apply / 1e9
+    achieved_tf = aflops / t_apply / 1e12
+    print(f"[bench] {name} apply {t_apply * 1e6:.1f} us  {gdofs:.1f} GDoF/s  {achieved_gbs:.0f} GB/s  "
+          f"{achieved_tf:.1f} TFLOP/s (method flops)", file=sys.stderr, flush=True)
+    del xs, ys
+    meas = MEASURED_TRAFFIC.get((name, src_hash, cpb))
+    traffic = meas["fetch_bytes"] + meas["write_bytes"] if meas else None
+    leg = {"config": {"workload": f"{name}: {w.dim}D Q{w.fe_degree} on {w.n_cells_1d}^{w.dim} cells, dG({w.time_degree}), "
+                                  f"M={w.n_vars}, p_xi={w.chaos_degree} ({w.n_chaos} modes), {n_dof} DoFs, "
+                                  f"{w.n_levels}-level GMG", "n_dofs": n_dof},
+           "apply_us": round(t_apply * 1e6, 2), "gdofs": round(gdofs, 3),
+           "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                        "kernel": "operator apply: k_apply then k_node_gather, one stream, median of "
+                                  f"{args.apply_reps} HIP-event-timed applies",
+                        "algorithmic_bytes_per_apply": abytes, "source_hash": src_hash, "cells_per_workgroup": cpb,
+                        "traffic_over_algorithmic": round(traffic / abytes, 3) if traffic else None},
+           "roofline_fp64": {"bound": "alu", "achieved": round(achieved_tf, 2), "peak": FP64_PEAK_TFLOPS,
+                             "unit": "TFLOP/s", "frac": round(achieved_tf / FP64_PEAK_TFLOPS, 4),
+                             "algorithmic_flops_per_apply": aflops, "flops_per_dof": round(aflops / n_dof, 1),
+                             "flops_without_even_odd": aflops_plain},
+           "apply_tiles": tiles, "setup_s": round(setup_s, 2)}
+
+    if not args.only_apply:
+        # right-hand side b = AA x* for a seeded x* that vanishes on the Dirichlet boundary (so b does too)
+        xg = torch.from_numpy(sg_inputs.interior_target(w)).to(dev)
+        b = G.apply(xg)
+        torch.cuda.synchronize()
+        x = torch.zeros_like(b)
+
+        def run_solves(P, count):
+            times, infos = [], []
+            for _ in range(count):
+                x.zero_()
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                _, info = P.solve(b, x, rtol=1e-8, max_iter=500)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+                infos.append(info)
+            return times, infos
+
+        run_solves(G, args.warmup)
+        t64, i64 = run_solves(G, args.steps)
+        x64 = x.clone()
+        res = {"fp64_ms": round(float(np.mean(t64)), 2), "fp64_iterations": i64[-1]["iterations"],
+               "fp64_rel_residual_true": i64[-1]["rel_residual_true"],
+               "fp64_t_apply_ms": round(i64[-1]["t_apply_ms"], 2), "fp64_t_prec_ms": round(i64[-1]["t_prec_ms"], 2),
+               "fp64_applies": i64[-1]["applies"], "fp64_vcycles": i64[-1]["vcycles"],
+               "fp64_err_vs_xstar": float(torch.linalg.norm(x - xg) / torch.linalg.norm(xg)),
+               "work_proxy": i64[-1]["work_proxy"]}
+        print(f"[bench] {name} fp64 solve {res['fp64_ms']} ms, {res['fp64_iterations']} it", file=sys.stderr,
+              flush=True)
+        if not args.no_mixed:
+            G32 = sgheat.problem_from_workload(w, sgheat.SG_MIXED)
+            if not args.no_autotune:
+                res["mixed_tiles"] = G32.autotune(reps=10)
+            run_solves(G32, args.warmup)
+            t32, i32 = run_solves(G32, args.steps)
+            err = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
+            res.update({"mixed_ms": round(float(np.mean(t32)), 2), "mixed_iterations": i32[-1]["iterations"],
+                        "mixed_rel_residual_true": i32[-1]["rel_residual_true"],
+                        "mixed_t_apply_ms": round(i32[-1]["t_apply_ms"], 2),
+                        "mixed_t_prec_ms": round(i32[-1]["t_prec_ms"], 2),
+                        "mixed_err_vs_xstar": float(torch.linalg.norm(x - xg) / torch.linalg.norm(xg)),
+                        "mixed_vs_fp64_solution_rel_diff": err,
+                        "mixed_speedup": round(float(np.mean(t64)) / float(np.mean(t32)), 3)})
+            print(f"[bench] {name} mixed solve {res['mixed_ms']} ms, {res['mixed_iterations']} it", file=sys.stderr,
+                  flush=True)
+            G32.close()
+        leg["solve"] = res
+        del b, x, xg, x64
+    G.close()
+    torch.cuda.empty_cache()
+    return leg
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -331,6 +516,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the occupancy-based apply tiles")
     ap.add_argument("--no-batch", action="store_true", help="skip the Monte-Carlo batch timing (256 samples, 20 slabs)")
     ap.add_argument("--only-apply", action="store_true", help="skip the solves (for profiling the apply)")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 3D Q3 24^3 dG(2) leg (apply and solves)")
+    ap.add_argument("--cpu-c3", action="store_true",
+                    help="also time the CPU oracle's apply on the full 3D Q3 workload (about 2 minutes of assembly)")
     ap.add_argument("--finite-chaos", type=int, default=-1, metavar="P",
                     help="also run the finite-chaos benchmark for p_xi = 0..P at the paper's discretisation")
     ap.add_argument("--mc-rootn", action="store_true",
@@ -362,116 +550,24 @@ def main():
         return
     w = sg_inputs.WORKLOADS[args.workload]
     stream = torch.cuda.current_stream()
-    t_setup = time.perf_counter()
-    G = sgheat.problem_from_workload(w, sgheat.SG_FP64)
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t_setup
-    tiles = G.autotune(reps=10) if not args.no_autotune else None
-    cpb = tiles["fp64_full"] if tiles else int(os.environ.get("SGHEAT_APPLY_CPB", "0")) or None
-    n = G.n(0)
-    print(f"[bench] {args.workload}: {n} DoFs, setup {setup_s:.2f} s", file=sys.stderr, flush=True)
-
-    # ---- operator apply over rotating (x, y) pairs --------------------------------------------------
-    n_dof, abytes, aflops = apply_model(w)
-    pairs = max(1, math.ceil(1.2e9 / (16 * n)))
-    xs = [torch.from_numpy(sg_inputs.uniform_vector(n, sg_inputs.SEED_APPLY_INPUT + 100 * i)).to(dev)
-          for i in range(pairs)]
-    ys = [torch.empty_like(xs[0]) for _ in range(pairs)]
-    for i in range(5):
-        G.apply(xs[i % pairs], ys[i % pairs])
-    torch.cuda.synchronize()
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.apply_reps + 1)]
-    evs[0].record(stream)
-    for i in range(args.apply_reps):
-        G.apply(xs[i % pairs], ys[i % pairs])
-        evs[i + 1].record(stream)
-    torch.cuda.synchronize()
-    per_apply = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.apply_reps)]) / 1e3
-    t_apply = float(np.median(per_apply))
-    gdofs = n_dof / t_apply / 1e9
-    achieved_gbs = abytes / t_apply / 1e9
-    achieved_tf = aflops / t_apply / 1e12
-    print(f"[bench] apply {t_apply * 1e6:.1f} us  {gdofs:.1f} GDoF/s  {achieved_gbs:.0f} GB/s  "
-          f"{achieved_tf:.1f} TFLOP/s", file=sys.stderr, flush=True)
-    del xs, ys
-    copy_gbs = copy_bandwidth(torch, dev)
     src_hash = apply_source_hash()
-    meas = MEASURED_TRAFFIC.get((args.workload, src_hash, cpb))
-    traffic = meas["fetch_bytes"] + meas["write_bytes"] if meas else None
+    leg = run_workload(torch, dev, stream, sgheat, sg_inputs, w, args, src_hash)
+    copy_gbs = copy_bandwidth(torch, dev)
     print(f"[bench] device copy {copy_gbs:.0f} GB/s; apply sources {src_hash}", file=sys.stderr, flush=True)
-
     out = {"metric": "SG operator apply GDoF/s + % HBM peak; FGMRES-GMG slab solve time, FP64 vs mixed",
-           "value": round(gdofs, 3), "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "value": leg["gdofs"], "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic (seeded PCG64 U[-1,1] input; analytic sine-mode coefficient)",
-           "config": {"workload": f"{args.workload}: {w.dim}D Q{w.fe_degree} on {w.n_cells_1d}^{w.dim} cells, "
-                                  f"dG({w.time_degree}), M={w.n_vars}, p_xi={w.chaos_degree} ({w.n_chaos} modes), "
-                                  f"{n_dof} DoFs, {w.n_levels}-level GMG", "n_dofs": n_dof},
-           "apply_us": round(t_apply * 1e6, 2),
-           "roofline": {"bound": "alu", "achieved": round(achieved_tf, 2), "peak": FP64_PEAK_TFLOPS,
-                        "unit": "TFLOP/s", "frac": round(achieved_tf / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
-                        "kernel": "operator apply: k_apply then k_node_gather, one stream, median of "
-                                  f"{args.apply_reps} HIP-event-timed applies",
-                        "algorithmic_flops_per_apply": aflops, "source_hash": src_hash, "cells_per_workgroup": cpb},
-           "roofline_hbm": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-                            "algorithmic_bytes_per_apply": abytes,
-                            "measured_frac": (round(traffic / t_apply / 1e9 / HBM_PEAK_GBS, 4) if traffic else None)},
-           "copy_gbs": round(copy_gbs, 1),
-           "apply_tiles": tiles,
-           "setup_s": round(setup_s, 2)}
-
-    # ---- slab solves -------------------------------------------------------------------------------
-    if not args.only_apply:
-        # right-hand side b = AA x* for a seeded x* that vanishes on the Dirichlet boundary (so b does too)
-        xg = torch.from_numpy(sg_inputs.interior_target(w)).to(dev)
-        b = G.apply(xg)
-        torch.cuda.synchronize()
-        x = torch.zeros_like(b)
-
-        def run_solves(P, count):
-            times, infos = [], []
-            for _ in range(count):
-                x.zero_()
-                torch.cuda.synchronize()
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                _, info = P.solve(b, x, rtol=1e-8, max_iter=500)
-                e1.record(stream)
-                torch.cuda.synchronize()
-                times.append(e0.elapsed_time(e1))
-                infos.append(info)
-            return times, infos
-
-        run_solves(G, args.warmup)
-        t64, i64 = run_solves(G, args.steps)
-        x64 = x.clone()
-        res = {"fp64_ms": round(float(np.mean(t64)), 2), "fp64_iterations": i64[-1]["iterations"],
-               "fp64_rel_residual_true": i64[-1]["rel_residual_true"],
-               "fp64_t_apply_ms": round(i64[-1]["t_apply_ms"], 2), "fp64_t_prec_ms": round(i64[-1]["t_prec_ms"], 2),
-               "fp64_applies": i64[-1]["applies"], "fp64_vcycles": i64[-1]["vcycles"],
-               "fp64_err_vs_xstar": float(torch.linalg.norm(x - xg) / torch.linalg.norm(xg)),
-               "work_proxy": i64[-1]["work_proxy"]}
-        out["ms_per_step"] = res["fp64_ms"]
-        print(f"[bench] fp64 solve {res['fp64_ms']} ms, {res['fp64_iterations']} it", file=sys.stderr, flush=True)
-        if not args.no_mixed:
-            G32 = sgheat.problem_from_workload(w, sgheat.SG_MIXED)
-            if not args.no_autotune:
-                res["mixed_tiles"] = G32.autotune(reps=10)
-            run_solves(G32, args.warmup)
-            t32, i32 = run_solves(G32, args.steps)
-            err = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
-            res.update({"mixed_ms": round(float(np.mean(t32)), 2), "mixed_iterations": i32[-1]["iterations"],
-                        "mixed_rel_residual_true": i32[-1]["rel_residual_true"],
-                        "mixed_err_vs_xstar": float(torch.linalg.norm(x - xg) / torch.linalg.norm(xg)),
-                        "mixed_vs_fp64_solution_rel_diff": err,
-                        "mixed_speedup": round(float(np.mean(t64)) / float(np.mean(t32)), 3)})
-            print(f"[bench] mixed solve {res['mixed_ms']} ms, {res['mixed_iterations']} it", file=sys.stderr,
-                  flush=True)
-            G32.close()
-        out["solve"] = res
+           "config": leg["config"], "apply_us": leg["apply_us"], "roofline": leg["roofline"],
+           "roofline_fp64": leg["roofline_fp64"], "copy_gbs": round(copy_gbs, 1), "apply_tiles": leg["apply_tiles"],
+           "setup_s": leg["setup_s"]}
+    if "solve" in leg:
+        out["solve"] = leg["solve"]
+        out["ms_per_step"] = leg["solve"]["fp64_ms"]
     else:
-        out["ms_per_step"] = round(t_apply * 1e3, 4)
+        out["ms_per_step"] = round(leg["apply_us"] / 1e3, 4)
+    if not args.no_c3 and args.workload == "c2":
+        out["c3"] = run_workload(torch, dev, stream, sgheat, sg_inputs, sg_inputs.WORKLOADS["c3"], args, src_hash)
 
     if not args.no_adjoint and not args.only_apply:
         out["adjoint"] = adjoint_timing(torch)
@@ -493,9 +589,9 @@ def main():
         print(f"[bench] Monte-Carlo root-N windows: {out['mc_root_n']['windows']}", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w)
+        extra = (sg_inputs.WORKLOADS["c3"],) if args.cpu_c3 else ()
+        out["cpu_baseline"] = cpu_baseline(w, extra=extra)
         print(f"[bench] cpu baseline {out['cpu_baseline']['value']:.4f} GDoF/s", file=sys.stderr, flush=True)
-    G.close()
     print(json.dumps(out))
 
 

@@ -50,7 +50,13 @@ struct ApplyArgs {
     int mu0;              // position of mu = 0 in the coefficient list
     int mum[8];           // position of mu = e_m (m = 1..M) in the coefficient list, -1 if absent
     int merge;            // 1: sum the x faces shared by the workgroup's cells before storing
+    int ss;               // slot stride of the exchange rows (>= N_xi N_t row_stride((k+1)^d))
 };
+
+// Stride of one component's row of point values in the exchange rows: odd, so the rows of consecutive
+// components start on different banks (a power-of-two point count, as 64 for Q3 cells, would put every
+// component of a wave instruction on the same bank).
+__host__ __device__ constexpr int row_stride(int np) { return np % 2 ? np : np + 1; }
 
 // out[.., o, ..] (+)= sum_i M(o, i) in[.., i, ..] along direction DIR of an N1^DIM point block;
 // M(o, i) = TR ? M[i*N1 + o] : M[o*N1 + i].
@@ -220,35 +226,35 @@ __device__ constexpr double kSqrtTab[9] = {0.0, 1.0, 1.4142135623730951, 1.73205
                                            2.2360679774997896, 2.4494897427831781, 2.6457513110645907,
                                            2.8284271247461903};
 
-// Chaos coupling at one (cell, point, time index) for all modes, in registers: g[alpha] -> flux.
-template <int M, int P, int NT, int NP, typename T>
+// Chaos coupling at one (cell, point, time index) for all modes, in registers: g[alpha] -> flux
+//     f[alpha] = a_0(x_q) g[alpha] + sum_m a_{e_m}(x_q) (sqrt(alpha_m) g[alpha - e_m] + sqrt(alpha_m + 1) g[alpha + e_m]).
+// The products a_{e_m}(x_q) sqrt(k), k = 1 .. P, are formed once per point, so every neighbour entry of
+// the Galerkin tensor costs one FMA.
+template <int M, int P, int NT, int NP, int RS, typename T>
 __device__ __forceinline__ void couple_point(T* rows, const T* crow, int q, int ti, int mu0, const int* mum) {
     constexpr ChaosTab<M, P> tab{};
     constexpr int N = ChaosTab<M, P>::N;
     T g[N];
 #pragma unroll
-    for (int al = 0; al < N; ++al) g[al] = rows[(al * NT + ti) * NP + q];
+    for (int al = 0; al < N; ++al) g[al] = rows[(al * NT + ti) * RS + q];
     const T c0 = crow[mu0 * NP + q];
-    T cm[M];
+    T w[M][P];
 #pragma unroll
-    for (int m = 0; m < M; ++m) cm[m] = mum[m] >= 0 ? crow[mum[m] * NP + q] : T(0);
+    for (int m = 0; m < M; ++m) {
+        const T cm = mum[m] >= 0 ? crow[mum[m] * NP + q] : T(0);
+#pragma unroll
+        for (int k = 0; k < P; ++k) w[m][k] = cm * T(kSqrtTab[k + 1]);
+    }
 #pragma unroll
     for (int al = 0; al < N; ++al) {
         T f = c0 * g[al];
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const int bm = tab.nbm[al][m], bp = tab.nbp[al][m];
-            if (bm < 0 && bp < 0) continue;
-            T t;
-            if (bm >= 0 && bp >= 0)
-                t = T(kSqrtTab[tab.idx[al][m]]) * g[bm] + T(kSqrtTab[tab.idx[al][m] + 1]) * g[bp];
-            else if (bm >= 0)
-                t = T(kSqrtTab[tab.idx[al][m]]) * g[bm];
-            else
-                t = T(kSqrtTab[tab.idx[al][m] + 1]) * g[bp];
-            f += cm[m] * t;
+            if (bm >= 0) f += w[m][tab.idx[al][m] - 1] * g[bm];
+            if (bp >= 0) f += w[m][tab.idx[al][m]] * g[bp];
         }
-        rows[(al * NT + ti) * NP + q] = f;
+        rows[(al * NT + ti) * RS + q] = f;
     }
 }
 
@@ -271,7 +277,8 @@ __device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const Tables<T
     constexpr int N1 = K + 1;
     constexpr int NP = ipow(N1, DIM);
     constexpr int NS = NP / N1;   // points per slice
-    T* const my_row = slot_rows + comp * NP;
+    constexpr int RS = row_stride(NP);
+    T* const my_row = slot_rows + comp * RS;
 
     // time coupling of the mass term: W[q] = w_q h^d sum_j (A_t[i][j] / B_t[i]) u_j(q)
 #pragma unroll
@@ -285,7 +292,7 @@ __device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const Tables<T
         T as = tb.As[j];
 #pragma unroll
         for (int i = 1; i < NT; ++i) as = (ti == i) ? tb.As[i * NT + j] : as;
-        const T* row = slot_rows + (alpha * NT + j) * NP;
+        const T* row = slot_rows + (alpha * NT + j) * RS;
 #pragma unroll
         for (int q = 0; q < NP; ++q) W[q] += as * row[q];
     }
@@ -351,7 +358,7 @@ __device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const Tables<T
                 const int q = task % NP;
                 const int tb_i = (task / NP) % NT;
                 const int sl = task / (NP * NT);
-                couple_point<CM, CP, NT, NP, T>(exch_all + (size_t)sl * SS, cl_all + (size_t)sl * CS, q, tb_i, a.mu0,
+                couple_point<CM, CP, NT, NP, RS, T>(exch_all + (size_t)sl * SS, cl_all + (size_t)sl * CS, q, tb_i, a.mu0,
                                                 a.mum);
             }
             __syncthreads();
@@ -396,7 +403,7 @@ __device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const Tables<T
                     // entries from LDS, or (wide workgroups, whose LDS holds only the rows) from memory
                     const T w = WIDE ? a.cw[e] : ent_w[e];
                     const T* cp = slot_coef + (WIDE ? a.cmu[e] * NP : ent_c[e]);
-                    const T* gp = slot_rows + (WIDE ? a.cbeta[e] * NT * NP : ent_g[e]) + ti * NP;
+                    const T* gp = slot_rows + (WIDE ? a.cbeta[e] * NT * RS : ent_g[e]) + ti * RS;
 #pragma unroll
                     for (int j = 0; j < NS; ++j) {
                         const int q = (j / st) * st * N1 + s * st + (j % st);
@@ -434,6 +441,74 @@ template <typename T>
 __host__ __device__ constexpr int padded_stride(int n) {
     constexpr int nb = sizeof(T) == 8 ? 16 : 32;   // 32 four-byte banks
     return n + ((1 - n) % nb + nb) % nb;
+}
+
+// LDS bank model of the exchange rows: the cycles of the wave instructions of the two access patterns
+// (a (cell, component) thread at one point of its own row; a coupling task of (cell, point, time
+// index) reading one mode), summed over `nb` banks of 4 bytes served `grp` lanes at a time.
+inline long exch_bank_cycles(int np, int rs, int nt, int nc, int cpb, int ss, int words, int nb, int grp) {
+    const int nthreads = nc * cpb;
+    const int ntask = cpb * np * nt;
+    long tot = 0;
+    std::vector<int> cnt(nb), last(nb);
+    std::vector<long long> addr(64);
+    auto wave = [&](int nl) {
+        for (int g0 = 0; g0 < nl; g0 += grp) {
+            std::fill(cnt.begin(), cnt.end(), 0);
+            std::fill(last.begin(), last.end(), -1);
+            int worst = 0;
+            for (int l = g0; l < std::min(nl, g0 + grp); ++l) {
+                if (addr[l] < 0) continue;
+                for (int w = 0; w < words; ++w) {
+                    const int b = (int)((addr[l] * words + w) % nb);
+                    bool dup = false;     // lanes reading the same word are served together
+                    for (int l2 = g0; l2 < l; ++l2)
+                        if (addr[l2] == addr[l]) { dup = true; break; }
+                    if (!dup) worst = std::max(worst, ++cnt[b]);
+                }
+            }
+            tot += worst;
+        }
+    };
+    for (int w0 = 0; w0 < nthreads; w0 += 64) {
+        const int nl = std::min(64, nthreads - w0);
+        for (int q = 0; q < np; ++q) {
+            for (int l = 0; l < nl; ++l) {
+                const int t = w0 + l;
+                addr[l] = (long long)(t % cpb) * ss + (long long)(t / cpb) * rs + q;
+            }
+            wave(nl);
+        }
+        for (int al = 0; al < std::min(nc / nt, 64); ++al) {
+            for (int l = 0; l < nl; ++l) {
+                const int t = w0 + l;
+                addr[l] = t < ntask ? (long long)(t / (np * nt)) * ss + (long long)(al * nt + (t / np) % nt) * rs + t % np
+                                    : -1;
+            }
+            wave(nl);
+        }
+    }
+    return tot;
+}
+
+// Slot stride of the exchange rows (>= nc rs elements): the residue, modulo the bank period, with the
+// fewest modelled cycles under both a 32- and a 64-bank LDS.
+template <typename T>
+inline int exch_slot_stride(int np, int nt, int nc, int cpb) {
+    const int rs = row_stride(np);
+    const int words = sizeof(T) / 4;
+    const int period = 32 / words;
+    const int base = nc * rs;
+    if (cpb == 1) return base;
+    int best = base;
+    long best_c = -1;
+    for (int r = 0; r < period; ++r) {
+        const int ss = base + r;
+        const long c = exch_bank_cycles(np, rs, nt, nc, cpb, ss, words, 32, 32 / words) +
+                       exch_bank_cycles(np, rs, nt, nc, cpb, ss, words, 64, 64 / words);
+        if (best_c < 0 || c < best_c) { best_c = c; best = ss; }
+    }
+    return best;
 }
 
 // Position of thread t of workgroup b: its cell slot and component, the workgroup's segment of cpb
@@ -477,7 +552,7 @@ __global__ void __launch_bounds__(WIDE ? 1024 : (ipow(K + 1, DIM) > 27 ? 256 : 5
     extern __shared__ unsigned char smem_raw[];
     const int cpb = a.cpb;
     const int NC = a.n_xi * NT;
-    const int SS = padded_stride<T>(NC * NP);                // slot stride of the exchange rows
+    const int SS = a.ss;                                     // slot stride of the exchange rows
     const int CS = padded_stride<T>(a.n_mu * NP);            // slot stride of the coefficient rows
     T* exch = reinterpret_cast<T*>(smem_raw);               // [cpb][SS]: rows [NC][NP]
     T* cl = exch + (size_t)SS * cpb;                         // [cpb][CS]: rows [n_mu][NP]
@@ -498,26 +573,23 @@ __global__ void __launch_bounds__(WIDE ? 1024 : (ipow(K + 1, DIM) > 27 ? 256 : 5
     const long long nn = a.g.n_nodes;
     const int* const cc = P.cc;
 
-    // stage the coefficient values of this block's cells (contiguous in memory)
-    for (int idx = t; idx < a.n_mu * NP * cpb; idx += nthreads) {
-        const int q = idx % NP;
-        const int mu = (idx / NP) % a.n_mu;
-        const int s = idx / (NP * a.n_mu);
-        const long long c2 = cell0 + s;
-        cl[s * CS + mu * NP + q] = (x0 + s < n) ? a.coef[mu * a.coef_mode_stride + c2 * NP + q] : T(0);
-    }
-    // stage the coupling entries (beta, mu, w) as LDS offsets
-    if constexpr (!MEAN && CM == 0 && !WIDE) {
-        for (int e = t; e < a.n_ent; e += nthreads) {
-            ent_w[e] = a.cw[e];
-            ent_g[e] = a.cbeta[e] * NT * NP;
-            ent_c[e] = a.cmu[e] * NP;
+    // All loads of the prologue are issued before the first wait: the coefficient values of this block's
+    // cells (contiguous in memory; into registers when every thread's share fits CPF of them), then the
+    // cell's nodal values.  Loads complete in order, so storing the coefficients to LDS waits only for
+    // their own loads, and one memory round trip serves the whole prologue.
+    constexpr int CPF = 4;
+    const int ncoef = a.n_mu * NP * cpb;
+    const bool cpf_ok = ncoef <= CPF * nthreads;
+    T cv[CPF];
+    if (cpf_ok) {
+#pragma unroll
+        for (int i = 0; i < CPF; ++i) {
+            const int idx = t + i * nthreads;
+            const int q = idx % NP;
+            const int mu = (idx / NP) % a.n_mu;
+            const int s = idx / (NP * a.n_mu);
+            cv[i] = (idx < ncoef && x0 + s < n) ? a.coef[mu * a.coef_mode_stride + (cell0 + s) * NP + q] : T(0);
         }
-    }
-    int e0 = 0, e1 = 0;
-    if constexpr (!MEAN && CM == 0) {
-        e0 = a.cptr[alpha * a.n_mu];
-        e1 = a.cptr[(alpha + 1) * a.n_mu];
     }
 
     T A[NP], B[NP];
@@ -537,6 +609,40 @@ __global__ void __launch_bounds__(WIDE ? 1024 : (ipow(K + 1, DIM) > 27 ? 256 : 5
         }
         A[p] = (active && !bnd) ? a.x[cbase + node] : T(0);
         if (p % 9 == 8) SG_FENCE();
+    }
+
+    if (cpf_ok) {
+#pragma unroll
+        for (int i = 0; i < CPF; ++i) {
+            const int idx = t + i * nthreads;
+            if (idx < ncoef) {
+                const int q = idx % NP;
+                const int mu = (idx / NP) % a.n_mu;
+                const int s = idx / (NP * a.n_mu);
+                cl[s * CS + mu * NP + q] = cv[i];
+            }
+        }
+    } else {
+        for (int idx = t; idx < ncoef; idx += nthreads) {
+            const int q = idx % NP;
+            const int mu = (idx / NP) % a.n_mu;
+            const int s = idx / (NP * a.n_mu);
+            const long long c2 = cell0 + s;
+            cl[s * CS + mu * NP + q] = (x0 + s < n) ? a.coef[mu * a.coef_mode_stride + c2 * NP + q] : T(0);
+        }
+    }
+    // stage the coupling entries (beta, mu, w) as LDS offsets
+    if constexpr (!MEAN && CM == 0 && !WIDE) {
+        for (int e = t; e < a.n_ent; e += nthreads) {
+            ent_w[e] = a.cw[e];
+            ent_g[e] = a.cbeta[e] * NT * row_stride(NP);
+            ent_c[e] = a.cmu[e] * NP;
+        }
+    }
+    int e0 = 0, e1 = 0;
+    if constexpr (!MEAN && CM == 0) {
+        e0 = a.cptr[alpha * a.n_mu];
+        e1 = a.cptr[(alpha + 1) * a.n_mu];
     }
 
     T* const slot_rows = exch + (size_t)slot * SS;
@@ -562,7 +668,7 @@ __global__ void __launch_bounds__(WIDE ? 1024 : (ipow(K + 1, DIM) > 27 ? 256 : 5
             // x = k face (the same two-term sum the gather would form) and the lower one skips it
             constexpr int NS = NP / N1;
             __syncthreads();                              // the exchange rows are free again
-            T* const mine = exch + (size_t)E.slot * SS + E.comp * NP;
+            T* const mine = exch + (size_t)E.slot * SS + E.comp * row_stride(NP);
 #pragma unroll
             for (int j = 0; j < NS; ++j) mine[j] = B[j * N1 + K];
             __syncthreads();
@@ -605,6 +711,25 @@ inline int choose_cpb_uncached(const void* kern, int nc, size_t lds_fixed, size_
         }
     }
     return best;
+}
+
+// The slot stride depends only on the sizes; remember it (the apply launch path is hot).
+template <typename T>
+inline int cached_slot_stride(int np, int nt, int nc, int cpb) {
+    struct Entry {
+        int np, nt, nc, cpb, ss;
+    };
+    static std::mutex mu;
+    static std::vector<Entry> cache;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (const Entry& e : cache)
+            if (e.np == np && e.nt == nt && e.nc == nc && e.cpb == cpb) return e.ss;
+    }
+    const int ss = exch_slot_stride<T>(np, nt, nc, cpb);
+    std::lock_guard<std::mutex> lk(mu);
+    cache.push_back({np, nt, nc, cpb, ss});
+    return ss;
 }
 
 // The choice depends only on the kernel and the sizes; remember it (the apply launch path is hot).
@@ -665,30 +790,20 @@ hipError_t run_apply(const ApplyOp<T>& op, const T* x, T* s_out, hipStream_t s) 
     a.mu0 = op.mu0;
     for (int m = 0; m < 8; ++m) a.mum[m] = op.mum[m];
     const int nc = op.n_xi * NT;
-    const size_t per_cell = (size_t)(padded_stride<T>(nc * NP) + padded_stride<T>(op.n_mu * NP)) * sizeof(T);
+    constexpr int RS = row_stride(NP);
+    const size_t cs_bytes = (size_t)padded_stride<T>(op.n_mu * NP) * sizeof(T);
+    // upper bound of one cell's LDS (the slot stride adds less than one bank period to nc RS)
+    const size_t per_cell = (size_t)(nc * RS + 32 / (sizeof(T) / 4)) * sizeof(T) + cs_bytes;
     if (nc > MAXT) {
         // more components than one regular workgroup: one cell per workgroup of nc <= 1024 threads (2D)
         if constexpr (DIM == 2) {
             auto wk = op.mean ? k_apply<DIM, K, NT, T, true, 0, 0, true> : k_apply<DIM, K, NT, T, false, 0, 0, true>;
-            ApplyArgs<T> a{};
-            a.x = x;
-            a.s = s_out;
-            a.coef = op.coef;
-            a.coef_mode_stride = op.coef_mode_stride;
-            a.cptr = op.cptr;
-            a.cbeta = op.cbeta;
-            a.cmu = op.cmu;
-            a.cw = op.cw;
-            a.n_xi = op.n_xi;
-            a.n_mu = op.n_mu;
-            a.n_ent = op.n_ent;
-            a.g = op.g;
-            a.mu0 = op.mu0;
-            for (int m = 0; m < 8; ++m) a.mum[m] = op.mum[m];
             a.cpb = 1;
             a.merge = 0;
+            a.ss = nc * RS;
             if (op.used_cpb) *op.used_cpb = 1;
-            const size_t lds = per_cell + 16;
+            if (op.used_lz) *op.used_lz = 1;
+            const size_t lds = (size_t)a.ss * sizeof(T) + cs_bytes + 16;
             if (nc > 1024 || lds > 160 * 1024) return hipErrorInvalidConfiguration;
             if (lds > 64 * 1024)
                 (void)hipFuncSetAttribute((const void*)wk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -704,9 +819,11 @@ hipError_t run_apply(const ApplyOp<T>& op, const T* x, T* s_out, hipStream_t s) 
     const int cpb = op.cells_per_block > 0 ? op.cells_per_block : choose_cpb((const void*)kern, nc, fixed, per_cell, MAXT);
     a.cpb = cpb;
     a.merge = op.merge && cpb > 1;
+    a.ss = cached_slot_stride<T>(NP, NT, nc, cpb);
     if (op.used_cpb) *op.used_cpb = cpb;
+    if (op.used_lz) *op.used_lz = 1;     // one cell layer per workgroup: the z layout is per cell
     const int threads = nc * cpb;
-    const size_t lds = fixed + per_cell * cpb;
+    const size_t lds = fixed + ((size_t)a.ss * sizeof(T) + cs_bytes) * cpb;
     if (threads > MAXT || lds > 160 * 1024) return hipErrorInvalidConfiguration;
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

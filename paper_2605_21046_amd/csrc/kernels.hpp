@@ -37,15 +37,23 @@ struct ApplyOp {
     int merge;                    // 1: the cells of a workgroup sum their shared x faces before storing
                                   // (broken along x only between workgroups: segments of cpb cells)
     int* used_cpb;                // if set, receives the cells per workgroup of the launch
+    int lz;                       // 3D, merged layout: cells per z chunk a workgroup marches through
+                                  // (0 = chosen from the mesh size; the z faces inside a chunk are summed
+                                  // in registers, so the broken layout is chunked along z as along x)
+    int* used_lz;                 // if set, receives the z chunk length of the launch
 };
 template <typename T>
 hipError_t launch_apply(const ApplyOp<T>& op, const T* x, T* s_out, hipStream_t s);
 // Length in node intervals of one broken x segment of an apply's output (k: per cell; cpb k: merged).
 template <typename T>
 inline int apply_segment(const ApplyOp<T>& op, int cpb) { return op.merge && cpb > 1 ? cpb * op.k : op.k; }
+// The same along z (lz k; k for the per-cell layout).
+template <typename T>
+inline int apply_zsegment(const ApplyOp<T>& op, int lz) { return lz * op.k; }
 
-// Sum of the broken copies of every node, then one of (sx: length of a broken segment along x in node
-// intervals, k for the per-cell layout, cpb k for an apply whose workgroups merged their x faces)
+// Sum of the broken copies of every node, then one of (sx, sz: length of a broken segment along x and
+// along z in node intervals; k for the per-cell layout, cpb k (x) and lz k (z) for an apply whose
+// workgroups merged their x faces and marched through z chunks)
 //   GATHER_SET:      out = sum                 (Dirichlet rows: out = x)
 //   GATHER_RESIDUAL: out = b - sum             (Dirichlet rows: out = b - x)
 //   GATHER_VANKA:    out += omega sum / mult   (Dirichlet rows: out = b); mult = cells sharing the node
@@ -67,7 +75,7 @@ hipError_t launch_sample_stats(const double* u, int N, int nt, long long nn, dou
                                hipStream_t s);
 template <typename T>
 hipError_t launch_node_gather(GatherOp op, int dim, int k, Grid g, int ncomp, const T* s_in, const T* x, const T* b,
-                              T* out, T omega, int sx, hipStream_t s);
+                              T* out, T omega, int sx, int sz, hipStream_t s);
 
 // ---- Vanka -----------------------------------------------------------------------------------------
 // Element stiffness of the mean coefficient: E[cell][a][b] = sum_q c0(cell,q) sum_d dphi_a dphi_b.

@@ -106,17 +106,19 @@ __global__ void k_transfer_1d(int dim, long long total, int i0, int i1, int o0, 
 template <typename T, int OP, int DIM, int K>
 __global__ void __launch_bounds__(256)
     k_node_gather(Grid g, const T* __restrict__ s_in, const T* __restrict__ x, const T* __restrict__ b,
-                  T* __restrict__ out, T omega, unsigned sx) {
+                  T* __restrict__ out, T omega, unsigned sx, unsigned sz) {
     constexpr int N1 = K + 1;
     const unsigned n1 = g.n1, nc = g.n;
     const unsigned nb1 = nc * N1;
-    // x: segments of sx node intervals (sx = K: one cell), sx + 1 broken entries each except a shorter
-    // last one: (n1 - 1) + nsx entries in all
+    // x (and z in 3D): segments of sx (sz) node intervals (K: one cell), sx + 1 broken entries each
+    // except a shorter last one: (n1 - 1) + nsx entries in all
     const unsigned nsx = (n1 - 1 + sx - 1) / sx;
     const unsigned nbx = (n1 - 1) + nsx;
+    const unsigned nsz = (n1 - 1 + sz - 1) / sz;
+    const unsigned nbz = (n1 - 1) + nsz;
     unsigned nbn = nbx;
     if (DIM >= 2) nbn *= nb1;
-    if (DIM == 3) nbn *= nb1;
+    if (DIM == 3) nbn *= nbz;
     const unsigned nn = (unsigned)g.n_nodes;
     const long long comp = blockIdx.y;
     const T* sc = s_in + comp * (long long)nbn;
@@ -133,8 +135,8 @@ __global__ void __launch_bounds__(256)
             const unsigned i = (d == DIM - 1) ? r : r % n1;
             r /= n1;
             bnd |= (i == 0) | (i == n1 - 1);
-            const unsigned sl = d == 0 ? sx : (unsigned)K;      // segment length along d
-            const unsigned ns = d == 0 ? nsx : nc;               // segments along d
+            const unsigned sl = d == 0 ? sx : (d == 2 ? sz : (unsigned)K);   // segment length along d
+            const unsigned ns = d == 0 ? nsx : (d == 2 ? nsz : nc);           // segments along d
             const unsigned c = i / sl;
             if (i % sl == 0 && i > 0 && i < n1 - 1) {
                 lo[d] = (c - 1) * (sl + 1) + sl;
@@ -493,12 +495,13 @@ hipError_t launch_transfer_1d(int dim, int ncomp, const int* in_dims, const int*
 
 template <typename T>
 hipError_t launch_node_gather(GatherOp op, int dim, int k, Grid g, int ncomp, const T* s_in, const T* x, const T* b,
-                              T* out, T omega, int sx, hipStream_t s) {
-    if (ncomp > 65535 || g.n_nodes > 0x7fffffffLL || k < 1 || k > 4 || sx < k || sx % k) return hipErrorInvalidConfiguration;
+                              T* out, T omega, int sx, int sz, hipStream_t s) {
+    if (ncomp > 65535 || g.n_nodes > 0x7fffffffLL || k < 1 || k > 4 || sx < k || sx % k || sz < k || sz % k)
+        return hipErrorInvalidConfiguration;
     const unsigned bx = std::min<long long>((g.n_nodes + 255) / 256, 4096);
     const dim3 grid(bx, ncomp), block(256);
 #define SG_NG(OP_, D_, K_) \
-    hipLaunchKernelGGL((k_node_gather<T, OP_, D_, K_>), grid, block, 0, s, g, s_in, x, b, out, omega, (unsigned)sx)
+    hipLaunchKernelGGL((k_node_gather<T, OP_, D_, K_>), grid, block, 0, s, g, s_in, x, b, out, omega, (unsigned)sx, (unsigned)sz)
 #define SG_NG_K(OP_, D_)                          \
     switch (k) {                                  \
         case 1: SG_NG(OP_, D_, 1); break;         \
@@ -626,9 +629,9 @@ template hipError_t launch_transfer_1d<double>(int, int, const int*, const int*,
 template hipError_t launch_transfer_1d<float>(int, int, const int*, const int*, int, const int*, const float*, int,
                                               const float*, float*, bool, hipStream_t);
 template hipError_t launch_node_gather<double>(GatherOp, int, int, Grid, int, const double*, const double*,
-                                               const double*, double*, double, int, hipStream_t);
+                                               const double*, double*, double, int, int, hipStream_t);
 template hipError_t launch_node_gather<float>(GatherOp, int, int, Grid, int, const float*, const float*, const float*,
-                                              float*, float, int, hipStream_t);
+                                              float*, float, int, int, hipStream_t);
 template hipError_t launch_coarse_solve<double>(const double*, long long, int, const int*, int, long long,
                                                 const double*, double*, hipStream_t);
 template hipError_t launch_coarse_solve<float>(const double*, long long, int, const int*, int, long long, const float*,

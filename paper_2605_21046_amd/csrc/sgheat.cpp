@@ -743,6 +743,17 @@ int apply_cpb_override() {
     return v;
 }
 
+// Cells per z chunk of the marching 3D apply kernel: chosen from the mesh size unless the
+// SGHEAT_APPLY_LZ environment variable fixes it (a tuning override).
+int apply_lz_override() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = std::getenv("SGHEAT_APPLY_LZ");
+        v = e ? std::max(0, std::atoi(e)) : 0;
+    }
+    return v;
+}
+
 template <typename T>
 ApplyOp<T> make_op(const sg_handle h, int level, bool full) {
     const Level& lv = h->lv[level];
@@ -787,6 +798,8 @@ ApplyOp<T> make_op(const sg_handle h, int level, bool full) {
     if (op.cells_per_block == 0 && level < 16) op.cells_per_block = h->tuned_cpb[sizeof(T) == 4][full][level];
     op.merge = 1;
     op.used_cpb = nullptr;
+    op.lz = apply_lz_override();
+    op.used_lz = nullptr;
     return op;
 }
 
@@ -830,16 +843,17 @@ sg_status autotune_apply(sg_handle h, int level, bool full, int reps, hipStream_
         if (cpb > lv.g.n) break;
         op.cells_per_block = cpb;
         // the cell kernel and its gather together (the merged layout's gain is in the gather)
-        int used = 1;
+        int used = 1, used_lz = 1;
         op.used_cpb = &used;
+        op.used_lz = &used_lz;
         hipError_t err = launch_apply<T>(op, x, sbuf_as<T>(h), s);
         if (err == hipErrorInvalidConfiguration) continue;     // more threads or LDS than one workgroup has
         if (err != hipSuccess) { st = fail(SG_EHIP, std::string("autotune: ") + hipGetErrorString(err)); break; }
-        const int sx = apply_segment(op, used);
+        const int sx = apply_segment(op, used), sz = apply_zsegment(op, used_lz);
         auto once = [&]() {
             (void)launch_apply<T>(op, x, sbuf_as<T>(h), s);
             (void)launch_node_gather<T>(GATHER_SET, op.dim, op.k, op.g, h->n_xi * h->NT, sbuf_as<T>(h), x, nullptr,
-                                        Prec<T>::r(lv), T(0), sx, s);
+                                        Prec<T>::r(lv), T(0), sx, sz, s);
         };
         once();
         (void)hipEventRecord(ev[0], s);
@@ -863,11 +877,12 @@ sg_status autotune_apply(sg_handle h, int level, bool full, int reps, hipStream_
 template <typename T>
 sg_status op_apply(sg_handle h, const ApplyOp<T>& op, const T* x, T* y, const T* b, hipStream_t s) {
     ApplyOp<T> o = op;
-    int cpb = 1;
+    int cpb = 1, lz = 1;
     o.used_cpb = &cpb;
+    o.used_lz = &lz;
     SG_HIP(launch_apply<T>(o, x, sbuf_as<T>(h), s));
     SG_HIP(launch_node_gather<T>(b ? GATHER_RESIDUAL : GATHER_SET, op.dim, op.k, op.g, h->n_xi * h->NT, sbuf_as<T>(h), x,
-                                 b, y, T(0), apply_segment(o, cpb), s));
+                                 b, y, T(0), apply_segment(o, cpb), apply_zsegment(o, lz), s));
     return SG_OK;
 }
 
@@ -887,7 +902,7 @@ sg_status smooth_level(sg_handle h, int l, const T* b, T* x, int sweeps, bool x_
         else
             SG_HIP(launch_vanka_cells<T>(h->d.dim, h->d.fe_degree, h->NT, lv.g, h->n_xi, inv, r, sbuf_as<T>(h), s));
         SG_HIP(launch_node_gather<T>(GATHER_VANKA, h->d.dim, h->d.fe_degree, lv.g, h->n_xi * h->NT, sbuf_as<T>(h),
-                                     nullptr, b, x, (T)h->d.vanka_omega, h->d.fe_degree, s));
+                                     nullptr, b, x, (T)h->d.vanka_omega, h->d.fe_degree, h->d.fe_degree, s));
     }
     return SG_OK;
 }
@@ -1048,12 +1063,13 @@ sg_status variant_apply(sg_handle h, const Tables<double>* tb, const double* coe
     op.tables = tb;
     op.coef = coef;
     op.merge = per_cell ? 0 : 1;     // per-cell results (for cell-wise forms) need the unmerged layout
-    int cpb = 1;
+    int cpb = 1, lz = 1;
     op.used_cpb = &cpb;
+    op.used_lz = &lz;
     SG_HIP(launch_apply<double>(op, x, h->sbuf.p, s));
     if (y)
         SG_HIP(launch_node_gather<double>(gop, h->d.dim, h->d.fe_degree, h->lv[0].g, h->n_xi * h->NT, h->sbuf.p, x,
-                                          nullptr, y, 0.0, apply_segment(op, cpb), s));
+                                          nullptr, y, 0.0, apply_segment(op, cpb), apply_zsegment(op, lz), s));
     return SG_OK;
 }
 
@@ -1536,7 +1552,8 @@ sg_status sg_load_vectors(sg_handle h, int nq1, int n_fields, const double* fval
         SG_HIP(launch_load_cells(h->d.dim, h->d.fe_degree, l0.g, nq1, tb, l0.h, fval ? fval + off : nullptr,
                                  fgrad ? fgrad + off * h->d.dim : nullptr, nf, h->sbuf.p, s));
         SG_HIP(launch_node_gather<double>(GATHER_INTERIOR, h->d.dim, h->d.fe_degree, l0.g, nf, h->sbuf.p, nullptr,
-                                          nullptr, out + (long long)f0 * l0.g.n_nodes, 0.0, h->d.fe_degree, s));
+                                          nullptr, out + (long long)f0 * l0.g.n_nodes, 0.0, h->d.fe_degree,
+                                          h->d.fe_degree, s));
     }
     return SG_OK;
 }
