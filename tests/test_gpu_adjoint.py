@@ -179,7 +179,7 @@ def test_autograd_backward_after_a_second_forward(torch_cuda):
     seq.close()
     for th, a0, J in ((th1, a01, J1), (th2, a02, J2)):
         Jo, _, dth, da0 = adj.gradient(aw, th.detach().numpy(), a0.detach().numpy())
-        assert float(J) == pytest.approx(Jo, rel=1e-9)
+        assert float(J.detach()) == pytest.approx(Jo, rel=1e-9)
         assert np.max(np.abs(th.grad.numpy() - dth)) <= 1e-7 * np.max(np.abs(dth))
         assert np.max(np.abs(a0.grad.numpy() - da0)) <= 1e-7 * np.max(np.abs(da0))
 
