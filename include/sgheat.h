@@ -133,6 +133,17 @@ sg_status sg_vector_length(sg_handle h, int level, long long* n);
  * solver-matrix-free-sg: only the action is formed).  FP64.  Asynchronous on the stream. */
 sg_status sg_operator_apply(sg_handle h, const double* x, double* y, void* hip_stream);
 
+/* y = AA x exactly as sg_operator_apply (same kernels, same result), for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the call allocates nothing and does not use the handle's cell-local workspace; the kernels write
+ * their cell-local results to a fixed scratch area of 64 MiB that the library holds on every GPU it
+ * runs on until the process ends (resolved once per device by sg_create).  Limit: the problem's
+ * N_xi * N_t * n_cells(0) * (k+1)^d doubles of cell-local results must fit those 64 MiB (8,388,608
+ * doubles), else SG_EINVAL and nothing is enqueued.  Every call on one GPU shares that GPU's scratch:
+ * calls that overlap in time on one GPU (different streams, or different handles) race and must be
+ * ordered by the caller.  x, y as for sg_operator_apply.  Asynchronous on the stream. */
+sg_status sg_operator_apply_noalloc(sg_handle h, const double* x, double* y, void* hip_stream);
+
 /* `sweeps` additive Vanka sweeps on the mean block I_xi (x) A_0 of level `level`, A_0 =
  * A_t (x) M_x + B_t (x) K_{a_0} (Remark solver-matrix-free-sg), or with desc.diag_blocks = 1 on the
  * block-diagonal operator diag_alpha(A_alpha) with each mode's own patch inverses:

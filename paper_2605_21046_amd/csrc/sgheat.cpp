@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -93,6 +94,7 @@ struct Level {
 
 struct sg_handle_s {
     sg_problem_desc d{};
+    int device = -1;                    // the GPU the handle's buffers live on
     std::vector<int> coef_mu;
     std::vector<double> samples;   // sample-batch handles: [n_samples][n_vars]
     std::vector<int> member_degree;     // member batches: [n_members]
@@ -873,17 +875,49 @@ sg_status autotune_apply(sg_handle h, int level, bool full, int reps, hipStream_
     return st;
 }
 
-// y = A x (b == nullptr) or y = b - A x, for the operator described by op
+// y = A x (b == nullptr) or y = b - A x, for the operator described by op; the cell-local results go
+// to `cells` (default: the handle's buffer)
 template <typename T>
-sg_status op_apply(sg_handle h, const ApplyOp<T>& op, const T* x, T* y, const T* b, hipStream_t s) {
+sg_status op_apply(sg_handle h, const ApplyOp<T>& op, const T* x, T* y, const T* b, hipStream_t s,
+                   T* cells = nullptr) {
     ApplyOp<T> o = op;
     int cpb = 1, lz = 1;
     o.used_cpb = &cpb;
     o.used_lz = &lz;
-    SG_HIP(launch_apply<T>(o, x, sbuf_as<T>(h), s));
-    SG_HIP(launch_node_gather<T>(b ? GATHER_RESIDUAL : GATHER_SET, op.dim, op.k, op.g, h->n_xi * h->NT, sbuf_as<T>(h), x,
-                                 b, y, T(0), apply_segment(o, cpb), apply_zsegment(o, lz), s));
+    T* sb = cells ? cells : sbuf_as<T>(h);
+    SG_HIP(launch_apply<T>(o, x, sb, s));
+    SG_HIP(launch_node_gather<T>(b ? GATHER_RESIDUAL : GATHER_SET, op.dim, op.k, op.g, h->n_xi * h->NT, sb, x, b, y,
+                                 T(0), apply_segment(o, cpb), apply_zsegment(o, lz), s));
     return SG_OK;
+}
+
+// ---- scratch of the allocation-free apply -----------------------------------------------------------
+// The cell-local results of sg_operator_apply_noalloc live in this file-scope device array (each GPU
+// the library runs on holds its own copy until the process ends).  In host code the name `scratch`
+// is a host-side stand-in, not device memory: host code uses only the device address resolved by
+// hipGetSymbolAddress, once per device at set-up (sg_create), with that device current.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `dev` (the current device); resolved once per device.
+sg_status resolve_scratch(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(SG_EUNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return SG_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(SG_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+    return SG_OK;
+}
+
+void* scratch_of(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[dev];
 }
 
 template <typename T>
@@ -1130,6 +1164,8 @@ sg_status sg_create(const sg_problem_desc* desc, sg_handle* out) {
     } catch (const std::bad_alloc&) {
         return fail(SG_ENOMEM, "host allocation failed during set-up");
     }
+    SG_HIP(hipGetDevice(&h->device));
+    SG_TRY(resolve_scratch(h->device));
     *out = h.release();
     return SG_OK;
 }
@@ -1153,6 +1189,22 @@ sg_status sg_operator_apply(sg_handle h, const double* x, double* y, void* hip_s
     if (overlap(x, y, h->N * sizeof(double))) return fail(SG_EINVAL, "x and y overlap");
     const ApplyOp<double> op = make_op<double>(h, 0, true);
     SG_TRY(op_apply<double>(h, op, x, y, nullptr, (hipStream_t)hip_stream));
+    return SG_OK;
+}
+
+sg_status sg_operator_apply_noalloc(sg_handle h, const double* x, double* y, void* hip_stream) {
+    if (!h || !x || !y) return fail(SG_EINVAL, "null argument");
+    if (overlap(x, y, h->N * sizeof(double))) return fail(SG_EINVAL, "x and y overlap");
+    // the cell-local results take at most n_xi N_t n_cells (k+1)^d doubles (the per-cell layout)
+    const size_t need = (size_t)h->n_xi * h->NT * (size_t)h->lv[0].g.n_cells * h->NP * sizeof(double);
+    if (need > kScratchBytes)
+        return fail(SG_EINVAL, "the operator's cell-local results (" + std::to_string(need) +
+                                   " bytes) exceed the allocation-free apply's scratch of " +
+                                   std::to_string(kScratchBytes) + " bytes; use sg_operator_apply");
+    double* cells = static_cast<double*>(scratch_of(h->device));
+    if (!cells) return fail(SG_EHIP, "scratch address of the handle's device is not resolved");
+    const ApplyOp<double> op = make_op<double>(h, 0, true);
+    SG_TRY(op_apply<double>(h, op, x, y, nullptr, (hipStream_t)hip_stream, cells));
     return SG_OK;
 }
 

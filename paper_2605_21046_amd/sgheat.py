@@ -18,7 +18,7 @@ SG_OK, SG_NOT_CONVERGED = 0, 1
 SG_FP64, SG_MIXED = 0, 1
 _STATUS = {0: "SG_OK", 1: "SG_NOT_CONVERGED", -1: "SG_EINVAL", -2: "SG_ENOMEM", -3: "SG_EHIP",
            -4: "SG_ESINGULAR", -5: "SG_EUNSUPPORTED"}
-EXPORTS = ["sg_create", "sg_destroy", "sg_vector_length", "sg_operator_apply", "sg_vanka_smooth",
+EXPORTS = ["sg_create", "sg_destroy", "sg_vector_length", "sg_operator_apply", "sg_operator_apply_noalloc", "sg_vanka_smooth",
            "gmg_vcycle", "fgmres_solve_slab", "sg_quadrature_points", "sg_node_coordinates", "sg_update_coefficients", "sg_operator_apply_T",
            "sg_slab_transfer", "sg_stiffness_form_cells", "sg_qoi_mean_var", "sg_sample_statistics", "sg_chaos_moments", "sg_gauss_points", "sg_index_set", "sg_chaos_projection",
            "sg_time_rule", "sg_time_load_weights", "sg_load_vectors", "sg_separable_vector", "sg_separable_error",
@@ -255,6 +255,12 @@ class Problem:
             y = torch.empty_like(x)
         n = self.n(0)
         _check(_lib.sg_operator_apply(self._h, _ptr(x, n, "x"), _ptr(y, n, "y"), _stream(stream)))
+        return y
+
+    def apply_noalloc(self, x, y, stream=None):
+        """y = AA x through sg_operator_apply_noalloc (no device allocation; y must be given)."""
+        n = self.n(0)
+        _check(_lib.sg_operator_apply_noalloc(self._h, _ptr(x, n, "x"), _ptr(y, n, "y"), _stream(stream)))
         return y
 
     def apply_T(self, x, y=None, stream=None):
