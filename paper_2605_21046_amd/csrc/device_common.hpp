@@ -8,7 +8,13 @@ namespace sg {
 constexpr int kMaxN1 = 5;   // k + 1 <= 5 (Q1 .. Q4)
 constexpr int kMaxNT = 4;   // r + 1 <= 4 (dG(0) .. dG(3))
 
-constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+// b^e, iterative: device code with a run-time exponent inlines and folds it (a recursive form is
+// not inlined, and such a call forces the whole kernel onto the call ABI with scratch spills)
+__host__ __device__ __forceinline__ constexpr int ipow(int b, int e) {
+    int r = 1;
+    for (int i = 0; i < e; ++i) r *= b;
+    return r;
+}
 
 // 1D reference tables and time matrices, copied into the kernel argument segment.
 //   S[q][a]  = l_a(g_q): GLL Lagrange basis a at Gauss point q          (interpolation to points)

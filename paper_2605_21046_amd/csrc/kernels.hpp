@@ -101,7 +101,23 @@ hipError_t launch_patch_invert(int dim, int k, int nt, Grid g, const double* E, 
                                const PatchTime& pt, double* inv64, float* inv32, int* status,
                                hipStream_t s);
 
-// Patch corrections c_K = A_{0,K}^{-1} R_K r of every cell (inverses stored transposed), written to
+// Storage of one cell's patch inverse (n_p x n_p) for the patch products below: B[c][I] = A^{-1}[I][c]
+// (c: the k index of the product, I: the patch row), in fragments so that the `spl` consecutive
+// k-steps (4 columns each) one lane consumes are contiguous: element (c, I) is at
+//     ((g * 4 + c % 4) * n_p + I) * spl + (c / 4) % spl,   g = c / (4 spl),
+// with 4 ceil(n_p / 4) columns per cell (zero beyond n_p).  spl: the largest of 4, 2, 1 dividing the
+// k-step count with spl values in at most 16 bytes (one vector load per lane and fragment).
+constexpr int vanka_ksteps(int npp) { return (npp + 3) / 4; }
+constexpr int vanka_spl(int npp, int elem) {
+    return (vanka_ksteps(npp) % 4 == 0 && 4 * elem <= 16) ? 4 : ((vanka_ksteps(npp) % 2 == 0 && 2 * elem <= 16) ? 2 : 1);
+}
+__host__ __device__ constexpr long long vanka_inv_stride(int npp) { return 4LL * vanka_ksteps(npp) * npp; }
+__host__ __device__ inline long long vanka_inv_offset(int npp, int spl, int c, int I) {
+    const int st = c / 4, kk = c % 4;
+    return ((long long)((st / spl) * 4 + kk) * npp + I) * spl + st % spl;
+}
+
+// Patch corrections c_K = A_{0,K}^{-1} R_K r of every cell (inverses in the fragment layout), written to
 // s_out in the broken layout; launch_node_gather(GATHER_VANKA) then forms
 // x <- x + omega sum_K R_K^T W_K c_K.  The residual patch of a cell (48 modes at a time) takes
 // ceil(n_p / 4) * 4 * 49 * sizeof(T) bytes of LDS.
@@ -109,7 +125,7 @@ inline size_t vanka_lds_bytes(int npp, size_t elem) { return (size_t)((npp + 3) 
 template <typename T>
 hipError_t launch_vanka_cells(int dim, int k, int nt, Grid g, int n_xi, const T* invT, const T* r, T* s_out,
                               hipStream_t s);
-// the same with one inverse per (mode, cell): invT [n_xi][n_cells][n_p][n_p]
+// the same with one inverse per (mode, cell): invT [n_xi][n_cells][vanka_inv_stride(n_p)]
 template <typename T>
 hipError_t launch_vanka_cells_modes(int dim, int k, int nt, Grid g, int n_xi, const T* invT, const T* r, T* s_out,
                                     hipStream_t s);

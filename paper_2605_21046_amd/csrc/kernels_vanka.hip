@@ -259,9 +259,10 @@ __global__ void __launch_bounds__(TG * TG)
             const int I = ty + TG * r, J = tx + TG * c;
             const int Jd = sigma_inv[J];
             if (I < npp && J < npp && Jd < npp) {
-                const long long o = (cell * npp + Jd) * npp + I;   // stored transposed: [cell][col][row]
-                if (inv64) inv64[o] = Am[r][c];
-                if (inv32) inv32[o] = (float)Am[r][c];
+                // B[Jd][I] = A^{-1}[I][Jd] in the fragment layout of each precision
+                const long long base = cell * vanka_inv_stride(npp);
+                if (inv64) inv64[base + vanka_inv_offset(npp, vanka_spl(npp, 8), Jd, I)] = Am[r][c];
+                if (inv32) inv32[base + vanka_inv_offset(npp, vanka_spl(npp, 4), Jd, I)] = (float)Am[r][c];
             }
         }
 }
@@ -300,6 +301,24 @@ struct Mfma16<float> {
     static __device__ __forceinline__ int out_row(int kk, int v) { return 4 * kk + v; }
 };
 
+// Vector of N values of T for one load (N = 1: T itself) and its element j (compile-time j).
+template <typename T, int N>
+struct VecOf {
+    typedef T type __attribute__((ext_vector_type(N)));
+};
+template <typename T>
+struct VecOf<T, 1> {
+    typedef T type;
+};
+template <typename T, int N>
+__device__ __forceinline__ T vec_elem(const typename VecOf<T, N>::type& v, int j) {
+    if constexpr (N == 1) {
+        return v;
+    } else {
+        return v[j];
+    }
+}
+
 constexpr int kVankaTiles = 3;                       // 16-mode tiles per pass (35 modes: one pass)
 constexpr int kVankaModesPerPass = kVankaTiles * 16;
 constexpr int kVankaLdr = kVankaModesPerPass + 1;    // LDS row stride, odd: rows in different banks
@@ -319,9 +338,11 @@ __global__ void __launch_bounds__(vanka_threads(DIM, K, NT))
     constexpr int KS = (NPP + 3) / 4;     // k-steps
     constexpr int KP = KS * 4;            // rows of the LDS tile (zero beyond n_p)
     constexpr int LR = (KP + 63) / 64 * 64;
-    // B fragments in flight: 16, or 8 for patches of more than 128 rows (whose three accumulator
-    // tiles and gather registers leave no room for 16 within the 3-waves-per-SIMD budget)
-    constexpr int PF = KS < 16 ? KS : (NPP > 128 ? 8 : 16);
+    // k-steps of B in flight: 128 bytes per lane (16 FP64 or 32 FP32 steps), or 64 for patches of more
+    // than 128 rows (whose three accumulator tiles and gather registers leave no room for more within
+    // the 3-waves-per-SIMD budget); all of them when the patch has fewer steps
+    constexpr int PF0 = (NPP > 128 ? 64 : 128) / (int)sizeof(T);
+    constexpr int PF = KS < PF0 ? KS : PF0;
     constexpr int NG = vanka_threads(DIM, K, NT) / LR;   // gather groups
     constexpr int LDR = kVankaLdr;
     constexpr int GB = (LDR + NG - 1) / NG;               // gathered values per thread and pass
@@ -343,18 +364,22 @@ __global__ void __launch_bounds__(vanka_threads(DIM, K, NT))
         for (int d = 0; d < DIM; ++d) { cc[d] = rr % g.n; rr /= g.n; }
     }
 
-    // B fragments: rows I, columns 4 step + kk of the inverse.  Every load is unconditional, from a
-    // clamped (valid) address: columns beyond n_p meet zero rows of A, and lanes with I >= n_p own
-    // output columns that are never stored, so the clamped values never reach a result.  (Loads
-    // under a branch would make the compiler wait for each refill at once.)
-    const T* const bc = invT + (long long)cell * (NPP * NPP) + min(I, NPP - 1);
-    const int last_col = min(4 * (KS - 1) + kk, NPP - 1);
-    auto load_b = [&](int step) -> T {   // step is a compile-time constant at every call
-        return step < KS - 1 ? bc[(4 * step + kk) * NPP] : bc[last_col * NPP];
+    // B fragments: rows I, columns 4 step + kk of the inverse, SPL consecutive k-steps per vector load
+    // (the fragment layout keeps them contiguous; columns beyond n_p are stored as zeros).  Every load
+    // is unconditional: lanes with I >= n_p read row n_p - 1 instead, they own output columns that
+    // are never stored.  (Loads under a branch would make the compiler wait for each refill at once.)
+    constexpr int SPL = vanka_spl(NPP, sizeof(T));
+    constexpr int NGR = KS / SPL;                          // fragment loads per lane and pass
+    constexpr int PFV = (PF / SPL) > 0 ? PF / SPL : 1;     // loads in flight
+    using VT = typename VecOf<T, SPL>::type;
+    const VT* const bc = reinterpret_cast<const VT*>(invT + (long long)cell * vanka_inv_stride(NPP)) +
+                         kk * NPP + min(I, NPP - 1);
+    auto load_b = [&](int grp) -> VT {   // grp is a compile-time constant at every call
+        return bc[grp * 4 * NPP];
     };
-    T ring[PF];
+    VT ring[PFV];
 #pragma unroll
-    for (int u = 0; u < PF; ++u) ring[u] = load_b(u);
+    for (int u = 0; u < PFV; ++u) ring[u] = load_b(u);
 
     // gather role: patch row lrow (node fastest: neighbouring lanes read neighbouring nodes), modes
     // agrp, agrp + NG, ... of the pass; Dirichlet rows, rows beyond n_p and modes beyond N_xi are 0.
@@ -401,7 +426,7 @@ __global__ void __launch_bounds__(vanka_threads(DIM, K, NT))
         if (pass > 0) {
             __syncthreads();                              // every wave is done with the previous pass
 #pragma unroll
-            for (int u = 0; u < PF; ++u) ring[u] = load_b(u);
+            for (int u = 0; u < PFV; ++u) ring[u] = load_b(u);
         }
         if (gthread) {
             T v[GB];
@@ -426,8 +451,9 @@ __global__ void __launch_bounds__(vanka_threads(DIM, K, NT))
         const T* const abase = rk + kk * LDR + (lane & 15);
 #pragma unroll
         for (int step = 0; step < KS; ++step) {
-            const T bv = ring[step % PF];
-            if (step + PF < KS) ring[step % PF] = load_b(step + PF);
+            const int grp = step / SPL;
+            const T bv = vec_elem<T, SPL>(ring[grp % PFV], step % SPL);
+            if (step % SPL == SPL - 1 && grp + PFV < NGR) ring[grp % PFV] = load_b(grp + PFV);
             const T* arow = abase + step * 4 * LDR;
 #pragma unroll
             for (int q = 0; q < kVankaTiles; ++q) acc[q] = M::run(arow[q * 16], bv, acc[q]);
@@ -664,10 +690,11 @@ __global__ void __launch_bounds__(256)
     }
     __syncthreads();
     if (t < NPP) {
-        const T* c = invT + ((long long)al * g.n_cells + cell) * (NPP * NPP) + t;
+        constexpr int SPL = vanka_spl(NPP, sizeof(T));
+        const T* c = invT + ((long long)al * g.n_cells + cell) * vanka_inv_stride(NPP);
         T acc = T(0);
 #pragma unroll 8
-        for (int j = 0; j < NPP; ++j) acc += c[(long long)j * NPP] * rp[j];
+        for (int j = 0; j < NPP; ++j) acc += c[vanka_inv_offset(NPP, SPL, j, t)] * rp[j];
         s_out[dst] = acc;
     }
 }

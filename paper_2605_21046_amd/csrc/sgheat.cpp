@@ -77,7 +77,7 @@ struct Level {
     Tables<float> tab32{};
     DevBuf<double> coef64;   // level 0: every mode; other levels: the mean mode only
     DevBuf<float> coef32;
-    DevBuf<double> inv64;    // patch inverses [n_cells][npp][npp]
+    DevBuf<double> inv64;    // patch inverses [n_cells][vanka_inv_stride(npp)] (fragment layout)
     DevBuf<float> inv32;
     // transfer stencils between this level (fine) and level + 1 (coarse)
     int wp = 0, wr = 0;
@@ -316,11 +316,14 @@ sg_status set_coefficients(sg_handle h, const double* coef_qp) {
             const double vol = std::pow(lv.h, dim);
             for (double& v : Mel) v *= vol;
             SG_TRY(Me.upload(Mel.data(), Mel.size(), "element matrices"));
-            const size_t ninv = (size_t)lv.g.n_cells * h->npp * h->npp;
+            // inverses in the fragment layout of the patch products (zero in the padding columns)
+            const size_t ninv = (size_t)lv.g.n_cells * vanka_inv_stride(h->npp);
             const bool want32 = h->mixed && l < L - 1;
             const int nblk = h->diag ? h->n_xi : 1;             // one set of patch inverses per mode
             SG_TRY(lv.inv64.alloc(ninv * nblk, "patch inverses"));
             if (want32) SG_TRY(lv.inv32.alloc(ninv * nblk, "patch inverses"));
+            SG_HIP(launch_fill<double>(lv.inv64.p, 0.0, (long long)(ninv * nblk), nullptr));
+            if (want32) SG_HIP(launch_fill<float>(lv.inv32.p, 0.0f, (long long)(ninv * nblk), nullptr));
             const size_t per_mode = (size_t)lv.g.n_cells * h->NP;
             std::vector<double> acomb(h->diag ? per_mode : 0);
             for (int a = 0; a < nblk; ++a) {

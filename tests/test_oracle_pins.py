@@ -99,19 +99,34 @@ def test_galerkin_tensors_structure():
         assert np.allclose(np.sort(np.linalg.eigvalsh(G)), roots, atol=1e-12)
 
 
-def test_finite_chaos_table_row_p0():
-    """Row p_xi = 0 of Table tab:finite-errors-rates follows in closed form from the index set.
-
-    E_full^2 = E_mean^2 + ||phi||^2 sum_{alpha != 0, |alpha| <= q} c_alpha^2 with ||phi||^2 = 1/9,
-    and the variance error is ||phi^2|| sum_{alpha != 0} c_alpha^2 with ||phi^2||^2 = (1/17)(3/4)^2.
-    """
+def test_finite_chaos_table_row_p0_truncation_and_variance():
+    """Row p_xi = 0 of Table tab:finite-errors-rates, the parts the discrete solve does not enter: the
+    oracle's own error routine, run on a small mesh, gives (i) the variance error, which at p_xi = 0 is
+    ||phi^2|| sum_{alpha != 0} c_alpha^2 (no nonzero mode is computed), and (ii) E_full^2 - E_mean^2, the
+    truncation part ||phi||^2 sum_{alpha != 0, |alpha| <= q} c_alpha^2 (eq. finite-truncation-error-L2);
+    both must equal the printed row (E_full^2 - E_mean^2 formed from the printed columns) to the printed
+    digits."""
+    import sg_inputs
+    from oracle import finitechaos as fc
     g = {k: float(v) for k, v in _read_golden("finite_chaos_p0.txt")}
-    s = chaos.total_degree_set(int(g["M"]), int(g["q"]))
-    csum = sum(g["eta"] ** (2 * sum(a)) for a in s if sum(a) > 0)
-    e_full = math.sqrt(g["E_mean_L2"] ** 2 + csum / 9.0)
-    e_var = math.sqrt((1.0 / 17.0) * 0.75 ** 2) * csum
-    assert f"{e_full:.5e}" == f"{g['E_full_L2']:.5e}"
-    assert f"{e_var:.5e}" == f"{g['E_var_L2']:.5e}"
+    e = fc.run(sg_inputs.finite_chaos_workload(4, 3, 3, 8, 0, 1))
+    assert e["E_var_L2"] == pytest.approx(g["E_var_L2"], rel=5e-6)
+    trunc = e["E_full_L2"] ** 2 - e["E_mean_L2"] ** 2
+    assert trunc == pytest.approx(g["E_full_L2"] ** 2 - g["E_mean_L2"] ** 2, rel=2e-5)
+
+
+@pytest.mark.xfail(strict=True, reason="the printed p_xi = 0 mean error (8.62293e-3) is not reproduced by the "
+                   "definitions of Section 3.2 as written (the oracle gives 5.33e-2 at every resolution) nor by "
+                   "any other reading tried; the readings and their values are listed in the design notes")
+def test_finite_chaos_table_row_p0_mean_error():
+    """The printed mean error of row p_xi = 0, computed by the oracle itself (the p_xi = 0 solution is
+    the mean-coefficient problem with the projected forcing; truncation-dominated, so a small mesh
+    suffices)."""
+    import sg_inputs
+    from oracle import finitechaos as fc
+    g = {k: float(v) for k, v in _read_golden("finite_chaos_p0.txt")}
+    e = fc.run(sg_inputs.finite_chaos_workload(4, 3, 3, 8, 0, 1))
+    assert e["E_mean_L2"] == pytest.approx(g["E_mean_L2"], rel=0.05)
 
 
 # ------------------------------------------------------------------------------------------------
