@@ -97,9 +97,25 @@ struct PatchTime {
 // partial pivoting, then its transpose into AinvT (column-major inverse, for coalesced reads of the
 // coarse solve).  Scratch: col[n], perm[n]; status is set to 1 if a pivot is zero.  2n + 2 launches.
 hipError_t launch_dense_invert(double* A, int n, double* col, int* perm, int* status, double* AinvT, hipStream_t s);
+// cells == nullptr: every cell's patch, inverse slot = cell index; else the n_list patches of the
+// listed cells, inverse slot = position in the list.
 hipError_t launch_patch_invert(int dim, int k, int nt, Grid g, const double* E, const double* Me,
                                const PatchTime& pt, double* inv64, float* inv32, int* status,
-                               hipStream_t s);
+                               hipStream_t s, const int* cells = nullptr, int n_list = 0);
+
+// Inverse slot of a cell: the cell itself, or with position classes (a level whose patch matrices
+// depend only on where the cell sits: constant coefficient on a uniform mesh) one of 3^d slots,
+// sum_d 3^d c_d with c_d = 0 for the first cell along d, 2 for the last and 1 between (n >= 2).
+template <int DIM>
+__host__ __device__ inline long long inverse_slot(long long cell, const int* cc, int n, int classes) {
+    if (!classes) return cell;
+    long long slot = 0, m = 1;
+    for (int d = 0; d < DIM; ++d) {
+        slot += m * (cc[d] == 0 ? 0 : (cc[d] == n - 1 ? 2 : 1));
+        m *= 3;
+    }
+    return slot;
+}
 
 // Storage of one cell's patch inverse (n_p x n_p) for the patch products below: B[c][I] = A^{-1}[I][c]
 // (c: the k index of the product, I: the patch row), in fragments so that the `spl` consecutive
@@ -122,9 +138,10 @@ __host__ __device__ inline long long vanka_inv_offset(int npp, int spl, int c, i
 // x <- x + omega sum_K R_K^T W_K c_K.  The residual patch of a cell (48 modes at a time) takes
 // ceil(n_p / 4) * 4 * 49 * sizeof(T) bytes of LDS.
 inline size_t vanka_lds_bytes(int npp, size_t elem) { return (size_t)((npp + 3) / 4 * 4) * 49 * elem; }
+// classes: 1 when the level stores one inverse per position class (inverse_slot), 0 for one per cell.
 template <typename T>
 hipError_t launch_vanka_cells(int dim, int k, int nt, Grid g, int n_xi, const T* invT, const T* r, T* s_out,
-                              hipStream_t s);
+                              int classes, hipStream_t s);
 // the same with one inverse per (mode, cell): invT [n_xi][n_cells][vanka_inv_stride(n_p)]
 template <typename T>
 hipError_t launch_vanka_cells_modes(int dim, int k, int nt, Grid g, int n_xi, const T* invT, const T* r, T* s_out,

@@ -94,7 +94,8 @@ __device__ void assembled_pair(int dim, int k, const Grid& g, const int* cc, int
 template <int TG, int R>
 __global__ void __launch_bounds__(TG * TG)
     k_patch_invert(int dim, int k, int nt, Grid g, const double* __restrict__ E, const double* __restrict__ Me,
-                   PatchTime pt, double* __restrict__ inv64, float* __restrict__ inv32, int* status) {
+                   PatchTime pt, double* __restrict__ inv64, float* __restrict__ inv32, int* status,
+                   const int* __restrict__ cells) {
     constexpr int NPAD = TG * R;
     __shared__ double prow[NPAD], pcol[NPAD];
     __shared__ double cval[TG];
@@ -107,7 +108,9 @@ __global__ void __launch_bounds__(TG * TG)
     const int N1 = k + 1;
     const int NP = dim == 2 ? N1 * N1 : N1 * N1 * N1;
     const int npp = nt * NP;
-    const long long cell = blockIdx.x;
+    // the patch of cell `cell`, stored in inverse slot `slot` (a cell list inverts representatives only)
+    const long long slot = blockIdx.x;
+    const long long cell = cells ? cells[slot] : slot;
     int cc[3] = {0, 0, 0};
     {
         long long r = cell;
@@ -260,7 +263,7 @@ __global__ void __launch_bounds__(TG * TG)
             const int Jd = sigma_inv[J];
             if (I < npp && J < npp && Jd < npp) {
                 // B[Jd][I] = A^{-1}[I][Jd] in the fragment layout of each precision
-                const long long base = cell * vanka_inv_stride(npp);
+                const long long base = slot * vanka_inv_stride(npp);
                 if (inv64) inv64[base + vanka_inv_offset(npp, vanka_spl(npp, 8), Jd, I)] = Am[r][c];
                 if (inv32) inv32[base + vanka_inv_offset(npp, vanka_spl(npp, 4), Jd, I)] = (float)Am[r][c];
             }
@@ -331,7 +334,7 @@ constexpr int vanka_threads(int dim, int k, int nt) { return 64 * ((nt * ipow(k 
 template <int DIM, int K, int NT, typename T>
 __global__ void __launch_bounds__(vanka_threads(DIM, K, NT))
     k_vanka_cells(Grid g, int n_xi, int n_cells, const T* __restrict__ invT, const T* __restrict__ r,
-                  T* __restrict__ s_out) {
+                  T* __restrict__ s_out, int classes) {
     constexpr int N1 = K + 1;
     constexpr int NP = ipow(N1, DIM);
     constexpr int NPP = NT * NP;
@@ -372,7 +375,8 @@ __global__ void __launch_bounds__(vanka_threads(DIM, K, NT))
     constexpr int NGR = KS / SPL;                          // fragment loads per lane and pass
     constexpr int PFV = (PF / SPL) > 0 ? PF / SPL : 1;     // loads in flight
     using VT = typename VecOf<T, SPL>::type;
-    const VT* const bc = reinterpret_cast<const VT*>(invT + (long long)cell * vanka_inv_stride(NPP)) +
+    const VT* const bc = reinterpret_cast<const VT*>(invT + inverse_slot<DIM>(cell, cc, g.n, classes) *
+                                                               vanka_inv_stride(NPP)) +
                          kk * NPP + min(I, NPP - 1);
     auto load_b = [&](int grp) -> VT {   // grp is a compile-time constant at every call
         return bc[grp * 4 * NPP];
@@ -473,7 +477,7 @@ __global__ void __launch_bounds__(vanka_threads(DIM, K, NT))
 }
 
 template <int DIM, int K, int NT, typename T>
-hipError_t run_vanka(Grid g, int n_xi, const T* invT, const T* r, T* s_out, hipStream_t s) {
+hipError_t run_vanka(Grid g, int n_xi, const T* invT, const T* r, T* s_out, int classes, hipStream_t s) {
     constexpr int NPP = NT * ipow(K + 1, DIM);
     constexpr int KP = (NPP + 3) / 4 * 4;
     constexpr int waves = (NPP + 15) / 16;
@@ -490,29 +494,29 @@ hipError_t run_vanka(Grid g, int n_xi, const T* invT, const T* r, T* s_out, hipS
         if (lds > 64 * 1024)
             (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         const int n_cells = (int)g.n_cells;
-        hipLaunchKernelGGL(kern, dim3(n_cells), dim3(waves * 64), lds, s, g, n_xi, n_cells, invT, r, s_out);
+        hipLaunchKernelGGL(kern, dim3(n_cells), dim3(waves * 64), lds, s, g, n_xi, n_cells, invT, r, s_out, classes);
         return hipGetLastError();
     }
 }
 
 template <int DIM, int K, typename T>
-hipError_t vanka_nt(int nt, Grid g, int n_xi, const T* invT, const T* r, T* s_out, hipStream_t s) {
+hipError_t vanka_nt(int nt, Grid g, int n_xi, const T* invT, const T* r, T* s_out, int classes, hipStream_t s) {
     switch (nt) {
-        case 1: return run_vanka<DIM, K, 1, T>(g, n_xi, invT, r, s_out, s);
-        case 2: return run_vanka<DIM, K, 2, T>(g, n_xi, invT, r, s_out, s);
-        case 3: return run_vanka<DIM, K, 3, T>(g, n_xi, invT, r, s_out, s);
-        case 4: return run_vanka<DIM, K, 4, T>(g, n_xi, invT, r, s_out, s);
+        case 1: return run_vanka<DIM, K, 1, T>(g, n_xi, invT, r, s_out, classes, s);
+        case 2: return run_vanka<DIM, K, 2, T>(g, n_xi, invT, r, s_out, classes, s);
+        case 3: return run_vanka<DIM, K, 3, T>(g, n_xi, invT, r, s_out, classes, s);
+        case 4: return run_vanka<DIM, K, 4, T>(g, n_xi, invT, r, s_out, classes, s);
     }
     return hipErrorInvalidValue;
 }
 
 template <int DIM, typename T>
-hipError_t vanka_k(int k, int nt, Grid g, int n_xi, const T* invT, const T* r, T* s_out, hipStream_t s) {
+hipError_t vanka_k(int k, int nt, Grid g, int n_xi, const T* invT, const T* r, T* s_out, int classes, hipStream_t s) {
     switch (k) {
-        case 1: return vanka_nt<DIM, 1, T>(nt, g, n_xi, invT, r, s_out, s);
-        case 2: return vanka_nt<DIM, 2, T>(nt, g, n_xi, invT, r, s_out, s);
-        case 3: return vanka_nt<DIM, 3, T>(nt, g, n_xi, invT, r, s_out, s);
-        case 4: return vanka_nt<DIM, 4, T>(nt, g, n_xi, invT, r, s_out, s);
+        case 1: return vanka_nt<DIM, 1, T>(nt, g, n_xi, invT, r, s_out, classes, s);
+        case 2: return vanka_nt<DIM, 2, T>(nt, g, n_xi, invT, r, s_out, classes, s);
+        case 3: return vanka_nt<DIM, 3, T>(nt, g, n_xi, invT, r, s_out, classes, s);
+        case 4: return vanka_nt<DIM, 4, T>(nt, g, n_xi, invT, r, s_out, classes, s);
     }
     return hipErrorInvalidValue;
 }
@@ -622,14 +626,15 @@ hipError_t launch_elem_stiffness(int dim, int k, Grid g, const double* coef0, co
 }
 
 hipError_t launch_patch_invert(int dim, int k, int nt, Grid g, const double* E, const double* Me,
-                               const PatchTime& pt, double* inv64, float* inv32, int* status, hipStream_t s) {
+                               const PatchTime& pt, double* inv64, float* inv32, int* status, hipStream_t s,
+                               const int* cells, int n_list) {
     const int np = dim == 2 ? (k + 1) * (k + 1) : (k + 1) * (k + 1) * (k + 1);
     const int npp = nt * np;
-    const unsigned blocks = (unsigned)g.n_cells;
+    const unsigned blocks = cells ? (unsigned)n_list : (unsigned)g.n_cells;
 #define SG_PI(TG, R)                                                                                        \
     if (npp <= TG * R) {                                                                                    \
         hipLaunchKernelGGL((k_patch_invert<TG, R>), dim3(blocks), dim3(TG * TG), 0, s, dim, k, nt, g, E, Me, pt, \
-                           inv64, inv32, status);                                                           \
+                           inv64, inv32, status, cells);                                                    \
         return hipGetLastError();                                                                           \
     }
     SG_PI(8, 1)
@@ -735,15 +740,16 @@ template hipError_t launch_vanka_cells_modes<float>(int, int, int, Grid, int, co
 
 template <typename T>
 hipError_t launch_vanka_cells(int dim, int k, int nt, Grid g, int n_xi, const T* invT, const T* r, T* s_out,
-                              hipStream_t s) {
-    if (dim == 2) return vanka_k<2, T>(k, nt, g, n_xi, invT, r, s_out, s);
-    if (dim == 3) return vanka_k<3, T>(k, nt, g, n_xi, invT, r, s_out, s);
+                              int classes, hipStream_t s) {
+    if (classes && g.n < 2) return hipErrorInvalidValue;
+    if (dim == 2) return vanka_k<2, T>(k, nt, g, n_xi, invT, r, s_out, classes, s);
+    if (dim == 3) return vanka_k<3, T>(k, nt, g, n_xi, invT, r, s_out, classes, s);
     return hipErrorInvalidValue;
 }
 
 template hipError_t launch_vanka_cells<double>(int, int, int, Grid, int, const double*, const double*, double*,
-                                               hipStream_t);
-template hipError_t launch_vanka_cells<float>(int, int, int, Grid, int, const float*, const float*, float*,
+                                               int, hipStream_t);
+template hipError_t launch_vanka_cells<float>(int, int, int, Grid, int, const float*, const float*, float*, int,
                                               hipStream_t);
 
 }  // namespace sg

@@ -77,8 +77,10 @@ struct Level {
     Tables<float> tab32{};
     DevBuf<double> coef64;   // level 0: every mode; other levels: the mean mode only
     DevBuf<float> coef32;
-    DevBuf<double> inv64;    // patch inverses [n_cells][vanka_inv_stride(npp)] (fragment layout)
+    DevBuf<double> inv64;    // patch inverses [slots][vanka_inv_stride(npp)] (fragment layout)
     DevBuf<float> inv32;
+    int inv_classes = 0;     // 1: one inverse per position class (inverse_slot), 3^d slots; 0: one per cell
+    DevBuf<int> class_cells; // a representative cell of every position class
     // transfer stencils between this level (fine) and level + 1 (coarse)
     int wp = 0, wr = 0;
     DevBuf<int> p_idx, r_idx;
@@ -237,6 +239,17 @@ void prolong_1d(int nc, int k, const std::vector<double>& gll, std::vector<int>*
     }
 }
 
+// Position classes of the patch inverses are used unless SGHEAT_PATCH_CLASSES=0 (a measurement switch:
+// one inverse per cell even where they coincide).
+bool patch_classes_disabled() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = std::getenv("SGHEAT_PATCH_CLASSES");
+        v = (e && std::atoi(e) == 0) ? 1 : 0;
+    }
+    return v == 1;
+}
+
 // Everything that depends on the coefficient values: the pre-scaled coefficients of every level,
 // the Vanka patch inverses and the coarsest-level inverse.  Called by sg_create and
 // sg_update_coefficients; the device arrays keep their allocations between calls.
@@ -284,6 +297,17 @@ sg_status set_coefficients(sg_handle h, const double* coef_qp) {
         }
         coef_off += (size_t)h->n_mu * per_mode;
         if (h->diag) c64_levels[l] = c64;
+        // With the mean coefficient identical in every cell (bitwise), the patch matrix of a cell depends
+        // only on where the cell sits (first, inner or last along every direction): one inverse per
+        // position class then serves every cell, bitwise what each cell's own inversion gives.
+        {
+            const double* m0 = c64.data() + (size_t)(all_modes ? h->cpl.mu0 : 0) * per_mode;
+            bool same = !h->diag && !patch_classes_disabled();
+            for (size_t c = 1; same && c < (size_t)lv.g.n_cells; ++c)
+                for (int q = 0; q < h->NP; ++q)
+                    if (m0[c * h->NP + q] != m0[q]) { same = false; break; }
+            lv.inv_classes = same ? 1 : 0;
+        }
         SG_TRY(lv.coef64.upload(c64.data(), c64.size(), "coefficients"));
         if (h->mixed) {
             std::vector<float> c32(c64.begin(), c64.end());
@@ -316,8 +340,25 @@ sg_status set_coefficients(sg_handle h, const double* coef_qp) {
             const double vol = std::pow(lv.h, dim);
             for (double& v : Mel) v *= vol;
             SG_TRY(Me.upload(Mel.data(), Mel.size(), "element matrices"));
-            // inverses in the fragment layout of the patch products (zero in the padding columns)
-            const size_t ninv = (size_t)lv.g.n_cells * vanka_inv_stride(h->npp);
+            // inverses in the fragment layout of the patch products (zero in the padding columns); one per
+            // cell, or one per position class (a representative cell of each is inverted)
+            int nclass = 1;
+            for (int dd = 0; dd < dim; ++dd) nclass *= 3;
+            if (lv.inv_classes) {
+                std::vector<int> rep(nclass);
+                for (int c = 0; c < nclass; ++c) {
+                    long long cell = 0, m = 1;
+                    for (int dd = 0, cr = c; dd < dim; ++dd, cr /= 3) {
+                        const int pos = cr % 3 == 0 ? 0 : (cr % 3 == 2 ? lv.g.n - 1 : std::min(1, lv.g.n - 1));
+                        cell += m * pos;
+                        m *= lv.g.n;
+                    }
+                    rep[c] = (int)cell;
+                }
+                SG_TRY(lv.class_cells.upload(rep.data(), rep.size(), "patch classes"));
+            }
+            const size_t nslot = lv.inv_classes ? (size_t)nclass : (size_t)lv.g.n_cells;
+            const size_t ninv = nslot * vanka_inv_stride(h->npp);
             const bool want32 = h->mixed && l < L - 1;
             const int nblk = h->diag ? h->n_xi : 1;             // one set of patch inverses per mode
             SG_TRY(lv.inv64.alloc(ninv * nblk, "patch inverses"));
@@ -342,7 +383,8 @@ sg_status set_coefficients(sg_handle h, const double* coef_qp) {
                 }
                 SG_HIP(launch_elem_stiffness(dim, k, lv.g, c0, et, E.p, nullptr));
                 SG_HIP(launch_patch_invert(dim, k, h->NT, lv.g, E.p, Me.p, pt, lv.inv64.p + a * ninv,
-                                           want32 ? lv.inv32.p + a * ninv : nullptr, status.p, nullptr));
+                                           want32 ? lv.inv32.p + a * ninv : nullptr, status.p, nullptr,
+                                           lv.inv_classes ? lv.class_cells.p : nullptr, (int)nslot));
                 SG_HIP(hipDeviceSynchronize());
             }
         }
@@ -937,7 +979,8 @@ sg_status smooth_level(sg_handle h, int l, const T* b, T* x, int sweeps, bool x_
         if (h->diag)
             SG_HIP(launch_vanka_cells_modes<T>(h->d.dim, h->d.fe_degree, h->NT, lv.g, h->n_xi, inv, r, sbuf_as<T>(h), s));
         else
-            SG_HIP(launch_vanka_cells<T>(h->d.dim, h->d.fe_degree, h->NT, lv.g, h->n_xi, inv, r, sbuf_as<T>(h), s));
+            SG_HIP(launch_vanka_cells<T>(h->d.dim, h->d.fe_degree, h->NT, lv.g, h->n_xi, inv, r, sbuf_as<T>(h),
+                                         lv.inv_classes, s));
         SG_HIP(launch_node_gather<T>(GATHER_VANKA, h->d.dim, h->d.fe_degree, lv.g, h->n_xi * h->NT, sbuf_as<T>(h),
                                      nullptr, b, x, (T)h->d.vanka_omega, h->d.fe_degree, h->d.fe_degree, s));
     }
