@@ -315,6 +315,18 @@ sg_status sg_moment_errors(sg_handle h, const double* acc, long long n_tot, int 
                            const double* theta, const double* mean_targets, const double* var_targets, double* out,
                            void* hip_stream);
 
+/* Run the lower part of every V-cycle (the levels from the first one of at most 512 cells below the
+ * finest, down to the coarsest: pre-smoothing, residuals, restrictions, the coarsest solve,
+ * prolongations, post-smoothing) as one persistent launch with one workgroup per stochastic mode
+ * (enable = 1), or kernel by kernel (enable = 0, the default; sg_autotune times both and keeps the
+ * faster).  Both compute the block-Jacobi cycle of Remark solver-matrix-free-sg with the mean block;
+ * they differ only in rounding order.  Drops a captured V-cycle graph and synchronises the device.
+ * enable = -1 changes nothing (a query).  first_level (host pointer, may be NULL) receives the first
+ * level the segment covers (for enable = -1: -1 while the cycle runs kernel by kernel); -1 when the
+ * hierarchy has no such levels or uses one diagonal block per mode (then every setting runs kernel by
+ * kernel). */
+sg_status sg_set_vcycle_segment(sg_handle h, int enable, int* first_level);
+
 /* Replay the V-cycle (gmg_vcycle, and the preconditioner inside fgmres_solve_slab) from a HIP graph
  * (enable = 1) or launch it kernel by kernel (0, the default).  With the graph, each V-cycle copies r
  * into the handle's level-0 work vector, replays the captured cycle and copies the result to z; the
@@ -331,8 +343,10 @@ sg_status sg_set_vcycle_graph(sg_handle h, int enable);
  * and 160 KB of LDS per workgroup) on this handle's own sizes and keeps the fastest (median) for all
  * later calls.  Without it the number comes from the runtime occupancy calculator.  The
  * SGHEAT_APPLY_CPB environment variable, if set, overrides both.  cpb_out (may be NULL) receives
- * [2 (FP64, FP32)][2 (mean, full)][n_levels] choices (0 = not tuned).  Synchronous; uses the handle's
- * level work vectors, so no other call on the handle may run meanwhile. */
+ * [2 (FP64, FP32)][2 (mean, full)][n_levels] choices (0 = not tuned).  Where the hierarchy has a coarse
+ * segment (sg_set_vcycle_segment), it then times `reps` V-cycles with the segment as one launch and
+ * kernel by kernel and keeps the faster.  Synchronous; uses the handle's level work vectors, so no
+ * other call on the handle may run meanwhile. */
 sg_status sg_autotune(sg_handle h, int reps, int* cpb_out, void* hip_stream);
 
 /* Message for the last non-OK status returned on the calling thread ("" if none). */

@@ -147,6 +147,51 @@ template <typename T>
 hipError_t launch_vanka_cells_modes(int dim, int k, int nt, Grid g, int n_xi, const T* invT, const T* r, T* s_out,
                                     hipStream_t s);
 
+// ---- the coarse segment of the V-cycle in one launch ----------------------------------------------------
+// Levels l0 .. l0 + nlev - 1 (the last is the coarsest) of the block-Jacobi cycle with the mean block, one
+// workgroup per stochastic mode (kernels_segment.hip).  Vectors are the levels' [n_xi][N_t][n_nodes]
+// buffers (b of the first level is the segment's right-hand side, x of the first level its result);
+// every pointer is a device pointer of the precision T of the launch (E, Me and the coarsest inverse FP64).
+constexpr int kSegMaxLevels = 4;
+struct SegLevelArgs {
+    Grid g;
+    const void* inv;           // Vanka patch inverses (fragment layout), T
+    int classes;               // inverse per position class (inverse_slot) or per cell
+    const double* E;           // element stiffness of the mean coefficient [n_cells][(k+1)^d][(k+1)^d]
+    const double* Me;          // element mass [(k+1)^d][(k+1)^d]
+    const int* r_idx;          // restriction to the next level: banded 1D tables (T weights)
+    const void* r_w;
+    int wr;
+    const int* p_idx;          // prolongation from the next level
+    const void* p_w;
+    int wp;
+    void* b;                   // level vectors (b of the first level is only read)
+    void* x;
+    void* r;
+    int lds_b, lds_x, lds_r;   // byte offsets of the on-chip copies in LDS (-1: used in place), set at launch
+    int lds_E, lds_Me, lds_inv;  // on-chip copies of E (one cell's, when the level has position classes),
+                                 // Me and the class inverses; set at launch
+};
+struct SegArgs {
+    int dim, k, nt, np, n_xi, nlev;
+    SegLevelArgs lv[kSegMaxLevels];
+    double At[kMaxNT * kMaxNT], Bt[kMaxNT];
+    double omega;
+    int pre, post;
+    const double* coarse_invT;   // [nint][nint], column-major inverse of A_0 on the coarsest interior DoFs
+    int nint;
+    const int* coarse_dofs;      // interior DoFs of one mode on the coarsest level
+    void* scratch;               // scratch_per_mode elements of T per mode
+    long long scratch_per_mode;
+    long long tmp_len;           // one transfer temporary (elements of T)
+    int lds_G, lds_C, lds_t0, lds_t1, lds_bytes;   // LDS placement, set at launch
+    int coarse_split;            // partial sums per coarsest row, set at launch
+};
+long long segment_scratch_per_mode(int nt, int np, long long cells0, long long tmp_len);
+
+template <typename T>
+hipError_t launch_vcycle_segment(const SegArgs& a, hipStream_t s);
+
 // ---- transfers ---------------------------------------------------------------------------------------
 // One 1D pass along `dir`: out[c][.., o, ..] (+)= sum_w tw[o*width + w] in[c][.., tidx[o*width + w], ..]
 template <typename T>

@@ -81,6 +81,8 @@ struct Level {
     DevBuf<float> inv32;
     int inv_classes = 0;     // 1: one inverse per position class (inverse_slot), 3^d slots; 0: one per cell
     DevBuf<int> class_cells; // a representative cell of every position class
+    DevBuf<double> E64;      // levels of the coarse segment: element stiffness of the mean coefficient
+    DevBuf<double> Me64;     // and the element mass
     // transfer stencils between this level (fine) and level + 1 (coarse)
     int wp = 0, wr = 0;
     DevBuf<int> p_idx, r_idx;
@@ -145,6 +147,8 @@ struct sg_handle_s {
     int tuned_cpb[2][2][16] = {};                // apply cells per workgroup from sg_autotune: [FP32][full][level]
     // V-cycle replayed from a HIP graph (sg_set_vcycle_graph): captured on the level-0 work vectors
     bool graph_on = false;
+    int seg_level = -1;          // first level of the coarse segment run as one launch (-1: none)
+    bool seg_on = false;
     int graph_calls = 0;
     hipGraph_t vgraph = nullptr;
     hipGraphExec_t vgraph_exec = nullptr;
@@ -382,6 +386,13 @@ sg_status set_coefficients(sg_handle h, const double* coef_qp) {
                     c0 = h->acomb.p;
                 }
                 SG_HIP(launch_elem_stiffness(dim, k, lv.g, c0, et, E.p, nullptr));
+                if (h->seg_level >= 0 && l >= h->seg_level) {
+                    // the coarse segment applies A_0 from the element matrices of these levels
+                    const size_t ne = (size_t)lv.g.n_cells * h->NP * h->NP;
+                    SG_TRY(lv.E64.alloc(ne, "segment element matrices"));
+                    SG_HIP(hipMemcpy(lv.E64.p, E.p, ne * sizeof(double), hipMemcpyDeviceToDevice));
+                    SG_TRY(lv.Me64.upload(Mel.data(), Mel.size(), "segment element matrices"));
+                }
                 SG_HIP(launch_patch_invert(dim, k, h->NT, lv.g, E.p, Me.p, pt, lv.inv64.p + a * ninv,
                                            want32 ? lv.inv32.p + a * ninv : nullptr, status.p, nullptr,
                                            lv.inv_classes ? lv.class_cells.p : nullptr, (int)nslot));
@@ -684,6 +695,23 @@ sg_status build(sg_handle h) {
         }
 
     h->Me1 = Me1;
+    // The coarse segment (levels from the first one of at most 512 cells, below the finest, down to the
+    // coarsest) runs as one launch when its per-mode scratch fits the cell-local buffer.
+    h->seg_level = -1;
+    if (!h->diag) {
+        for (int l = 1; l + 1 < L; ++l) {
+            if (h->lv[l].g.n_cells > 512) continue;
+            if (L - l > kSegMaxLevels) break;
+            const long long nf = h->lv[l].g.n1, nc = h->lv[l + 1].g.n1;
+            const long long tmp = (long long)h->NT * (dim == 3 ? nf * nf * nc : nf * nc);
+            const long long need = (long long)h->n_xi * segment_scratch_per_mode(h->NT, h->NP, h->lv[l].g.n_cells, tmp);
+            const long long have = (long long)h->n_xi * h->NT * h->lv[0].g.n_cells * h->NP;   // doubles
+            if (need <= have) h->seg_level = l;
+            break;
+        }
+    }
+    // kernel by kernel until sg_set_vcycle_segment or sg_autotune (which times both) says otherwise
+    h->seg_on = false;
     SG_TRY(set_coefficients(h, d.coef_qp));
 
     // transfer stencils and temporaries
@@ -872,6 +900,8 @@ T* sbuf_as(sg_handle h) {
     return reinterpret_cast<T*>(h->sbuf.p);
 }
 
+sg_status vcycle_fixed(sg_handle h, hipStream_t s);
+
 // Time the operator (cell kernel + gather) for every feasible cells-per-workgroup value on one level
 // and keep the fastest (median of `reps` event-timed launches each).
 template <typename T>
@@ -917,6 +947,38 @@ sg_status autotune_apply(sg_handle h, int level, bool full, int reps, hipStream_
     }
     for (auto& e : ev) (void)hipEventDestroy(e);
     if (st == SG_OK && level < 16) h->tuned_cpb[sizeof(T) == 4][full][level] = best;
+    return st;
+}
+
+// Time `reps` V-cycles on the level-0 work vectors with the coarse segment as one launch and kernel by
+// kernel (median of each) and keep the faster.
+sg_status autotune_segment(sg_handle h, int reps, hipStream_t s) {
+    if (h->seg_level < 0) return SG_OK;
+    Level& l0 = h->lv[0];
+    if (h->mixed) SG_HIP(launch_fill<float>(l0.b32.p, 0.0f, l0.len, s));
+    else SG_HIP(launch_fill<double>(l0.b64.p, 0.0, l0.len, s));
+    std::vector<hipEvent_t> ev(reps + 1);
+    for (auto& e : ev) SG_HIP(hipEventCreate(&e));
+    float med[2] = {0.0f, 0.0f};
+    sg_status st = SG_OK;
+    for (int on = 0; on < 2 && st == SG_OK; ++on) {
+        h->seg_on = on == 1;
+        st = vcycle_fixed(h, s);
+        if (st != SG_OK) break;
+        (void)hipEventRecord(ev[0], s);
+        for (int r = 0; r < reps && st == SG_OK; ++r) {
+            st = vcycle_fixed(h, s);
+            (void)hipEventRecord(ev[r + 1], s);
+        }
+        if (st != SG_OK) break;
+        if (hipEventSynchronize(ev[reps]) != hipSuccess) { st = fail(SG_EHIP, "autotune: event"); break; }
+        std::vector<float> t(reps);
+        for (int r = 0; r < reps; ++r) (void)hipEventElapsedTime(&t[r], ev[r], ev[r + 1]);
+        std::nth_element(t.begin(), t.begin() + reps / 2, t.end());
+        med[on] = t[reps / 2];
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (st == SG_OK) h->seg_on = med[1] < med[0];
     return st;
 }
 
@@ -1035,10 +1097,61 @@ sg_status prolong_add(sg_handle h, int l, const T* xc, T* xf, hipStream_t s) {
     return SG_OK;
 }
 
+// Levels l .. L-1 of the cycle in one launch (kernels_segment.hip): one workgroup per mode.
+template <typename T>
+sg_status vcycle_segment(sg_handle h, int l0, const T* b, T* x, hipStream_t s) {
+    const int L = h->d.n_levels;
+    SegArgs a{};
+    a.dim = h->d.dim;
+    a.k = h->d.fe_degree;
+    a.nt = h->NT;
+    a.np = h->NP;
+    a.n_xi = h->n_xi;
+    a.nlev = L - l0;
+    long long tmp = 0;
+    for (int i = 0; i < a.nlev; ++i) {
+        Level& lv = h->lv[l0 + i];
+        SegLevelArgs& q = a.lv[i];
+        q.g = lv.g;
+        q.inv = Prec<T>::inv(lv);
+        q.classes = lv.inv_classes;
+        q.E = lv.E64.p;
+        q.Me = lv.Me64.p;
+        q.b = i == 0 ? const_cast<T*>(b) : Prec<T>::b(lv);
+        q.x = i == 0 ? x : Prec<T>::x(lv);
+        q.r = Prec<T>::r(lv);
+        if (l0 + i < L - 1) {
+            q.r_idx = lv.r_idx.p;
+            q.r_w = Prec<T>::rw(lv);
+            q.wr = lv.wr;
+            q.p_idx = lv.p_idx.p;
+            q.p_w = Prec<T>::pw(lv);
+            q.wp = lv.wp;
+            // the largest intermediate of a 1D pass between this level and the next, one mode
+            const long long nf = lv.g.n1, nc = h->lv[l0 + i + 1].g.n1;
+            tmp = std::max(tmp, (long long)h->NT * (h->d.dim == 3 ? nf * nf * nc : nf * nc));
+        }
+    }
+    for (int i = 0; i < h->NT * h->NT; ++i) a.At[i] = h->At[i];
+    for (int i = 0; i < h->NT; ++i) a.Bt[i] = h->Bt[i];
+    a.omega = h->d.vanka_omega;
+    a.pre = h->d.pre_smooth;
+    a.post = h->d.post_smooth;
+    a.coarse_invT = h->coarse_invT.p;
+    a.nint = h->nint;
+    a.coarse_dofs = h->coarse_dofs.p;
+    a.tmp_len = tmp;
+    a.scratch_per_mode = segment_scratch_per_mode(h->NT, h->NP, h->lv[l0].g.n_cells, tmp);
+    a.scratch = h->sbuf.p;
+    SG_HIP(launch_vcycle_segment<T>(a, s));
+    return SG_OK;
+}
+
 template <typename T>
 sg_status vcycle_level(sg_handle h, int l, const T* b, T* x, hipStream_t s) {
     const int L = h->d.n_levels;
     Level& lv = h->lv[l];
+    if (h->seg_on && l == h->seg_level) return vcycle_segment<T>(h, l, b, x, s);
     if (l == L - 1) {
         SG_HIP(launch_coarse_solve<T>(h->coarse_invT.p, h->diag ? (long long)h->nint * h->nint : 0, h->nint,
                                       h->coarse_dofs.p, h->n_xi, (long long)h->NT * lv.g.n_nodes,
@@ -1769,6 +1882,16 @@ sg_status sg_moment_errors(sg_handle h, const double* acc, long long n_tot, int 
     return SG_OK;
 }
 
+sg_status sg_set_vcycle_segment(sg_handle h, int enable, int* first_level) {
+    if (!h || enable < -1 || enable > 1) return fail(SG_EINVAL, "bad argument");
+    if (first_level) *first_level = enable == -1 && !h->seg_on ? -1 : h->seg_level;
+    if (enable == -1) return SG_OK;
+    (void)hipDeviceSynchronize();
+    h->drop_graph();                           // a captured V-cycle holds the other path
+    h->seg_on = enable == 1;
+    return SG_OK;
+}
+
 sg_status sg_set_vcycle_graph(sg_handle h, int enable) {
     if (!h || (enable != 0 && enable != 1)) return fail(SG_EINVAL, "bad argument");
     if (!enable) {
@@ -1790,6 +1913,7 @@ sg_status sg_autotune(sg_handle h, int reps, int* cpb_out, void* hip_stream) {
     for (int l = 0; l < L; ++l) SG_TRY(autotune_apply<double>(h, l, false, reps, s));
     if (h->mixed)
         for (int l = 0; l < L; ++l) SG_TRY(autotune_apply<float>(h, l, false, reps, s));
+    SG_TRY(autotune_segment(h, reps, s));
     if (cpb_out)
         for (int p = 0; p < 2; ++p)
             for (int f = 0; f < 2; ++f)

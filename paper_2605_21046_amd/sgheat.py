@@ -22,7 +22,7 @@ EXPORTS = ["sg_create", "sg_destroy", "sg_vector_length", "sg_operator_apply", "
            "gmg_vcycle", "fgmres_solve_slab", "sg_quadrature_points", "sg_node_coordinates", "sg_update_coefficients", "sg_operator_apply_T",
            "sg_slab_transfer", "sg_stiffness_form_cells", "sg_qoi_mean_var", "sg_sample_statistics", "sg_chaos_moments", "sg_gauss_points", "sg_index_set", "sg_chaos_projection",
            "sg_time_rule", "sg_time_load_weights", "sg_load_vectors", "sg_separable_vector", "sg_separable_error",
-           "sg_sample_psi", "sg_sample_qp_moments", "sg_moment_errors", "sg_autotune", "sg_set_vcycle_graph", "sg_last_error"]
+           "sg_sample_psi", "sg_sample_qp_moments", "sg_moment_errors", "sg_autotune", "sg_set_vcycle_graph", "sg_set_vcycle_segment", "sg_last_error"]
 
 
 class SgError(RuntimeError):
@@ -87,6 +87,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sg_sample_psi.argtypes = [P, I, PI, PD]
     lib.sg_autotune.argtypes = [P, I, PI, V]
     lib.sg_set_vcycle_graph.argtypes = [P, I]
+    lib.sg_set_vcycle_segment.argtypes = [P, I, PI]
     lib.sg_sample_qp_moments.argtypes = [P, V, I, I, V, V]
     lib.sg_moment_errors.argtypes = [P, V, ctypes.c_longlong, I, V, I, PD, PD, PD, PD, V]
     lib.sg_last_error.restype = ctypes.c_char_p
@@ -385,17 +386,32 @@ class Problem:
                                        float(C2), _dp(out), _stream(stream)))
         return out
 
+    def set_vcycle_segment(self, enable: bool = True) -> int:
+        """Coarse levels of the V-cycle as one persistent launch or kernel by kernel (the default);
+        returns the first level the segment covers (-1: the hierarchy has none)."""
+        lvl = ctypes.c_int(-1)
+        _check(_lib.sg_set_vcycle_segment(self._h, 1 if enable else 0, ctypes.byref(lvl)))
+        return lvl.value
+
+    def vcycle_segment_level(self) -> int:
+        """First level of the coarse segment while it runs as one launch, else -1."""
+        lvl = ctypes.c_int(-1)
+        _check(_lib.sg_set_vcycle_segment(self._h, -1, ctypes.byref(lvl)))
+        return lvl.value
+
     def set_vcycle_graph(self, enable: bool = True):
         """Replay the V-cycle from a HIP graph (captured on first use) instead of launching its kernels."""
         _check(_lib.sg_set_vcycle_graph(self._h, int(bool(enable))))
 
     def autotune(self, reps: int = 20, stream=None) -> dict:
-        """Time the cell kernel's workgroup tiles on this handle and keep the fastest; returns the choices."""
+        """Time the cell kernel's workgroup tiles (and the V-cycle with and without the coarse segment)
+        on this handle and keep the fastest; returns the choices."""
         L = self.spec.n_levels
         out = np.zeros((2, 2, L), dtype=np.int32)
         _check(_lib.sg_autotune(self._h, int(reps), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _stream(stream)))
         return {"fp64_full": int(out[0, 1, 0]), "fp64_mean": out[0, 0].tolist(),
-                "fp32_mean": out[1, 0].tolist() if self.precision == SG_MIXED else None}
+                "fp32_mean": out[1, 0].tolist() if self.precision == SG_MIXED else None,
+                "segment_level": self.vcycle_segment_level()}
 
     # --- Monte-Carlo estimators at quadrature points --------------------------------------------------
     def sample_psi(self, alphas) -> np.ndarray:

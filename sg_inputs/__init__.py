@@ -86,6 +86,10 @@ WORKLOADS = {
     # small meshes whose cell counts per direction are not multiples of the apply's tile widths
     "t3c2": Workload("t3c2", 3, 10, 2, 1, 1.0 / 10, 4, 3, 2, "sine"),
     "t3c3": Workload("t3c3", 3, 5, 3, 2, 1.0 / 5, 3, 4, 1, "sine"),
+    # three-level hierarchies whose lower two levels form one persistent coarse segment
+    "t2s3": Workload("t2s3", 2, 8, 3, 2, 0.02, 3, 2, 3, "sine"),
+    "t3s2": Workload("t3s2", 3, 4, 2, 1, 0.05, 2, 2, 3, "sine"),
+    "t2v2": Workload("t2v2", 2, 8, 2, 1, 0.02, 2, 2, 3, "vmean"),
 }
 
 
@@ -105,6 +109,7 @@ def coefficient_modes(w: Workload, x: np.ndarray):
     Returns ``(mu_list, values)`` with ``values[k]`` = a_{mu_k}(x).  The first mode is mu = 0.
     * "c1":   a = 1 + 0.1 xi_1 sin(pi x) sin(pi y) + 0.05 xi_2 sin(2 pi x) sin(pi y)
     * "sine": a = 1 + sum_m (0.1 / m^2) xi_m phi_m(x)
+    * "vmean": a = 1 + 0.5 x y + sum_m (0.1 / m^2) xi_m phi_m(x) (a mean that varies between cells)
     * "finite": the non-affine coefficient of the finite-chaos benchmark (M = 4, d = 2), see
       finite_chaos_coefficient_modes.
     """
@@ -113,7 +118,7 @@ def coefficient_modes(w: Workload, x: np.ndarray):
     if w.field == "finite":
         return finite_chaos_coefficient_modes(x)
     mus = [tuple([0] * M)]
-    vals = [np.ones(x.shape[:-1])]
+    vals = [np.ones(x.shape[:-1]) + (0.5 * x[..., 0] * x[..., 1] if w.field == "vmean" else 0.0)]
     for m in range(1, M + 1):
         e = [0] * M
         e[m - 1] = 1
@@ -125,7 +130,7 @@ def coefficient_modes(w: Workload, x: np.ndarray):
                 v = 0.05 * np.sin(2 * math.pi * x[..., 0]) * np.sin(math.pi * x[..., 1])
             else:
                 v = np.zeros(x.shape[:-1])
-        elif w.field == "sine":
+        elif w.field in ("sine", "vmean"):
             v = (0.1 / m ** 2) * _sine_shape(m, x)
         else:
             raise ValueError(f"unknown field {w.field}")

@@ -115,7 +115,7 @@ def test_vanka_matches_oracle(torch_cuda, name):
         assert _rel_inf(xg.cpu().numpy(), ref) <= 1e-11, level
 
 
-@pytest.mark.parametrize("name", ["c1", "t2q2", "t2q3", "t2q4", "t3q1", "t3q2", "t2q2p4", "t3c2"])
+@pytest.mark.parametrize("name", ["c1", "t2q2", "t2q3", "t2q4", "t3q1", "t3q2", "t2q2p4", "t3c2", "t2s3", "t3s2"])
 def test_vcycle_matches_oracle(torch_cuda, name):
     torch = torch_cuda
     w = sg_inputs.WORKLOADS[name]
@@ -274,6 +274,7 @@ def test_autotuned_tiles_keep_results_bitwise(torch_cuda, name):
     chosen = G.autotune(reps=3)
     print(name, chosen, flush=True)
     assert chosen["fp64_full"] in (1, 2, 3, 4, 5, 6, 8, 10, 12, 16)
+    assert chosen["segment_level"] in ((-1, 1) if w.n_levels == 3 else (-1,))
     y1 = G.apply(x)
     assert torch.equal(y0, y1)
     P = from_workload(w)
@@ -283,15 +284,19 @@ def test_autotuned_tiles_keep_results_bitwise(torch_cuda, name):
     assert info["converged"]
 
 
-@pytest.mark.parametrize("name,precision", [("c1", 0), ("t3q2", 1), ("t2q3", 0)])
-def test_vcycle_graph_replays_match_the_kernel_by_kernel_cycle(torch_cuda, name, precision):
+@pytest.mark.parametrize("name,precision,segment", [("c1", 0, False), ("t3q2", 1, False), ("t2q3", 0, False),
+                                                    ("t2s3", 0, True), ("t3s2", 1, True)])
+def test_vcycle_graph_replays_match_the_kernel_by_kernel_cycle(torch_cuda, name, precision, segment):
     """Every replay of the captured V-cycle, with eager work and synchronisations between replays,
-    equals the kernel-by-kernel cycle bit for bit; so does a whole FGMRES solve."""
+    equals the eagerly launched cycle bit for bit (also with the coarse segment as one launch); so
+    does a whole FGMRES solve."""
     torch = torch_cuda
     w = sg_inputs.WORKLOADS[name]
-    print(f"V-cycle graph {name} precision {precision}", flush=True)
+    print(f"V-cycle graph {name} precision {precision} segment {segment}", flush=True)
     G = _gpu(w, precision)
     Gg = _gpu(w, precision)
+    if segment:
+        assert G.set_vcycle_segment(True) == 1 and Gg.set_vcycle_segment(True) == 1
     Gg.set_vcycle_graph(True)
     n = G.n(0)
     for k in range(6):
@@ -309,6 +314,45 @@ def test_vcycle_graph_replays_match_the_kernel_by_kernel_cycle(torch_cuda, name,
     assert torch.equal(x0, x1)
     Gg.set_vcycle_graph(False)
     assert torch.equal(Gg.vcycle(r), G.vcycle(r))
+
+
+@pytest.mark.parametrize("name,precision", [("c1", 0), ("t2s3", 0), ("t3s2", 0), ("t2v2", 0), ("t2s3", 1), ("t3s2", 1),
+                                            ("t2v2", 1)])
+def test_vcycle_segment_matches_the_kernel_by_kernel_cycle(torch_cuda, name, precision):
+    """The lower levels of the V-cycle as one persistent launch (one workgroup per mode) and as one
+    kernel per step compute the same cycle up to rounding order: FP64 both within 1e-11 of the
+    oracle's V-cycle; FP32 preconditioner both within 2e-4 of it (single-precision rounding times
+    patch condition numbers below 1e3 here); an FGMRES solve with each reaches the tolerance.  t2v2's
+    mean coefficient varies between cells (element matrices and patch inverses per cell); the others'
+    is constant (one of each per position class, staged on chip)."""
+    torch = torch_cuda
+    w = sg_inputs.WORKLOADS[name]
+    print(f"V-cycle segment {name} precision {precision}", flush=True)
+    H = hierarchy_from_workload(w)
+    G = _gpu(w, precision)
+    assert G.vcycle_segment_level() == -1           # kernel by kernel unless asked (or autotuned)
+    assert G.set_vcycle_segment(True) == 1
+    assert G.vcycle_segment_level() == 1
+    r = sg_inputs.uniform_vector(G.n(0), 43)
+    ref = H.vcycle(r, w.n_chaos)
+    z_seg = G.vcycle(_to_gpu(torch, r)).cpu().numpy()
+    assert G.set_vcycle_segment(False) == 1
+    assert G.vcycle_segment_level() == -1
+    z_kbk = G.vcycle(_to_gpu(torch, r)).cpu().numpy()
+    e_seg, e_kbk = _rel_inf(z_seg, ref), _rel_inf(z_kbk, ref)
+    print(f"  segment {e_seg:.3e}  kernel by kernel {e_kbk:.3e}  between {_rel_inf(z_seg, z_kbk):.3e}", flush=True)
+    tol = 1e-11 if precision == 0 else 2e-4
+    assert e_seg <= tol and e_kbk <= tol
+    P = from_workload(w)
+    b = P.apply_route2(sg_inputs.interior_target(w))
+    its = []
+    for on in (True, False):
+        G.set_vcycle_segment(on)
+        x, info = G.solve(_to_gpu(torch, b), rtol=1e-9)
+        assert info["converged"] == 1
+        assert np.linalg.norm(b - P.apply_route2(x.cpu().numpy())) / np.linalg.norm(b) <= 1.0001e-9
+        its.append(info["iterations"])
+    assert abs(its[0] - its[1]) <= 1, its
 
 
 @pytest.mark.parametrize("field", ["sine", "finite"])
