@@ -236,10 +236,38 @@ def adjoint_timing(torch, name="c5", reps=2):
             "J": J, "n_params": len(th) + len(a0), "fgmres_iterations": stats}
 
 
+CYCLE_VARIANTS = (("kernels", False, False), ("graph", False, True), ("segment", True, False),
+                  ("segment_graph", True, True))
+
+
+def _cycle_variants(torch, handles, run, reps):
+    """Wall time of `run` (min over reps, after one untimed run) with the V-cycle launched kernel by
+    kernel, replayed from a HIP graph, with its coarse levels as one persistent launch, and both."""
+    out = {}
+    for label, segment, graph in CYCLE_VARIANTS:
+        for P in handles:
+            P.set_vcycle_segment(segment)
+            P.set_vcycle_graph(graph)
+        run()
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            run()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        out[label] = round(1e3 * float(np.min(times)), 1)
+    for P in handles:
+        P.set_vcycle_segment(False)
+        P.set_vcycle_graph(False)
+    return out
+
+
 def sample_batch_timing(torch, name="c4", reps=2):
     """All slabs of the Monte-Carlo batch (256 pathwise problems in one handle): wall time of the whole
     time march (right-hand sides, slab solves to 1e-8, transfers) and of the sample statistics, FP64 and
-    mixed precision; set-up excluded."""
+    mixed precision; set-up excluded.  FP64 also with the V-cycle variants (graph replay, persistent
+    coarse segment, both; march only)."""
     import sg_inputs
     from paper_2605_21046_amd import sgheat
     from paper_2605_21046_amd.montecarlo import SampleBatch
@@ -267,6 +295,8 @@ def sample_batch_timing(torch, name="c4", reps=2):
         out[f"{label}_iterations_per_slab"] = [min(its), max(its)]
         out[f"{label}_sample_slabs_per_s"] = round(sw.n_samples * sw.n_slabs / t, 1)
         out["dofs_per_slab"] = n_dofs
+        if label == "fp64":
+            out["fp64_cycle_variants_ms"] = _cycle_variants(torch, [B.P], B.run, reps)
         B.close()
     return out
 
@@ -274,7 +304,8 @@ def sample_batch_timing(torch, name="c4", reps=2):
 def member_batch_timing(torch, name="c4", reps=2):
     """All slabs of the 64 SG problems of degree 1..4 (packed into member-batch handles): wall time of
     the whole time march (slab solves to 1e-8, transfers) and of the chaos moments, FP64 and mixed;
-    set-up excluded."""
+    set-up excluded.  FP64 also with the V-cycle variants (graph replay, persistent coarse segment,
+    both; march only)."""
     import sg_inputs
     from paper_2605_21046_amd import sgheat
     from paper_2605_21046_amd.sgbatch import MemberBatch
@@ -303,6 +334,8 @@ def member_batch_timing(torch, name="c4", reps=2):
         out[f"{label}_ms"] = round(1e3 * t, 1)
         out[f"{label}_iterations_per_slab"] = [min(its), max(its)]
         out[f"{label}_problem_slabs_per_s"] = round(len(mw.degrees) * mw.n_slabs / t, 1)
+        if label == "fp64":
+            out["fp64_cycle_variants_ms"] = _cycle_variants(torch, B.handles, B.run, reps)
         B.close()
     return out
 

@@ -41,6 +41,7 @@ struct ApplyOp {
                                   // (0 = chosen from the mesh size; the z faces inside a chunk are summed
                                   // in registers, so the broken layout is chunked along z as along x)
     int* used_lz;                 // if set, receives the z chunk length of the launch
+    int level;                    // multigrid level of the operator
 };
 template <typename T>
 hipError_t launch_apply(const ApplyOp<T>& op, const T* x, T* s_out, hipStream_t s);
@@ -191,6 +192,28 @@ long long segment_scratch_per_mode(int nt, int np, long long cells0, long long t
 
 template <typename T>
 hipError_t launch_vcycle_segment(const SegArgs& a, hipStream_t s);
+
+// ---- the mean block as a Kronecker sum (constant mean coefficient) ----------------------------------
+// y = A_0 x (b == nullptr; Dirichlet rows y = x) or y = b - A_0 x (Dirichlet rows b - x) on every mode of
+// one level, A_0 = A_t (x) M + B_t (x) K_0 with M and K_0 formed from the assembled 1D mass and stiffness
+// matrices in band storage, band[i][d] = M1[i][i - k + d] (zero beyond the mesh), the stiffness band
+// already multiplied by the constant mean coefficient (kernels_stencil.hip).  Vectors [n_xi][N_t][n1^d].
+struct StencilArgs {
+    int dim, k, nt, n1, n_xi;
+    const void* Mb;          // [n1][2k+1], T
+    const void* Kb;          // [n1][2k+1], T
+    double At[kMaxNT * kMaxNT], Bt[kMaxNT];
+    const void* x;
+    const void* b;           // nullptr: y = A_0 x
+    void* y;
+    int ty, zc;              // rows per workgroup and z planes per workgroup (set at launch)
+    int mode;                // set inside the kernel
+};
+size_t stencil_lds_bytes(const StencilArgs& a, int elem);
+// Chooses the rows per workgroup; false when no tile fits (the element route applies then).
+bool stencil_fits(StencilArgs& a, int elem);
+template <typename T>
+hipError_t launch_mean_stencil(const StencilArgs& a, hipStream_t s);
 
 // ---- transfers ---------------------------------------------------------------------------------------
 // One 1D pass along `dir`: out[c][.., o, ..] (+)= sum_w tw[o*width + w] in[c][.., tidx[o*width + w], ..]

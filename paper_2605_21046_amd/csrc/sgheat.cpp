@@ -80,6 +80,9 @@ struct Level {
     DevBuf<double> inv64;    // patch inverses [slots][vanka_inv_stride(npp)] (fragment layout)
     DevBuf<float> inv32;
     int inv_classes = 0;     // 1: one inverse per position class (inverse_slot), 3^d slots; 0: one per cell
+    bool mean_const = false;                 // mean coefficient one constant: mean block as a Kronecker sum
+    DevBuf<double> mb64, kb64;               // its assembled 1D mass / stiffness bands [n1][2k+1] (K times c)
+    DevBuf<float> mb32, kb32;
     DevBuf<int> class_cells; // a representative cell of every position class
     DevBuf<double> E64;      // levels of the coarse segment: element stiffness of the mean coefficient
     DevBuf<double> Me64;     // and the element mass
@@ -160,9 +163,11 @@ struct sg_handle_s {
         vgraph = nullptr;
         graph_calls = 0;
     }
+    std::vector<hipEvent_t> ev_pool;          // timing events of the solver, created once and reused
     ~sg_handle_s() {
         drop_graph();
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     }
     std::vector<double> hstage;
     std::vector<double> trip;                 // E[Psi_a Psi_b Psi_eps], [n_xi][n_xi][n_eps]
@@ -254,6 +259,39 @@ bool patch_classes_disabled() {
     return v == 1;
 }
 
+// The mean block of a level with a constant mean coefficient is applied as a Kronecker sum of assembled
+// 1D matrices unless SGHEAT_MEAN_STENCIL=0 (a measurement switch: the element route everywhere).
+bool mean_stencil_disabled() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = std::getenv("SGHEAT_MEAN_STENCIL");
+        v = (e && std::atoi(e) == 0) ? 1 : 0;
+    }
+    return v == 1;
+}
+
+// Assembled 1D mass and stiffness matrices of Q_k on n cells of width h, in band storage
+// band[i][d] = M1[i][i - k + d] (zero beyond the mesh): the Gauss-quadrature integrals of the GLL
+// basis on every cell, summed over the cells sharing a node.
+void assemble_1d_bands(int n, int k, double h, const std::vector<double>& S, const std::vector<double>& Dn,
+                       const std::vector<double>& gw, std::vector<double>& mb, std::vector<double>& kb) {
+    const int N1 = k + 1, n1 = n * k + 1, W = 2 * k + 1;
+    mb.assign((size_t)n1 * W, 0.0);
+    kb.assign((size_t)n1 * W, 0.0);
+    for (int c = 0; c < n; ++c)
+        for (int a = 0; a < N1; ++a)
+            for (int b = 0; b < N1; ++b) {
+                double m = 0.0, st = 0.0;
+                for (int q = 0; q < N1; ++q) {
+                    m += gw[q] * S[q * N1 + a] * S[q * N1 + b];
+                    st += gw[q] * Dn[q * N1 + a] * Dn[q * N1 + b];
+                }
+                const int i = c * k + a, j = c * k + b;
+                mb[(size_t)i * W + (j - i + k)] += h * m;
+                kb[(size_t)i * W + (j - i + k)] += st / h;
+            }
+}
+
 // Everything that depends on the coefficient values: the pre-scaled coefficients of every level,
 // the Vanka patch inverses and the coarsest-level inverse.  Called by sg_create and
 // sg_update_coefficients; the device arrays keep their allocations between calls.
@@ -298,6 +336,26 @@ sg_status set_coefficients(sg_handle h, const double* coef_qp) {
                     for (int dd = 0, qq = q; dd < dim; ++dd, qq /= N1) wq *= gw[qq % N1];
                     c64[mi * per_mode + c * h->NP + q] = src[c * h->NP + q] * wq;
                 }
+        }
+        // a mean coefficient equal to one constant c at every Gauss point of the level: the mean block
+        // is the Kronecker sum of the 1D matrices (stiffness scaled by c)
+        {
+            const double* s0 = coef_qp + coef_off + (size_t)h->cpl.mu0 * per_mode;
+            bool cst = !h->diag;
+            for (size_t q = 1; cst && q < per_mode; ++q) cst = s0[q] == s0[0];
+            lv.mean_const = cst;
+            if (cst) {
+                std::vector<double> mb, kb;
+                assemble_1d_bands(lv.g.n, k, lv.h, S, Dn, gw, mb, kb);
+                for (double& v : kb) v *= s0[0];
+                SG_TRY(lv.mb64.upload(mb.data(), mb.size(), "mean-block bands"));
+                SG_TRY(lv.kb64.upload(kb.data(), kb.size(), "mean-block bands"));
+                if (h->mixed) {
+                    std::vector<float> m32(mb.begin(), mb.end()), k32(kb.begin(), kb.end());
+                    SG_TRY(lv.mb32.upload(m32.data(), m32.size(), "mean-block bands"));
+                    SG_TRY(lv.kb32.upload(k32.data(), k32.size(), "mean-block bands"));
+                }
+            }
         }
         coef_off += (size_t)h->n_mu * per_mode;
         if (h->diag) c64_levels[l] = c64;
@@ -856,6 +914,7 @@ ApplyOp<T> make_op(const sg_handle h, int level, bool full) {
         op.cw = Prec<T>::cwm(h);
     }
     op.mean = !full;
+    op.level = level;
     op.n_ent = full ? (int)h->cpl.beta.size() : h->n_xi;
     // compile-time Hermite tables describe a single total-degree problem only
     op.affine = h->cpl.affine && h->d.n_vars <= 8 && h->d.n_samples == 0 && h->d.n_members == 0;
@@ -987,6 +1046,27 @@ sg_status autotune_segment(sg_handle h, int reps, hipStream_t s) {
 template <typename T>
 sg_status op_apply(sg_handle h, const ApplyOp<T>& op, const T* x, T* y, const T* b, hipStream_t s,
                    T* cells = nullptr) {
+    if (op.mean && !h->diag && !cells && op.level >= 0 && h->lv[op.level].mean_const && !mean_stencil_disabled()) {
+        const Level& lv = h->lv[op.level];
+        StencilArgs sa{};
+        sa.dim = h->d.dim;
+        sa.k = h->d.fe_degree;
+        sa.nt = h->NT;
+        sa.n1 = lv.g.n1;
+        sa.n_xi = h->n_xi;
+        sa.Mb = sizeof(T) == 8 ? (const void*)lv.mb64.p : (const void*)lv.mb32.p;
+        sa.Kb = sizeof(T) == 8 ? (const void*)lv.kb64.p : (const void*)lv.kb32.p;
+        for (int i = 0; i < h->NT * h->NT; ++i) sa.At[i] = h->At[i];
+        for (int i = 0; i < h->NT; ++i) sa.Bt[i] = h->Bt[i];
+        sa.x = x;
+        sa.b = b;
+        sa.y = y;
+        StencilArgs probe = sa;
+        if (stencil_fits(probe, (int)sizeof(T))) {
+            SG_HIP(launch_mean_stencil<T>(sa, s));
+            return SG_OK;
+        }
+    }
     ApplyOp<T> o = op;
     int cpb = 1, lz = 1;
     o.used_cpb = &cpb;
@@ -1398,19 +1478,20 @@ sg_status fgmres_solve_slab(sg_handle h, const double* b, double* x, double rtol
     const long long n = h->N;
     const int m = h->restart;
     sg_solve_info inf{};
-    std::vector<hipEvent_t> ev;
+    // timing marks from the handle's event pool (grown on first use, reused by later solves)
+    size_t ev_used = 0;
     auto mark = [&](std::vector<hipEvent_t>& v) -> hipError_t {
-        hipEvent_t e;
-        hipError_t r = hipEventCreate(&e);
-        if (r != hipSuccess) return r;
+        if (ev_used == h->ev_pool.size()) {
+            hipEvent_t e;
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+            h->ev_pool.push_back(e);
+        }
+        hipEvent_t e = h->ev_pool[ev_used++];
         v.push_back(e);
         return hipEventRecord(e, s);
     };
     std::vector<hipEvent_t> ev_apply, ev_prec, ev_total;
-    struct EvGuard {
-        std::vector<hipEvent_t>* v[3];
-        ~EvGuard() { for (auto* p : v) for (auto e : *p) (void)hipEventDestroy(e); }
-    } guard{{&ev_apply, &ev_prec, &ev_total}};
     SG_HIP(mark(ev_total));
     const ApplyOp<double> op = make_op<double>(h, 0, true);
     double* V = h->V.p;
