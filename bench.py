@@ -43,8 +43,9 @@ APPLY_SOURCES = ["device_common.hpp", "kernels.hpp", "apply_impl.hpp", "apply_3d
 # after any change to those the entry no longer matches and the traffic is reported as null until it
 # is measured again.
 MEASURED_TRAFFIC = {
-    # profiles/sg_apply_c2_hbm_traffic.md
-    ("c2", "10b9cc6d6bca7d4a", 3): {"fetch_bytes": 645592419, "write_bytes": 545938308},
+    # profiles/sg_apply_c2_c3_hbm_traffic.md
+    ("c2", "308a06b2f18b99f3", 3): {"fetch_bytes": 646070710, "write_bytes": 547065205},
+    ("c3", "308a06b2f18b99f3", 2): {"fetch_bytes": 1240629079, "write_bytes": 1000738377},
 }
 
 
