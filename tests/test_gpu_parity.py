@@ -262,7 +262,7 @@ def test_argument_errors(torch_cuda):
         sgheat.Problem(big, [[0, 0, 0, 0]], coef1)
 
 
-@pytest.mark.parametrize("name", ["c1", "t3q2", "t2q3"])
+@pytest.mark.parametrize("name", ["c1", "t3q2", "t2q3", "t3c2", "t3c3"])
 def test_autotuned_tiles_keep_results_bitwise(torch_cuda, name):
     """Every thread computes one (cell, component) and the gather sums in a fixed order, so the tile
     chosen by the autotuner must not change a single bit of the apply."""
