@@ -32,9 +32,14 @@ namespace sg {
 
 namespace {
 
-constexpr int kStThreads = 512;
-constexpr int kStPos = 2;        // (y, x) positions per thread in the z march
-constexpr int kStOut = 2;        // output nodes per thread and plane
+// 3D: 1024 (y, x) positions and output nodes per workgroup, one per thread in workgroups of 1024 threads
+// where the z window of a position is small (FP64 with N_t (2k+1) <= 10: 16 waves per CU at about 113
+// VGPRs), two per thread in workgroups of 512 otherwise (a larger window at 1024 threads spills, and
+// the FP32 kernels keep two 512-thread workgroups per CU).
+constexpr int kStSlots = 1024;
+template <typename T, int K, int NT>
+constexpr int st_threads() { return (sizeof(T) == 8 && NT * (2 * K + 1) <= 10) ? 1024 : 512; }
+constexpr int kStThreads2d = 512;
 
 template <typename T, int K, int NT>
 __device__ __forceinline__ void st_x_pass(const T* Mb, const T* Kb, const T* A, const T* B, int rows_out, int n1,
@@ -73,8 +78,11 @@ __device__ __forceinline__ void st_store(const StencilArgs& a, long long nn, lon
 }
 
 template <typename T, int K, int NT, bool RES>
-__global__ void __launch_bounds__(kStThreads) k_mean_stencil_3d(StencilArgs a) {
+__global__ void __launch_bounds__((st_threads<T, K, NT>())) k_mean_stencil_3d(StencilArgs a) {
     constexpr int W = 2 * K + 1;
+    constexpr int kStThreads = st_threads<T, K, NT>();
+    constexpr int kStPos = kStSlots / kStThreads;     // (y, x) positions per thread in the z march
+    constexpr int kStOut = kStSlots / kStThreads;     // output nodes per thread and plane
     extern __shared__ __align__(16) unsigned char st_lds[];
     const int n1 = a.n1, TY = a.ty, ZC = a.zc;
     const int rows = TY + 2 * K;
@@ -226,7 +234,8 @@ __global__ void __launch_bounds__(kStThreads) k_mean_stencil_3d(StencilArgs a) {
 }
 
 template <typename T, int K, int NT, bool RES>
-__global__ void __launch_bounds__(kStThreads) k_mean_stencil_2d(StencilArgs a) {
+__global__ void __launch_bounds__(kStThreads2d) k_mean_stencil_2d(StencilArgs a) {
+    constexpr int kStThreads = kStThreads2d;
     constexpr int W = 2 * K + 1;
     extern __shared__ __align__(16) unsigned char st_lds[];
     const int n1 = a.n1, TY = a.ty;
@@ -346,13 +355,14 @@ hipError_t launch_knt(const StencilArgs& a, hipStream_t s) {
         if (lds > 64 * 1024)
             (void)hipFuncSetAttribute((const void*)k_mean_stencil_3d<T, K, NT, RES>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_mean_stencil_3d<T, K, NT, RES>), dim3((unsigned)blocks), dim3(kStThreads), lds, s, a);
+        hipLaunchKernelGGL((k_mean_stencil_3d<T, K, NT, RES>), dim3((unsigned)blocks), dim3(st_threads<T, K, NT>()), lds, s,
+                           a);
     } else {
         const long long blocks = (long long)a.n_xi * nyt;
         if (lds > 64 * 1024)
             (void)hipFuncSetAttribute((const void*)k_mean_stencil_2d<T, K, NT, RES>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_mean_stencil_2d<T, K, NT, RES>), dim3((unsigned)blocks), dim3(kStThreads), lds, s, a);
+        hipLaunchKernelGGL((k_mean_stencil_2d<T, K, NT, RES>), dim3((unsigned)blocks), dim3(kStThreads2d), lds, s, a);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -395,8 +405,8 @@ bool stencil_fits(StencilArgs& a, int elem) {
     for (int ty = 8; ty >= 1; --ty) {
         a.ty = ty;
         a.zc = 8;
-        if (a.dim == 3 && (long long)(ty + 2 * k) * a.n1 > (long long)kStPos * kStThreads) continue;
-        if (a.dim == 3 && (long long)ty * a.n1 > (long long)kStOut * kStThreads) continue;
+        if (a.dim == 3 && (long long)(ty + 2 * k) * a.n1 > kStSlots) continue;
+        if (a.dim == 3 && (long long)ty * a.n1 > kStSlots) continue;
         if (stencil_lds_bytes(a, elem) > 160 * 1024) continue;
         return true;
     }
