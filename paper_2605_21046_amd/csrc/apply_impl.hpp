@@ -26,6 +26,7 @@
 #include <mutex>
 #include <vector>
 
+#include "fastdiv.hpp"
 #include "kernels.hpp"
 
 namespace sg {
@@ -51,7 +52,28 @@ struct ApplyArgs {
     int mum[8];           // position of mu = e_m (m = 1..M) in the coefficient list, -1 if absent
     int merge;            // 1: sum the x faces shared by the workgroup's cells before storing
     int ss;               // slot stride of the exchange rows (>= N_xi N_t row_stride((k+1)^d))
+    // quotients by the launch's run-time sizes as multiply-shift (set with cpb): cells per workgroup,
+    // segments per cell row, cells per direction, cells of a row chunk of the traversal, coefficient
+    // modes; segs and the log2 of the chunk's rows
+    FastDiv fcpb, fsegs, fn, ftyn, fnmu;
+    int segs, tylg;
 };
+
+// Sets the multiply-shift quotients of a launch with `cpb` cells per workgroup.
+template <typename T>
+inline void set_apply_divisors(ApplyArgs<T>& a, int cpb) {
+    const int n = a.g.n;
+    const int ty = row_tile(n);
+    a.segs = (n + cpb - 1) / cpb;
+    a.tylg = ty == 4 ? 2 : (ty == 2 ? 1 : 0);
+    a.fcpb = make_fastdiv((unsigned)cpb);
+    a.fsegs = make_fastdiv((unsigned)a.segs);
+    a.fn = make_fastdiv((unsigned)n);
+    a.ftyn = make_fastdiv((unsigned)(ty * n));
+    a.fnmu = make_fastdiv((unsigned)a.n_mu);
+}
+
+__device__ __forceinline__ int apply_quot(const FastDiv& f, int x) { return (int)fast_quot(f, (unsigned)x); }
 
 // Stride of one component's row of point values in the exchange rows: odd, so the rows of consecutive
 // components start on different banks (a power-of-two point count, as 64 for Q3 cells, would put every
@@ -524,19 +546,29 @@ template <int DIM, typename T>
 __device__ __forceinline__ ApplyPos<DIM> apply_position(const ApplyArgs<T>& a, int cpb, int t, int b) {
     ApplyPos<DIM> P;
     const int n = a.g.n;
-    P.slot = t % cpb;
-    P.comp = t / cpb;
-    P.segs = (n + cpb - 1) / cpb;
+    P.comp = apply_quot(a.fcpb, t);
+    P.slot = t - P.comp * cpb;
+    P.segs = a.segs;
     const int lb = xcd_position(b, a.nblocks);
-    P.seg = lb % P.segs;
+    const int o = apply_quot(a.fsegs, lb);        // row in traversal order
+    P.seg = lb - o * P.segs;
     P.x0 = P.seg * cpb;
-    P.cell0 = (long long)tiled_row<DIM>(lb / P.segs, n) * n + P.x0;
+    int row = o;                                   // tiled_row with the quotients precomputed
+    if constexpr (DIM == 3) {
+        const int chunk = apply_quot(a.ftyn, o);
+        const int rem = o - chunk * (n << a.tylg);
+        row = (chunk << a.tylg) + (rem & ((1 << a.tylg) - 1)) + n * (rem >> a.tylg);
+    }
+    const int c0 = row * n + P.x0;                 // cell indices fit 32 bits
+    P.cell0 = c0;
     P.active = P.x0 + P.slot < n;
-    long long r = P.active ? P.cell0 + P.slot : 0;
+    int r = P.active ? c0 + P.slot : 0;
     P.cc[0] = P.cc[1] = P.cc[2] = 0;
+#pragma unroll
     for (int d = 0; d < DIM; ++d) {
-        P.cc[d] = (int)(r % n);
-        r /= n;
+        const int q = apply_quot(a.fn, r);
+        P.cc[d] = r - q * n;
+        r = q;
     }
     return P;
 }
@@ -585,9 +617,8 @@ __global__ void __launch_bounds__(WIDE ? 1024 : (ipow(K + 1, DIM) > 27 ? 256 : 5
 #pragma unroll
         for (int i = 0; i < CPF; ++i) {
             const int idx = t + i * nthreads;
-            const int q = idx % NP;
-            const int mu = (idx / NP) % a.n_mu;
-            const int s = idx / (NP * a.n_mu);
+            const int j = idx / NP, q = idx - j * NP;
+            const int s = apply_quot(a.fnmu, j), mu = j - s * a.n_mu;
             cv[i] = (idx < ncoef && x0 + s < n) ? a.coef[mu * a.coef_mode_stride + (cell0 + s) * NP + q] : T(0);
         }
     }
@@ -616,17 +647,15 @@ __global__ void __launch_bounds__(WIDE ? 1024 : (ipow(K + 1, DIM) > 27 ? 256 : 5
         for (int i = 0; i < CPF; ++i) {
             const int idx = t + i * nthreads;
             if (idx < ncoef) {
-                const int q = idx % NP;
-                const int mu = (idx / NP) % a.n_mu;
-                const int s = idx / (NP * a.n_mu);
+                const int j = idx / NP, q = idx - j * NP;
+                const int s = apply_quot(a.fnmu, j), mu = j - s * a.n_mu;
                 cl[s * CS + mu * NP + q] = cv[i];
             }
         }
     } else {
         for (int idx = t; idx < ncoef; idx += nthreads) {
-            const int q = idx % NP;
-            const int mu = (idx / NP) % a.n_mu;
-            const int s = idx / (NP * a.n_mu);
+            const int j = idx / NP, q = idx - j * NP;
+            const int s = apply_quot(a.fnmu, j), mu = j - s * a.n_mu;
             const long long c2 = cell0 + s;
             cl[s * CS + mu * NP + q] = (x0 + s < n) ? a.coef[mu * a.coef_mode_stride + c2 * NP + q] : T(0);
         }
@@ -799,6 +828,7 @@ hipError_t run_apply(const ApplyOp<T>& op, const T* x, T* s_out, hipStream_t s) 
         if constexpr (DIM == 2) {
             auto wk = op.mean ? k_apply<DIM, K, NT, T, true, 0, 0, true> : k_apply<DIM, K, NT, T, false, 0, 0, true>;
             a.cpb = 1;
+            set_apply_divisors(a, 1);
             a.merge = 0;
             a.ss = nc * RS;
             if (op.used_cpb) *op.used_cpb = 1;
@@ -818,6 +848,7 @@ hipError_t run_apply(const ApplyOp<T>& op, const T* x, T* s_out, hipStream_t s) 
     const size_t fixed = op.mean ? 16 : (size_t)op.n_ent * (sizeof(T) + 2 * sizeof(int)) + 16;
     const int cpb = op.cells_per_block > 0 ? op.cells_per_block : choose_cpb((const void*)kern, nc, fixed, per_cell, MAXT);
     a.cpb = cpb;
+    set_apply_divisors(a, cpb);
     a.merge = op.merge && cpb > 1;
     a.ss = cached_slot_stride<T>(NP, NT, nc, cpb);
     if (op.used_cpb) *op.used_cpb = cpb;

@@ -103,10 +103,16 @@ __global__ void k_transfer_1d(int dim, long long total, int i0, int i1, int o0, 
 // Sum of the broken copies of each node (fixed order: lower cell first in every direction), then the
 // requested update; one thread per node of one component (component = blockIdx.y), consecutive
 // threads on consecutive x nodes.
+// Quotients of the gather by its run-time extents as multiply-shift: nodes per direction, the x and z
+// segment lengths.
+struct GatherDivs {
+    FastDiv n1, sx, sz;
+};
+
 template <typename T, int OP, int DIM, int K>
 __global__ void __launch_bounds__(256)
     k_node_gather(Grid g, const T* __restrict__ s_in, const T* __restrict__ x, const T* __restrict__ b,
-                  T* __restrict__ out, T omega, unsigned sx, unsigned sz) {
+                  T* __restrict__ out, T omega, unsigned sx, unsigned sz, GatherDivs dv) {
     constexpr int N1 = K + 1;
     const unsigned n1 = g.n1, nc = g.n;
     const unsigned nb1 = nc * N1;
@@ -132,13 +138,17 @@ __global__ void __launch_bounds__(256)
         bool bnd = false;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-            const unsigned i = (d == DIM - 1) ? r : r % n1;
-            r /= n1;
+            unsigned i = r;
+            if (d < DIM - 1) {
+                const unsigned q = fast_quot(dv.n1, r);
+                i = r - q * n1;
+                r = q;
+            }
             bnd |= (i == 0) | (i == n1 - 1);
             const unsigned sl = d == 0 ? sx : (d == 2 ? sz : (unsigned)K);   // segment length along d
             const unsigned ns = d == 0 ? nsx : (d == 2 ? nsz : nc);           // segments along d
-            const unsigned c = i / sl;
-            if (i % sl == 0 && i > 0 && i < n1 - 1) {
+            const unsigned c = d == 0 ? fast_quot(dv.sx, i) : (d == 2 ? fast_quot(dv.sz, i) : i / (unsigned)K);
+            if (i == c * sl && i > 0 && i < n1 - 1) {
                 lo[d] = (c - 1) * (sl + 1) + sl;
                 hi[d] = c * (sl + 1);
                 whi[d] = T(1);
@@ -500,8 +510,10 @@ hipError_t launch_node_gather(GatherOp op, int dim, int k, Grid g, int ncomp, co
         return hipErrorInvalidConfiguration;
     const unsigned bx = std::min<long long>((g.n_nodes + 255) / 256, 4096);
     const dim3 grid(bx, ncomp), block(256);
+    const GatherDivs dv{make_fastdiv((unsigned)g.n1), make_fastdiv((unsigned)sx), make_fastdiv((unsigned)sz)};
 #define SG_NG(OP_, D_, K_) \
-    hipLaunchKernelGGL((k_node_gather<T, OP_, D_, K_>), grid, block, 0, s, g, s_in, x, b, out, omega, (unsigned)sx, (unsigned)sz)
+    hipLaunchKernelGGL((k_node_gather<T, OP_, D_, K_>), grid, block, 0, s, g, s_in, x, b, out, omega, (unsigned)sx, \
+                       (unsigned)sz, dv)
 #define SG_NG_K(OP_, D_)                          \
     switch (k) {                                  \
         case 1: SG_NG(OP_, D_, 1); break;         \
