@@ -22,7 +22,12 @@
  *   - Homogeneous Dirichlet condition: rows of boundary DoFs are identity rows; boundary columns
  *     are dropped from the other rows.
  *   - Streams: `hip_stream` is a hipStream_t passed as void* (NULL = the default stream).  Work is
- *     enqueued on that stream only.
+ *     enqueued on that stream only.  Calls on one handle share its work buffers: calls on different
+ *     streams must be ordered by the caller (events), as they would race otherwise.  Every
+ *     asynchronous call records an event of the handle on its stream at the end (unless the stream
+ *     is being captured into a graph); sg_update_coefficients, sg_set_vcycle_segment,
+ *     sg_set_vcycle_graph and sg_destroy wait for that event, i.e. for the handle's last call and
+ *     everything ordered before it, never for the whole device.
  *   - Errors: every call returns an sg_status; arguments are checked before anything is enqueued.
  *     No C++ exception crosses the ABI.  sg_last_error() gives a thread-local message for the last
  *     non-OK status of the calling thread.
@@ -123,7 +128,8 @@ typedef struct {
  * SG_ESINGULAR for a singular patch or coarsest-level matrix. */
 sg_status sg_create(const sg_problem_desc* desc, sg_handle* out);
 
-/* Release every device and host resource of the handle.  NULL is accepted. */
+/* Release every device and host resource of the handle after its last asynchronous call has
+ * completed.  NULL is accepted. */
 sg_status sg_destroy(sg_handle h);
 
 /* Number of entries N_xi * N_t * N_x(level) of a vector on multigrid level `level`. */
@@ -182,8 +188,9 @@ sg_status sg_node_coordinates(const sg_problem_desc* desc, int level, double* xy
  * HOST [n_levels][n_coef_modes][n_cells(l)][(k+1)^d], copied) and redo everything that depends on
  * them: the Vanka patch inverses of every level and the coarsest-level inverse (Remark
  * solver-matrix-free-sg).  Keeps every device allocation of the handle, so a parameter sweep (e.g.
- * the forward/adjoint solves of an optimisation loop) pays no allocation.  Synchronous; must not
- * overlap other calls on the handle.  SG_ESINGULAR if a patch or the coarse matrix is singular. */
+ * the forward/adjoint solves of an optimisation loop) pays no allocation.  Waits for the handle's
+ * last asynchronous call, then runs synchronously on the null stream; must not overlap other calls on
+ * the handle.  SG_ESINGULAR if a patch or the coarse matrix is singular. */
 sg_status sg_update_coefficients(sg_handle h, const double* coef_qp);
 
 /* y = AA^T x for a handle made with transpose = 0 (y = AA x for transpose = 1): the operator of the
@@ -207,9 +214,22 @@ sg_status sg_slab_transfer(sg_handle h, int transpose, const double* x, double* 
  * the Gauss points coef_qp[n_cells(0)][(k+1)^d] (HOST array, same layout and points as one mode of
  * the create-time coef_qp on level 0) and K_{c|K} is the stiffness matrix of c restricted to cell K.
  * lam and u are device slab vectors that vanish on Dirichlet DoFs; out is a device array of
- * n_cells(0) doubles.  d/d theta of lam^T AA u for a_mu = theta c is sum_K out[K].  Asynchronous. */
+ * n_cells(0) doubles.  d/d theta of lam^T AA u for a_mu = theta c is sum_K out[K].  The scaled field
+ * stays on the device per mode: only a call whose coef_qp differs from the last one given for that
+ * mode uploads it and synchronises the stream.  Asynchronous otherwise. */
 sg_status sg_stiffness_form_cells(sg_handle h, int mu_index, const double* coef_qp, const double* lam,
                                   const double* u, double* out, void* hip_stream);
+
+/* The same forms accumulated on the device, for the parameter gradient of an adjoint sweep over many
+ * slabs (each slab n contributes lam_n^T (dAA/dtheta) u_n, with no copy to the host per slab):
+ *     cells[K] += scale out[K]        (cells: device array of n_cells(0) doubles, may be NULL),
+ *     total[0] += scale sum_K out[K]  (total: one device double, may be NULL; the sum over K in one
+ *                                      fixed order, so repeated runs agree bitwise),
+ * with out[K] as in sg_stiffness_form_cells.  SG_EINVAL if both are NULL.  Same field caching and
+ * synchronisation as sg_stiffness_form_cells. */
+sg_status sg_stiffness_form_accumulate(sg_handle h, int mu_index, const double* coef_qp, const double* lam,
+                                       const double* u, double scale, double* cells, double* total,
+                                       void* hip_stream);
 
 /* Mean/variance quantity of interest at the end of a slab.  With u(T) the end-of-slab trace of the
  * slab vector u (time component r) and Q(xi) = int_D u(x, T, xi)^2 dx = sum_{alpha,beta} m_{alpha beta}
@@ -320,7 +340,8 @@ sg_status sg_moment_errors(sg_handle h, const double* acc, long long n_tot, int 
  * prolongations, post-smoothing) as one persistent launch with one workgroup per stochastic mode
  * (enable = 1), or kernel by kernel (enable = 0, the default; sg_autotune times both and keeps the
  * faster).  Both compute the block-Jacobi cycle of Remark solver-matrix-free-sg with the mean block;
- * they differ only in rounding order.  Drops a captured V-cycle graph and synchronises the device.
+ * they differ only in rounding order.  Waits for the handle's last asynchronous call and drops a
+ * captured V-cycle graph.
  * enable = -1 changes nothing (a query).  first_level (host pointer, may be NULL) receives the first
  * level the segment covers (for enable = -1: -1 while the cycle runs kernel by kernel); -1 when the
  * hierarchy has no such levels or uses one diagonal block per mode (then every setting runs kernel by
@@ -333,7 +354,8 @@ sg_status sg_set_vcycle_segment(sg_handle h, int enable, int* first_level);
  * graph is captured on the second V-cycle after enabling (the first runs kernel by kernel) on a stream
  * of the handle's own, and dropped by sg_update_coefficients, sg_autotune and enable = 0.  Results are
  * bitwise those of the kernel-by-kernel cycle.  It pays for small problems, where launching the tens
- * of kernels of a cycle costs more than running them.  Host only. */
+ * of kernels of a cycle costs more than running them.  enable = 0 waits for the handle's last
+ * asynchronous call before dropping the graph; enable = 1 is host only. */
 sg_status sg_set_vcycle_graph(sg_handle h, int enable);
 
 /* Tile autotuner of the operator kernel: for the full operator on level 0 and the mean-block operator

@@ -142,10 +142,12 @@ class SlabSequence:
         if not (np.array_equal(ck.theta, self.theta) and np.array_equal(ck.a0, self.a0)):
             self.set_parameters(ck.theta, ck.a0)
         self.traces, self.u_last, self.grad_u = ck.traces, ck.u_last, ck.grad_u
+        import torch
         M = self.w.n_vars
-        dth = np.zeros(M)
         n_cells = self.qp[0].shape[0]
-        da0 = np.zeros(n_cells)
+        # both gradients accumulate on the device over the slabs; one copy to the host at the end
+        dth = torch.zeros(M, dtype=torch.float64, device=self.dev)
+        da0 = torch.zeros(n_cells, dtype=torch.float64, device=self.dev)
         rhs = self.grad_u
         rhs_buf = self._zeros()
         lam = self._zeros()
@@ -159,7 +161,6 @@ class SlabSequence:
                 u_n = self.u_last
             else:
                 if n == 0:
-                    import torch
                     t0 = torch.zeros(self.n_xi, self.n_x, dtype=torch.float64, device=self.dev)
                     t0[0] = torch.from_numpy(self.u0).to(self.dev)
                     self._trace_to_slab(t0, tmp)
@@ -168,11 +169,10 @@ class SlabSequence:
                 self.G.slab_transfer(tmp, b)
                 u_n = self._solve(self.G, b, u, "recompute_iterations")
             for m in range(M):
-                cells = self.G.stiffness_form_cells(m + 1, self.phi_qp[m], lam, u_n)
-                dth[m] -= float(np.sum(cells.cpu().numpy()))
-            da0 -= self.G.stiffness_form_cells(0, self.ones_qp, lam, u_n).cpu().numpy()
+                self.G.stiffness_form_accumulate(m + 1, self.phi_qp[m], lam, u_n, -1.0, total=dth[m:m + 1])
+            self.G.stiffness_form_accumulate(0, self.ones_qp, lam, u_n, -1.0, cells=da0)
             rhs = self.G.slab_transfer(lam, rhs_buf, transpose=True)
-        return dth, da0
+        return dth.cpu().numpy(), da0.cpu().numpy()
 
     def gradient(self, theta, a0_cells):
         J, EQ, VQ = self.forward(theta, a0_cells)

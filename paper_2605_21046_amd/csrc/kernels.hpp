@@ -66,6 +66,10 @@ enum GatherOp { GATHER_SET = 0, GATHER_RESIDUAL = 1, GATHER_VANKA = 2, GATHER_IN
 // cell-local operator whose per-cell results s_in = A_K u are in the broken layout.
 hipError_t launch_cell_dot(int dim, int k, Grid g, int ncomp, const double* lam, const double* s_in, double* out,
                            hipStream_t s);
+// cells[K] += scale form[K] (cells may be null) and total[0] += scale sum_K form[K] (total may be null),
+// the sum taken in one fixed order by one workgroup
+hipError_t launch_form_accumulate(const double* form, long long n, double scale, double* cells, double* total,
+                                  hipStream_t s);
 
 // mean[i][node] and unbiased var[i][node] over N sample blocks of a slab vector u[N][nt][nn]
 // mean[j][i][node] = u[off[j]][i][node], var = sum_{off[j] < a < off[j+1]} u[a][i][node]^2

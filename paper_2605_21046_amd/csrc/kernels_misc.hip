@@ -274,6 +274,25 @@ __global__ void __launch_bounds__(256)
     if (threadIdx.x == 0) out[cell] = sh[0];
 }
 
+__global__ void __launch_bounds__(1024)
+    k_form_accumulate(const double* __restrict__ form, long long n, double scale, double* __restrict__ cells,
+                      double* __restrict__ total) {
+    __shared__ double sh[1024];
+    double acc = 0.0;
+    for (long long i = threadIdx.x; i < n; i += 1024) {
+        const double v = scale * form[i];
+        if (cells) cells[i] += v;
+        acc += v;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && total) total[0] += sh[0];
+}
+
 constexpr int kCoarseModes = 2;   // modes per workgroup when every mode uses the same inverse
 constexpr int kCoarseWaves = 8;   // waves per workgroup, each summing one range of l
 
@@ -556,6 +575,13 @@ hipError_t launch_cell_dot(int dim, int k, Grid g, int ncomp, const double* lam,
                            hipStream_t s) {
     if (g.n_cells > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(k_cell_dot, dim3((unsigned)g.n_cells), dim3(256), 0, s, dim, k, g, ncomp, lam, s_in, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_form_accumulate(const double* form, long long n, double scale, double* cells, double* total,
+                                  hipStream_t s) {
+    if (n < 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_form_accumulate, dim3(1), dim3(1024), 0, s, form, n, scale, cells, total);
     return hipGetLastError();
 }
 

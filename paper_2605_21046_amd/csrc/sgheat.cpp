@@ -164,10 +164,23 @@ struct sg_handle_s {
         graph_calls = 0;
     }
     std::vector<hipEvent_t> ev_pool;          // timing events of the solver, created once and reused
+    // recorded on the caller's stream at the end of every asynchronous call: calls on one handle are
+    // ordered by the caller, so once it completes no earlier work of the handle is pending either
+    hipEvent_t last_work = nullptr;
+    // cell-wise forms: the last field of every mode as given (host) and scaled on the device, and the
+    // mode whose field sits in fcoef (whose other modes stay zero)
+    std::vector<std::vector<double>> form_raw;
+    DevBuf<double> form_fields, form_cells;
+    int form_active = -1;
     ~sg_handle_s() {
         drop_graph();
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+        if (last_work) (void)hipEventDestroy(last_work);
+    }
+    // waits for the handle's last asynchronous call, not for the whole device
+    void quiesce() {
+        if (last_work) (void)hipEventSynchronize(last_work);
     }
     std::vector<double> hstage;
     std::vector<double> trip;                 // E[Psi_a Psi_b Psi_eps], [n_xi][n_xi][n_eps]
@@ -175,6 +188,19 @@ struct sg_handle_s {
 };
 
 namespace {
+
+// Records the handle's completion event on the caller's stream when an entry point returns (not
+// while the stream is being captured into a graph: the caller's graph owns that work).
+struct WorkMark {
+    sg_handle h;
+    hipStream_t s;
+    ~WorkMark() {
+        if (!h || !h->last_work) return;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone)
+            (void)hipEventRecord(h->last_work, s);
+    }
+};
 
 int ipow_h(int b, int e) {
     int r = 1;
@@ -454,7 +480,7 @@ sg_status set_coefficients(sg_handle h, const double* coef_qp) {
                 SG_HIP(launch_patch_invert(dim, k, h->NT, lv.g, E.p, Me.p, pt, lv.inv64.p + a * ninv,
                                            want32 ? lv.inv32.p + a * ninv : nullptr, status.p, nullptr,
                                            lv.inv_classes ? lv.class_cells.p : nullptr, (int)nslot));
-                SG_HIP(hipDeviceSynchronize());
+                SG_HIP(hipStreamSynchronize(nullptr));   // set-up runs on the null stream
             }
         }
         int st = 0;
@@ -825,7 +851,7 @@ sg_status build(sg_handle h) {
     SG_TRY(h->partial.alloc((size_t)kDotBlocks * (h->restart + 2), "partials"));
     SG_TRY(h->dscal.alloc(3 * 80, "scalars"));
     SG_TRY(h->sbuf.alloc((size_t)h->n_xi * h->NT * h->lv[0].g.n_cells * h->NP, "cell-local results"));
-    SG_HIP(hipDeviceSynchronize());
+    SG_HIP(hipStreamSynchronize(nullptr));
     return SG_OK;
 }
 
@@ -1405,13 +1431,14 @@ sg_status sg_create(const sg_problem_desc* desc, sg_handle* out) {
     }
     SG_HIP(hipGetDevice(&h->device));
     SG_TRY(resolve_scratch(h->device));
+    SG_HIP(hipEventCreateWithFlags(&h->last_work, hipEventDisableTiming));
     *out = h.release();
     return SG_OK;
 }
 
 sg_status sg_destroy(sg_handle h) {
     if (!h) return SG_OK;
-    (void)hipDeviceSynchronize();
+    h->quiesce();
     delete h;
     return SG_OK;
 }
@@ -1424,6 +1451,7 @@ sg_status sg_vector_length(sg_handle h, int level, long long* n) {
 }
 
 sg_status sg_operator_apply(sg_handle h, const double* x, double* y, void* hip_stream) {
+    const WorkMark work_mark{h, (hipStream_t)hip_stream};
     if (!h || !x || !y) return fail(SG_EINVAL, "null argument");
     if (overlap(x, y, h->N * sizeof(double))) return fail(SG_EINVAL, "x and y overlap");
     const ApplyOp<double> op = make_op<double>(h, 0, true);
@@ -1432,6 +1460,7 @@ sg_status sg_operator_apply(sg_handle h, const double* x, double* y, void* hip_s
 }
 
 sg_status sg_operator_apply_noalloc(sg_handle h, const double* x, double* y, void* hip_stream) {
+    const WorkMark work_mark{h, (hipStream_t)hip_stream};
     if (!h || !x || !y) return fail(SG_EINVAL, "null argument");
     if (overlap(x, y, h->N * sizeof(double))) return fail(SG_EINVAL, "x and y overlap");
     // the cell-local results take at most n_xi N_t n_cells (k+1)^d doubles (the per-cell layout)
@@ -1448,6 +1477,7 @@ sg_status sg_operator_apply_noalloc(sg_handle h, const double* x, double* y, voi
 }
 
 sg_status sg_vanka_smooth(sg_handle h, int level, const double* b, double* x, int sweeps, void* hip_stream) {
+    const WorkMark work_mark{h, (hipStream_t)hip_stream};
     if (!h || !b || !x) return fail(SG_EINVAL, "null argument");
     if (level < 0 || level >= h->d.n_levels) return fail(SG_EINVAL, "level out of range");
     if (sweeps < 0) return fail(SG_EINVAL, "sweeps must be >= 0");
@@ -1464,6 +1494,7 @@ sg_status sg_vanka_smooth(sg_handle h, int level, const double* b, double* x, in
 }
 
 sg_status gmg_vcycle(sg_handle h, const double* r, double* z, void* hip_stream) {
+    const WorkMark work_mark{h, (hipStream_t)hip_stream};
     if (!h || !r || !z) return fail(SG_EINVAL, "null argument");
     if (overlap(r, z, h->N * sizeof(double))) return fail(SG_EINVAL, "r and z overlap");
     return vcycle(h, r, z, (hipStream_t)hip_stream);
@@ -1471,6 +1502,7 @@ sg_status gmg_vcycle(sg_handle h, const double* r, double* z, void* hip_stream) 
 
 sg_status fgmres_solve_slab(sg_handle h, const double* b, double* x, double rtol, int max_iter, sg_solve_info* info,
                             void* hip_stream) {
+    const WorkMark work_mark{h, (hipStream_t)hip_stream};
     if (!h || !b || !x) return fail(SG_EINVAL, "null argument");
     if (!(rtol > 0.0) || max_iter < 1) return fail(SG_EINVAL, "rtol > 0 and max_iter >= 1 required");
     if (overlap(b, x, h->N * sizeof(double))) return fail(SG_EINVAL, "b and x overlap");
@@ -1600,7 +1632,7 @@ sg_status fgmres_solve_slab(sg_handle h, const double* b, double* x, double rtol
 sg_status sg_update_coefficients(sg_handle h, const double* coef_qp) {
     if (!h || !coef_qp) return fail(SG_EINVAL, "null argument");
     try {
-        (void)hipDeviceSynchronize();
+        h->quiesce();
         h->drop_graph();                       // the graph holds the set-up's buffers and tiles
         return set_coefficients(h, coef_qp);
     } catch (const std::bad_alloc&) {
@@ -1609,6 +1641,7 @@ sg_status sg_update_coefficients(sg_handle h, const double* coef_qp) {
 }
 
 sg_status sg_operator_apply_T(sg_handle h, const double* x, double* y, void* hip_stream) {
+    const WorkMark work_mark{h, (hipStream_t)hip_stream};
     if (!h || !x || !y) return fail(SG_EINVAL, "null argument");
     if (overlap(x, y, h->N * sizeof(double))) return fail(SG_EINVAL, "x and y overlap");
     ApplyOp<double> op = make_op<double>(h, 0, true);
@@ -1618,6 +1651,7 @@ sg_status sg_operator_apply_T(sg_handle h, const double* x, double* y, void* hip
 }
 
 sg_status sg_slab_transfer(sg_handle h, int transpose, const double* x, double* y, void* hip_stream) {
+    const WorkMark work_mark{h, (hipStream_t)hip_stream};
     if (!h || !x || !y) return fail(SG_EINVAL, "null argument");
     if (transpose != 0 && transpose != 1) return fail(SG_EINVAL, "transpose must be 0 or 1");
     if (overlap(x, y, h->N * sizeof(double))) return fail(SG_EINVAL, "x and y overlap");
@@ -1633,39 +1667,88 @@ sg_status sg_slab_transfer(sg_handle h, int transpose, const double* x, double* 
     return variant_apply(h, &tb, h->zcoef.p, false, x, y, GATHER_INTERIOR, s);
 }
 
-sg_status sg_stiffness_form_cells(sg_handle h, int mu_index, const double* coef_qp, const double* lam,
-                                  const double* u, double* out, void* hip_stream) {
-    if (!h || !coef_qp || !lam || !u || !out) return fail(SG_EINVAL, "null argument");
-    if (mu_index < 0 || mu_index >= h->n_mu) return fail(SG_EINVAL, "mu_index out of range");
-    hipStream_t s = (hipStream_t)hip_stream;
+namespace {
+
+// out[K] = lam^T (G_mu (x) B_t (x) K_{c|K}) u on level 0.  The scaled field of every mode stays on the
+// device: it is uploaded again (and the stream synchronised, the staging array being the caller's
+// stack) only when the caller's values differ from the last ones given for that mode.
+sg_status form_cells(sg_handle h, int mu_index, const double* coef_qp, const double* lam, const double* u,
+                     double* out, hipStream_t s) {
     const Level& l0 = h->lv[0];
     const int dim = h->d.dim, N1 = h->d.fe_degree + 1;
     const size_t per_mode = (size_t)l0.g.n_cells * h->NP;
     const bool mean = mu_index == h->cpl.mu0;
-    // the field at the Gauss points, scaled like the create-time coefficients (weight, h^(d-2))
-    h->hstage.resize(per_mode);
-    const double hs = std::pow(l0.h, dim - 2);
-    for (size_t c = 0; c < (size_t)l0.g.n_cells; ++c)
-        for (int q = 0; q < h->NP; ++q) {
-            double wq = hs;
-            for (int dd = 0, qq = q; dd < dim; ++dd, qq /= N1) wq *= h->tgw[qq % N1];
-            h->hstage[c * h->NP + q] = coef_qp[c * h->NP + q] * wq;
+    if (h->form_fields.n < (size_t)h->n_mu * per_mode) {
+        SG_TRY(h->form_fields.alloc((size_t)h->n_mu * per_mode, "form fields"));
+        SG_TRY(h->fcoef.alloc((size_t)h->n_mu * per_mode, "form coefficient"));
+        SG_HIP(launch_fill<double>(h->fcoef.p, 0.0, (long long)(h->n_mu * per_mode), s));
+        h->form_raw.assign(h->n_mu, {});
+        h->form_active = -1;
+    }
+    std::vector<double>& raw = h->form_raw[mu_index];
+    double* field = h->form_fields.p + (size_t)mu_index * per_mode;
+    if (raw.size() != per_mode || std::memcmp(raw.data(), coef_qp, per_mode * sizeof(double)) != 0) {
+        // the field at the Gauss points, scaled like the create-time coefficients (weight, h^(d-2))
+        std::vector<double> stage(per_mode);
+        const double hs = std::pow(l0.h, dim - 2);
+        for (size_t c = 0; c < (size_t)l0.g.n_cells; ++c)
+            for (int q = 0; q < h->NP; ++q) {
+                double wq = hs;
+                for (int dd = 0, qq = q; dd < dim; ++dd, qq /= N1) wq *= h->tgw[qq % N1];
+                stage[c * h->NP + q] = coef_qp[c * h->NP + q] * wq;
+            }
+        SG_HIP(hipMemcpyAsync(field, stage.data(), per_mode * sizeof(double), hipMemcpyHostToDevice, s));
+        SG_HIP(hipStreamSynchronize(s));
+        raw.assign(coef_qp, coef_qp + per_mode);
+        if (h->form_active == mu_index) h->form_active = -1;    // fcoef holds the old values
+    }
+    const double* coef = field;                 // the mean-block operator reads one mode
+    if (!mean) {
+        // the full operator reads every mode: only mode mu of fcoef is non-zero
+        if (h->form_active != mu_index) {
+            if (h->form_active >= 0)
+                SG_HIP(launch_fill<double>(h->fcoef.p + (size_t)h->form_active * per_mode, 0.0, (long long)per_mode, s));
+            SG_HIP(hipMemcpyAsync(h->fcoef.p + (size_t)mu_index * per_mode, field, per_mode * sizeof(double),
+                                  hipMemcpyDeviceToDevice, s));
+            h->form_active = mu_index;
         }
-    const size_t nmodes = mean ? 1 : (size_t)h->n_mu;
-    if (h->fcoef.n < (size_t)h->n_mu * per_mode) SG_TRY(h->fcoef.alloc((size_t)h->n_mu * per_mode, "form coefficient"));
-    if (!mean) SG_HIP(launch_fill<double>(h->fcoef.p, 0.0, (long long)(nmodes * per_mode), s));
-    double* dst = h->fcoef.p + (mean ? 0 : (size_t)mu_index * per_mode);
-    SG_HIP(hipMemcpyAsync(dst, h->hstage.data(), per_mode * sizeof(double), hipMemcpyHostToDevice, s));
+        coef = h->fcoef.p;
+    }
     const std::vector<double> no_mass((size_t)h->NT * h->NT, 0.0);
     const Tables<double> tb = tables_with(h, no_mass);
-    SG_TRY(variant_apply(h, &tb, h->fcoef.p, !mean, u, nullptr, GATHER_SET, s, true));
+    SG_TRY(variant_apply(h, &tb, coef, !mean, u, nullptr, GATHER_SET, s, true));
     SG_HIP(launch_cell_dot(dim, h->d.fe_degree, l0.g, h->n_xi * h->NT, lam, h->sbuf.p, out, s));
-    SG_HIP(hipStreamSynchronize(s));   // the host staging array is reused by the next call
+    return SG_OK;
+}
+
+}  // namespace
+
+sg_status sg_stiffness_form_cells(sg_handle h, int mu_index, const double* coef_qp, const double* lam,
+                                  const double* u, double* out, void* hip_stream) {
+    const WorkMark work_mark{h, (hipStream_t)hip_stream};
+    if (!h || !coef_qp || !lam || !u || !out) return fail(SG_EINVAL, "null argument");
+    if (mu_index < 0 || mu_index >= h->n_mu) return fail(SG_EINVAL, "mu_index out of range");
+    return form_cells(h, mu_index, coef_qp, lam, u, out, (hipStream_t)hip_stream);
+}
+
+sg_status sg_stiffness_form_accumulate(sg_handle h, int mu_index, const double* coef_qp, const double* lam,
+                                       const double* u, double scale, double* cells, double* total,
+                                       void* hip_stream) {
+    const WorkMark work_mark{h, (hipStream_t)hip_stream};
+    if (!h || !coef_qp || !lam || !u) return fail(SG_EINVAL, "null argument");
+    if (!cells && !total) return fail(SG_EINVAL, "cells and total are both null");
+    if (mu_index < 0 || mu_index >= h->n_mu) return fail(SG_EINVAL, "mu_index out of range");
+    const hipStream_t s = (hipStream_t)hip_stream;
+    const long long nc = h->lv[0].g.n_cells;
+    if (h->form_cells.n < (size_t)nc) SG_TRY(h->form_cells.alloc((size_t)nc, "cell forms"));
+    SG_TRY(form_cells(h, mu_index, coef_qp, lam, u, h->form_cells.p, s));
+    SG_HIP(launch_form_accumulate(h->form_cells.p, nc, scale, cells, total, s));
     return SG_OK;
 }
 
 sg_status sg_qoi_mean_var(sg_handle h, const double* u, double w_mean, double w_var, double* qoi, double* grad,
                           void* hip_stream) {
+    const WorkMark work_mark{h, (hipStream_t)hip_stream};
     if (!h || !u || !qoi) return fail(SG_EINVAL, "null argument");
     if (h->d.n_samples > 0 || h->d.n_members > 0)
         return fail(SG_EUNSUPPORTED, "the chaos QoI needs a single stochastic Galerkin problem");
@@ -1830,6 +1913,7 @@ QTables make_qtables(int k, int nq1) {
 
 sg_status sg_load_vectors(sg_handle h, int nq1, int n_fields, const double* fval, const double* fgrad, double* out,
                           void* hip_stream) {
+    const WorkMark work_mark{h, (hipStream_t)hip_stream};
     if (!h || !out || n_fields < 0) return fail(SG_EINVAL, "bad argument");
     if (nq1 < 1 || nq1 > kMaxQ1) return fail(SG_EINVAL, "nq1 must be in 1..8");
     if (n_fields == 0) return SG_OK;
@@ -1852,6 +1936,7 @@ sg_status sg_load_vectors(sg_handle h, int nq1, int n_fields, const double* fval
 
 sg_status sg_separable_vector(sg_handle h, int n_terms, const double* W, const double* V, double beta, double* y,
                               void* hip_stream) {
+    const WorkMark work_mark{h, (hipStream_t)hip_stream};
     if (!h || !y || n_terms < 0 || (n_terms > 0 && (!W || !V))) return fail(SG_EINVAL, "bad argument");
     const hipStream_t s = (hipStream_t)hip_stream;
     const size_t nw = (size_t)std::max(n_terms, 1) * h->n_xi * h->NT;
@@ -1864,6 +1949,7 @@ sg_status sg_separable_vector(sg_handle h, int n_terms, const double* W, const d
 
 sg_status sg_separable_error(sg_handle h, const double* u, int nq1, const double* s_qp, const double* gs_qp, int ntq,
                              const double* theta, const double* c, double C2, double* out, void* hip_stream) {
+    const WorkMark work_mark{h, (hipStream_t)hip_stream};
     if (!h || !u || !s_qp || !gs_qp || !theta || !c || !out) return fail(SG_EINVAL, "null argument");
     if (nq1 < 1 || nq1 > kMaxQ1 || ntq < 1 || ntq > kMaxTimeQ) return fail(SG_EINVAL, "nq1 and ntq must be in 1..8");
     if (h->d.n_samples > 0 || h->d.n_members > 0) return fail(SG_EINVAL, "needs a single stochastic Galerkin problem");
@@ -1929,6 +2015,7 @@ sg_status sg_sample_psi(sg_handle h, int n_idx, const int* alpha, double* out) {
 }
 
 sg_status sg_sample_qp_moments(sg_handle h, const double* u, int nq1, int ntq, double* acc, void* hip_stream) {
+    const WorkMark work_mark{h, (hipStream_t)hip_stream};
     if (!h || !u || !acc) return fail(SG_EINVAL, "null argument");
     if (h->d.n_samples < 1) return fail(SG_EINVAL, "not a sample-batch handle");
     if (nq1 < 1 || nq1 > kMaxQ1 || ntq < 1 || ntq > kMaxTimeQ) return fail(SG_EINVAL, "nq1 and ntq must be in 1..8");
@@ -1946,6 +2033,7 @@ sg_status sg_sample_qp_moments(sg_handle h, const double* u, int nq1, int ntq, d
 sg_status sg_moment_errors(sg_handle h, const double* acc, long long n_tot, int nq1, const double* s_qp, int ntq,
                            const double* theta, const double* mean_targets, const double* var_targets, double* out,
                            void* hip_stream) {
+    const WorkMark work_mark{h, (hipStream_t)hip_stream};
     if (!h || !acc || !s_qp || !theta || !mean_targets || !var_targets || !out) return fail(SG_EINVAL, "null argument");
     if (n_tot < 2) return fail(SG_EINVAL, "the unbiased variance needs at least two samples");
     if (nq1 < 1 || nq1 > kMaxQ1 || ntq < 1 || ntq > kMaxTimeQ) return fail(SG_EINVAL, "nq1 and ntq must be in 1..8");
@@ -1967,7 +2055,7 @@ sg_status sg_set_vcycle_segment(sg_handle h, int enable, int* first_level) {
     if (!h || enable < -1 || enable > 1) return fail(SG_EINVAL, "bad argument");
     if (first_level) *first_level = enable == -1 && !h->seg_on ? -1 : h->seg_level;
     if (enable == -1) return SG_OK;
-    (void)hipDeviceSynchronize();
+    h->quiesce();
     h->drop_graph();                           // a captured V-cycle holds the other path
     h->seg_on = enable == 1;
     return SG_OK;
@@ -1976,7 +2064,7 @@ sg_status sg_set_vcycle_segment(sg_handle h, int enable, int* first_level) {
 sg_status sg_set_vcycle_graph(sg_handle h, int enable) {
     if (!h || (enable != 0 && enable != 1)) return fail(SG_EINVAL, "bad argument");
     if (!enable) {
-        (void)hipDeviceSynchronize();
+        h->quiesce();
         h->drop_graph();
     }
     h->graph_on = enable == 1;
@@ -1984,6 +2072,7 @@ sg_status sg_set_vcycle_graph(sg_handle h, int enable) {
 }
 
 sg_status sg_autotune(sg_handle h, int reps, int* cpb_out, void* hip_stream) {
+    const WorkMark work_mark{h, (hipStream_t)hip_stream};
     if (!h) return fail(SG_EINVAL, "null argument");
     if (reps < 1 || reps > 1000) return fail(SG_EINVAL, "reps must be in 1..1000");
     const hipStream_t s = (hipStream_t)hip_stream;
@@ -2004,6 +2093,7 @@ sg_status sg_autotune(sg_handle h, int reps, int* cpb_out, void* hip_stream) {
 }
 
 sg_status sg_sample_statistics(sg_handle h, const double* u, double* mean, double* var, void* hip_stream) {
+    const WorkMark work_mark{h, (hipStream_t)hip_stream};
     if (!h || !u || !mean) return fail(SG_EINVAL, "null argument");
     if (h->d.n_samples < 1) return fail(SG_EINVAL, "not a sample-batch handle");
     SG_HIP(launch_sample_stats(u, h->d.n_samples, h->NT, h->lv[0].g.n_nodes, mean, var, (hipStream_t)hip_stream));
@@ -2011,6 +2101,7 @@ sg_status sg_sample_statistics(sg_handle h, const double* u, double* mean, doubl
 }
 
 sg_status sg_chaos_moments(sg_handle h, const double* u, double* mean, double* var, void* hip_stream) {
+    const WorkMark work_mark{h, (hipStream_t)hip_stream};
     if (!h || !u || !mean) return fail(SG_EINVAL, "null argument");
     if (h->d.n_samples > 0) return fail(SG_EINVAL, "a sample-batch handle has no chaos modes");
     SG_HIP(launch_chaos_moments(u, h->moff.p, (int)h->member_off.size() - 1, h->NT, h->lv[0].g.n_nodes, mean, var,

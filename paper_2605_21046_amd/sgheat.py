@@ -20,7 +20,7 @@ _STATUS = {0: "SG_OK", 1: "SG_NOT_CONVERGED", -1: "SG_EINVAL", -2: "SG_ENOMEM", 
            -4: "SG_ESINGULAR", -5: "SG_EUNSUPPORTED"}
 EXPORTS = ["sg_create", "sg_destroy", "sg_vector_length", "sg_operator_apply", "sg_operator_apply_noalloc", "sg_vanka_smooth",
            "gmg_vcycle", "fgmres_solve_slab", "sg_quadrature_points", "sg_node_coordinates", "sg_update_coefficients", "sg_operator_apply_T",
-           "sg_slab_transfer", "sg_stiffness_form_cells", "sg_qoi_mean_var", "sg_sample_statistics", "sg_chaos_moments", "sg_gauss_points", "sg_index_set", "sg_chaos_projection",
+           "sg_slab_transfer", "sg_stiffness_form_cells", "sg_stiffness_form_accumulate", "sg_qoi_mean_var", "sg_sample_statistics", "sg_chaos_moments", "sg_gauss_points", "sg_index_set", "sg_chaos_projection",
            "sg_time_rule", "sg_time_load_weights", "sg_load_vectors", "sg_separable_vector", "sg_separable_error",
            "sg_sample_psi", "sg_sample_qp_moments", "sg_moment_errors", "sg_autotune", "sg_set_vcycle_graph", "sg_set_vcycle_segment", "sg_last_error"]
 
@@ -72,6 +72,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sg_operator_apply_T.argtypes = [P, V, V, V]
     lib.sg_slab_transfer.argtypes = [P, I, V, V, V]
     lib.sg_stiffness_form_cells.argtypes = [P, I, ctypes.POINTER(ctypes.c_double), V, V, V, V]
+    lib.sg_stiffness_form_accumulate.argtypes = [P, I, ctypes.POINTER(ctypes.c_double), V, V, D, V, V, V]
     lib.sg_qoi_mean_var.argtypes = [P, V, D, D, ctypes.POINTER(ctypes.c_double), V, V]
     lib.sg_sample_statistics.argtypes = [P, V, V, V, V]
     lib.sg_chaos_moments.argtypes = [P, V, V, V, V]
@@ -294,6 +295,17 @@ class Problem:
                                             _ptr(lam, n, "lam"), _ptr(u, n, "u"), _ptr(out, n_cells, "out"),
                                             _stream(stream)))
         return out
+
+    def stiffness_form_accumulate(self, mu_index, coef_qp, lam, u, scale, cells=None, total=None, stream=None):
+        """cells[K] += scale out[K] and total[0] += scale sum_K out[K] on the device, with out[K] as in
+        stiffness_form_cells (either target may be None, not both)."""
+        n = self.n(0)
+        n_cells = self.spec.n_cells_1d ** self.spec.dim
+        c = np.ascontiguousarray(np.asarray(coef_qp, dtype=np.float64).reshape(n_cells, -1))
+        _check(_lib.sg_stiffness_form_accumulate(
+            self._h, int(mu_index), c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(lam, n, "lam"),
+            _ptr(u, n, "u"), float(scale), None if cells is None else _ptr(cells, n_cells, "cells"),
+            None if total is None else _ptr(total, 1, "total"), _stream(stream)))
 
     def qoi_mean_var(self, u, w_mean=1.0, w_var=1.0, grad=None, stream=None):
         """(E[Q], Var[Q]) of Q = int_D u(T)^2 and, if grad is a tensor, dJ/du for J = w_mean E + w_var Var."""

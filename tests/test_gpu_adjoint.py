@@ -114,6 +114,41 @@ def test_stiffness_forms_match_oracle(torch_cuda, name):
 
 
 @pytest.mark.parametrize("name", ["c1", "t3q2"])
+def test_stiffness_form_accumulate_and_field_cache(torch_cuda, name):
+    """Device accumulation of the forms over a sequence of calls that revisit modes, change a field and
+    give it back: every per-cell result against the oracle (1e-12), the accumulated cells and total
+    against the oracle's sums (1e-12 of the summed magnitudes)."""
+    from paper_2605_21046_amd import sgheat
+    torch = torch_cuda
+    w = sg_inputs.WORKLOADS[name]
+    P = from_workload(w)
+    G = sgheat.problem_from_workload(w)
+    lam, u = _interior_vector(P, 24), _interior_vector(P, 25)
+    lg, ug = _to_gpu(torch, lam), _to_gpu(torch, u)
+    pts = P.mesh.qp_coords()
+    fields = [np.ones((P.mesh.n_cells, P.mesh.nq))] + [sg_inputs.sine_shape_at(m, pts) for m in range(1, w.n_vars + 1)]
+    calls = [(i, fields[i]) for i in range(len(P.coef_mu))]
+    calls += [(1, 2.0 * fields[1]), (0, 0.5 * fields[0] + 1.0), (1, fields[1]), (len(P.coef_mu) - 1, fields[-1])]
+    cells = torch.zeros(P.mesh.n_cells, dtype=torch.float64, device="cuda")
+    total = torch.zeros(1, dtype=torch.float64, device="cuda")
+    exp_cells = np.zeros(P.mesh.n_cells)
+    mag = np.zeros(P.mesh.n_cells)
+    for k, (i, f) in enumerate(calls):
+        print(f"form accumulate {name} call {k} mode {i}", flush=True)
+        ref = adj.cell_forms(P, lam, u, chaos.galerkin_tensor(P.coef_mu[i], P.index_set), f)
+        got = G.stiffness_form_cells(i, f, lg, ug).cpu().numpy()
+        assert _rel_inf(got, ref) <= 1e-12
+        scale = (-1.0) ** k * (1.0 + 0.25 * k)
+        G.stiffness_form_accumulate(i, f, lg, ug, scale, cells=cells, total=total)
+        exp_cells += scale * ref
+        mag += np.abs(scale * ref)
+    assert np.abs(cells.cpu().numpy() - exp_cells).max() <= 1e-12 * mag.max()
+    assert abs(total.item() - exp_cells.sum()) <= 1e-12 * mag.sum()
+    with pytest.raises(sgheat.SgError):
+        G.stiffness_form_accumulate(0, fields[0], lg, ug, 1.0)
+
+
+@pytest.mark.parametrize("name", ["c1", "t3q2"])
 def test_qoi_and_gradient_match_oracle(torch_cuda, name):
     from paper_2605_21046_amd import sgheat
     torch = torch_cuda

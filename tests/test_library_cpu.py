@@ -119,6 +119,7 @@ def test_null_handles_are_rejected_by_every_entry_point():
     assert L.sg_autotune(None, 5, None, None) == -1
     assert L.sg_set_vcycle_graph(None, 1) == -1
     assert L.sg_set_vcycle_segment(None, 1, None) == -1
+    assert L.sg_stiffness_form_accumulate(None, 0, None, None, None, 1.0, None, None, None) == -1
     assert L.sg_update_coefficients(None, None) == -1
     assert L.sg_qoi_mean_var(None, None, 1.0, 1.0, None, None, None) == -1
 
