@@ -152,6 +152,30 @@ template <typename T>
 hipError_t launch_vanka_cells_modes(int dim, int k, int nt, Grid g, int n_xi, const T* invT, const T* r, T* s_out,
                                     hipStream_t s);
 
+// The same corrections for a level whose mean coefficient is one constant, by fast diagonalisation of
+// the Kronecker-structured patch matrices (kernels_vanka.hip): Sv [3][k+1][k+1] per-direction
+// transforms of the first / inner / last cell, Tt [3^d][(k+1)^d][N_t][N_t] inverted time blocks per
+// position class.  The modes go through LDS in passes of vanka_fdm_modes_per_pass.
+constexpr int kFdmLdsBudget = 32 * 1024;   // LDS per workgroup aimed at (several workgroups per CU)
+inline int vanka_fdm_modes_per_pass(int dim, int k, int nt, int n_xi, size_t elem) {
+    int np = 1;
+    for (int d = 0; d < dim; ++d) np *= k + 1;
+    const long long per_mode = (long long)nt * (np | 1) * (long long)elem;
+    const long long tab = (long long)np * nt * nt * (long long)elem;
+    long long mmax = (kFdmLdsBudget - tab) / per_mode;
+    if (mmax < 1) mmax = 1;
+    const long long passes = (n_xi + mmax - 1) / mmax;
+    return (int)((n_xi + passes - 1) / passes);
+}
+inline size_t vanka_fdm_lds_bytes(int dim, int k, int nt, int mp, size_t elem) {
+    int np = 1;
+    for (int d = 0; d < dim; ++d) np *= k + 1;
+    return ((size_t)np * nt * nt + (size_t)mp * nt * (np | 1)) * elem;
+}
+template <typename T>
+hipError_t launch_vanka_fdm(int dim, int k, int nt, Grid g, int n_xi, const T* Sv, const T* Tt, const T* r,
+                            T* s_out, hipStream_t s);
+
 // ---- the coarse segment of the V-cycle in one launch ----------------------------------------------------
 // Levels l0 .. l0 + nlev - 1 (the last is the coarsest) of the block-Jacobi cycle with the mean block, one
 // workgroup per stochastic mode (kernels_segment.hip).  Vectors are the levels' [n_xi][N_t][n_nodes]

@@ -752,4 +752,253 @@ template hipError_t launch_vanka_cells<double>(int, int, int, Grid, int, const d
 template hipError_t launch_vanka_cells<float>(int, int, int, Grid, int, const float*, const float*, float*, int,
                                               hipStream_t);
 
+// ------------------------------------------------------------------------------------------------
+// Vanka patch corrections by fast diagonalisation, for levels whose mean coefficient is one constant
+// c.  The assembled mean block is then A_t (x) M + B_t (x) K with M = (x)_d M1 and K = sum_d of the
+// Kronecker products with one factor c K1 (M1, K1 the assembled 1D matrices), and the restriction of
+// a Kronecker product to the nodes of a cell is the Kronecker product of the restrictions.  On the
+// interior nodes of the cell along each direction, the 1D pencil has c K1r S = M1r S Lambda with
+// S^T M1r S = I, so with S3 = (x)_d S_d the patch matrix becomes block diagonal:
+//     A_{0,K}^{-1} = (I (x) S3) diag_e (A_t + lambda_e B_t)^{-1} (I (x) S3^T),
+// lambda_e the sum of the 1D eigenvalues of eigen index e.  S_d is stored (k+1) x (k+1) with zero
+// rows for Dirichlet nodes and zero columns for unused eigen indices, so the product is zero on the
+// Dirichlet DoFs, as the identity rows of the dense patch give for the masked residual there.
+//   Sv: [3 variants][k+1 nodes j][k+1 eigen i]; variant 0 / 1 / 2 = first / inner / last cell
+//       along a direction (the 1D restriction is the same in every direction of the uniform mesh).
+//   Tt: [3^d classes][(k+1)^d eigen e][N_t][N_t], (A_t + lambda_e B_t)^{-1} (zero for unused e);
+//       class = sum_d 3^d variant_d.
+// One workgroup per cell.  The residual patch of up to `mp` modes is gathered into LDS (components
+// of odd stride P, so the line sweeps below hit different banks), transformed along every direction
+// but the last in place, then the last direction, the time blocks and the inverse transform of the
+// last direction run in one sweep per (mode, line), and the remaining inverse transforms follow; the
+// result goes to the broken node array like k_vanka_cells' results.
+namespace {
+
+constexpr int kFdmThreads = 256;
+
+template <int DIM, int K, int NT, typename T>
+__global__ void __launch_bounds__(kFdmThreads)
+    k_vanka_fdm(Grid g, int n_xi, int mp, const T* __restrict__ Sv, const T* __restrict__ Tt,
+                const T* __restrict__ r, T* __restrict__ s_out) {
+    constexpr int N1 = K + 1;
+    constexpr int NP = ipow(N1, DIM);
+    constexpr int P = NP | 1;                 // LDS stride of one component
+    constexpr int NL = NP / N1;               // lines of one component along one direction
+    constexpr int NTT = NT * NT;
+    extern __shared__ unsigned char smem_raw[];
+    T* const tb = reinterpret_cast<T*>(smem_raw);   // [NP][NT][NT] of this cell's class
+    T* const X = tb + NP * NTT;                     // [mp * NT][P]
+
+    const int n_cells = (int)g.n_cells;
+    const int pos = xcd_position(blockIdx.x, n_cells);
+    const int cell = tiled_row<DIM>(pos / g.n, g.n) * g.n + pos % g.n;
+    int cc[3] = {0, 0, 0};
+    {
+        int rr = cell;
+        for (int d = 0; d < DIM; ++d) { cc[d] = rr % g.n; rr /= g.n; }
+    }
+    int cls = 0, node0 = 0, brk0 = 0;
+    const int nb1 = g.n * N1;
+    int nbn = 1;
+    const T* Sd[3];
+    for (int d = 0, m3 = 1, mn = 1; d < DIM; ++d) {
+        const int v = cc[d] == 0 ? 0 : (cc[d] == g.n - 1 ? 2 : 1);
+        cls += m3 * v;
+        Sd[d] = Sv + v * N1 * N1;
+        node0 += cc[d] * K * mn;
+        brk0 += cc[d] * N1 * nbn;
+        m3 *= 3;
+        mn *= g.n1;
+        nbn *= nb1;
+    }
+    const int nn = (int)g.n_nodes;
+    const T* const tc = Tt + (long long)cls * NP * NTT;
+    for (int i = threadIdx.x; i < NP * NTT; i += kFdmThreads) tb[i] = tc[i];
+
+    for (int m0 = 0; m0 < n_xi; m0 += mp) {
+        const int nm = min(mp, n_xi - m0);
+        const int ncomp = nm * NT;
+        // gather: neighbouring threads read neighbouring nodes; Dirichlet values are zeroed
+        for (int idx = threadIdx.x; idx < ncomp * NP; idx += kFdmThreads) {
+            const int c = idx / NP, p = idx - c * NP;
+            int node = node0;
+            bool live = true;
+            for (int d = 0, pp = p, mn = 1; d < DIM; ++d, pp /= N1) {
+                const int id = cc[d] * K + pp % N1;
+                live &= (id != 0) & (id != g.n1 - 1);
+                node += (pp % N1) * mn;
+                mn *= g.n1;
+            }
+            const T v = r[(m0 * NT + c) * nn + node];
+            X[c * P + p] = live ? v : T(0);
+        }
+        __syncthreads();
+        // forward transforms along every direction but the last: u_i = sum_j S[j][i] v_j
+#pragma unroll
+        for (int d = 0; d < DIM - 1; ++d) {
+            const int st = ipow(N1, d);
+            T S[N1 * N1];
+#pragma unroll
+            for (int i = 0; i < N1 * N1; ++i) S[i] = Sd[d][i];
+            for (int it = threadIdx.x; it < ncomp * NL; it += kFdmThreads) {
+                const int c = it / NL, q = it - c * NL;
+                const int lo = q % st, hi = q / st;
+                T* const line = X + c * P + lo + hi * st * N1;
+                T v[N1];
+#pragma unroll
+                for (int j = 0; j < N1; ++j) v[j] = line[j * st];
+#pragma unroll
+                for (int i = 0; i < N1; ++i) {
+                    T u = T(0);
+#pragma unroll
+                    for (int j = 0; j < N1; ++j) u += S[j * N1 + i] * v[j];
+                    line[i * st] = u;
+                }
+            }
+            __syncthreads();
+        }
+        // last direction: forward transform, the time block of every eigen index, inverse transform
+        {
+            constexpr int st = NL;
+            T S[N1 * N1];
+#pragma unroll
+            for (int i = 0; i < N1 * N1; ++i) S[i] = Sd[DIM - 1][i];
+            for (int it = threadIdx.x; it < nm * NL; it += kFdmThreads) {
+                const int ml = it / NL, q = it - ml * NL;
+                T u[NT][N1];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const T* const line = X + (ml * NT + t) * P + q;
+                    T v[N1];
+#pragma unroll
+                    for (int j = 0; j < N1; ++j) v[j] = line[j * st];
+#pragma unroll
+                    for (int i = 0; i < N1; ++i) {
+                        T a = T(0);
+#pragma unroll
+                        for (int j = 0; j < N1; ++j) a += S[j * N1 + i] * v[j];
+                        u[t][i] = a;
+                    }
+                }
+                T w[NT][N1];
+#pragma unroll
+                for (int i = 0; i < N1; ++i) {
+                    const T* const te = tb + (q + i * st) * NTT;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        T a = T(0);
+#pragma unroll
+                        for (int t2 = 0; t2 < NT; ++t2) a += te[t * NT + t2] * u[t2][i];
+                        w[t][i] = a;
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    T* const line = X + (ml * NT + t) * P + q;
+#pragma unroll
+                    for (int j = 0; j < N1; ++j) {
+                        T a = T(0);
+#pragma unroll
+                        for (int i = 0; i < N1; ++i) a += S[j * N1 + i] * w[t][i];
+                        line[j * st] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // inverse transforms along the other directions: o_j = sum_i S[j][i] w_i
+#pragma unroll
+        for (int d = DIM - 2; d >= 0; --d) {
+            const int st = ipow(N1, d);
+            T S[N1 * N1];
+#pragma unroll
+            for (int i = 0; i < N1 * N1; ++i) S[i] = Sd[d][i];
+            for (int it = threadIdx.x; it < ncomp * NL; it += kFdmThreads) {
+                const int c = it / NL, q = it - c * NL;
+                const int lo = q % st, hi = q / st;
+                T* const line = X + c * P + lo + hi * st * N1;
+                T w[N1];
+#pragma unroll
+                for (int i = 0; i < N1; ++i) w[i] = line[i * st];
+#pragma unroll
+                for (int j = 0; j < N1; ++j) {
+                    T a = T(0);
+#pragma unroll
+                    for (int i = 0; i < N1; ++i) a += S[j * N1 + i] * w[i];
+                    line[j * st] = a;
+                }
+            }
+            __syncthreads();
+        }
+        // store into the broken layout [comp][b_z][b_y][b_x]
+        for (int idx = threadIdx.x; idx < ncomp * NP; idx += kFdmThreads) {
+            const int c = idx / NP, p = idx - c * NP;
+            int b = brk0;
+            for (int d = 0, pp = p, bm = 1; d < DIM; ++d, pp /= N1) {
+                b += (pp % N1) * bm;
+                bm *= nb1;
+            }
+            s_out[(m0 * NT + c) * nbn + b] = X[c * P + p];
+        }
+        __syncthreads();                          // the next pass reuses X
+    }
+}
+
+template <int DIM, int K, int NT, typename T>
+hipError_t run_vanka_fdm(Grid g, int n_xi, const T* Sv, const T* Tt, const T* r, T* s_out, hipStream_t s) {
+    constexpr int NP = ipow(K + 1, DIM);
+    long long nbn = 1;
+    for (int d = 0; d < DIM; ++d) nbn *= (long long)g.n * (K + 1);
+    if ((long long)n_xi * NT * g.n_nodes >= (1LL << 31) || (long long)n_xi * NT * nbn >= (1LL << 31) ||
+        g.n_cells >= (1LL << 31) || n_xi < 1)
+        return hipErrorInvalidValue;      // 32-bit offsets
+    const int mp = vanka_fdm_modes_per_pass(DIM, K, NT, n_xi, sizeof(T));
+    const size_t lds = vanka_fdm_lds_bytes(DIM, K, NT, mp, sizeof(T));
+    if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+    auto kern = k_vanka_fdm<DIM, K, NT, T>;
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)NP;
+    hipLaunchKernelGGL(kern, dim3((unsigned)g.n_cells), dim3(kFdmThreads), lds, s, g, n_xi, mp, Sv, Tt, r, s_out);
+    return hipGetLastError();
+}
+
+template <int DIM, int K, typename T>
+hipError_t vanka_fdm_nt(int nt, Grid g, int n_xi, const T* Sv, const T* Tt, const T* r, T* s_out, hipStream_t s) {
+    switch (nt) {
+        case 1: return run_vanka_fdm<DIM, K, 1, T>(g, n_xi, Sv, Tt, r, s_out, s);
+        case 2: return run_vanka_fdm<DIM, K, 2, T>(g, n_xi, Sv, Tt, r, s_out, s);
+        case 3: return run_vanka_fdm<DIM, K, 3, T>(g, n_xi, Sv, Tt, r, s_out, s);
+        case 4: return run_vanka_fdm<DIM, K, 4, T>(g, n_xi, Sv, Tt, r, s_out, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int DIM, typename T>
+hipError_t vanka_fdm_k(int k, int nt, Grid g, int n_xi, const T* Sv, const T* Tt, const T* r, T* s_out,
+                       hipStream_t s) {
+    switch (k) {
+        case 1: return vanka_fdm_nt<DIM, 1, T>(nt, g, n_xi, Sv, Tt, r, s_out, s);
+        case 2: return vanka_fdm_nt<DIM, 2, T>(nt, g, n_xi, Sv, Tt, r, s_out, s);
+        case 3: return vanka_fdm_nt<DIM, 3, T>(nt, g, n_xi, Sv, Tt, r, s_out, s);
+        case 4: return vanka_fdm_nt<DIM, 4, T>(nt, g, n_xi, Sv, Tt, r, s_out, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_vanka_fdm(int dim, int k, int nt, Grid g, int n_xi, const T* Sv, const T* Tt, const T* r,
+                            T* s_out, hipStream_t s) {
+    if (dim == 2) return vanka_fdm_k<2, T>(k, nt, g, n_xi, Sv, Tt, r, s_out, s);
+    if (dim == 3) return vanka_fdm_k<3, T>(k, nt, g, n_xi, Sv, Tt, r, s_out, s);
+    return hipErrorInvalidValue;
+}
+
+template hipError_t launch_vanka_fdm<double>(int, int, int, Grid, int, const double*, const double*, const double*,
+                                             double*, hipStream_t);
+template hipError_t launch_vanka_fdm<float>(int, int, int, Grid, int, const float*, const float*, const float*,
+                                            float*, hipStream_t);
+
 }  // namespace sg

@@ -83,6 +83,10 @@ struct Level {
     bool mean_const = false;                 // mean coefficient one constant: mean block as a Kronecker sum
     DevBuf<double> mb64, kb64;               // its assembled 1D mass / stiffness bands [n1][2k+1] (K times c)
     DevBuf<float> mb32, kb32;
+    // and its Vanka corrections by fast diagonalisation: per-direction transforms of the first / inner /
+    // last cell [3][k+1][k+1] and inverted time blocks per position class [3^d][(k+1)^d][N_t][N_t]
+    DevBuf<double> fdmS64, fdmT64;
+    DevBuf<float> fdmS32, fdmT32;
     DevBuf<int> class_cells; // a representative cell of every position class
     DevBuf<double> E64;      // levels of the coarse segment: element stiffness of the mean coefficient
     DevBuf<double> Me64;     // and the element mass
@@ -296,6 +300,174 @@ bool mean_stencil_disabled() {
     return v == 1;
 }
 
+// Levels with a constant mean coefficient compute their Vanka corrections by fast diagonalisation unless
+// SGHEAT_VANKA_FDM=0 (a measurement switch: the dense position-class inverses instead).  Read at every
+// smoothing call, so a process can compare both.
+bool vanka_fdm_disabled() {
+    const char* e = std::getenv("SGHEAT_VANKA_FDM");
+    return e && std::atoi(e) == 0;
+}
+
+// Generalised symmetric-definite eigenproblem A s = lambda B s of order m (row-major, B positive
+// definite): S (column i = eigenvector i, S^T B S = I, S^T A S = diag(lambda)), by the Cholesky factor
+// B = L L^T and cyclic Jacobi rotations of the symmetric C = L^{-1} A L^{-T} (Golub and Van Loan,
+// Matrix Computations, the symmetric Schur decomposition of Section 8.5).  false if B is not positive
+// definite.
+bool sym_gen_eig(int m, const std::vector<double>& A, const std::vector<double>& B, std::vector<double>& S,
+                 std::vector<double>& lam) {
+    std::vector<double> L((size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double v = B[(size_t)i * m + j];
+            for (int q = 0; q < j; ++q) v -= L[(size_t)i * m + q] * L[(size_t)j * m + q];
+            if (i == j) {
+                if (!(v > 0.0)) return false;
+                L[(size_t)i * m + i] = std::sqrt(v);
+            } else {
+                L[(size_t)i * m + j] = v / L[(size_t)j * m + j];
+            }
+        }
+    // Y = L^{-1} A (forward substitution, column by column), C = L^{-1} Y^T (A symmetric: C = C^T)
+    auto lsolve = [&](std::vector<double>& X) {   // X <- L^{-1} X, X row-major m x m
+        for (int c = 0; c < m; ++c)
+            for (int i = 0; i < m; ++i) {
+                double v = X[(size_t)i * m + c];
+                for (int q = 0; q < i; ++q) v -= L[(size_t)i * m + q] * X[(size_t)q * m + c];
+                X[(size_t)i * m + c] = v / L[(size_t)i * m + i];
+            }
+    };
+    std::vector<double> C(A);
+    lsolve(C);
+    for (int i = 0; i < m; ++i)
+        for (int j = i + 1; j < m; ++j) std::swap(C[(size_t)i * m + j], C[(size_t)j * m + i]);
+    lsolve(C);
+    for (int i = 0; i < m; ++i)                   // symmetrise the rounding
+        for (int j = i + 1; j < m; ++j) {
+            const double v = 0.5 * (C[(size_t)i * m + j] + C[(size_t)j * m + i]);
+            C[(size_t)i * m + j] = C[(size_t)j * m + i] = v;
+        }
+    std::vector<double> V((size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i) V[(size_t)i * m + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) {
+                const double v = C[(size_t)i * m + j] * C[(size_t)i * m + j];
+                tot += v;
+                if (i != j) off += v;
+            }
+        if (off <= 1e-32 * tot) break;
+        for (int p = 0; p < m; ++p)
+            for (int q = p + 1; q < m; ++q) {
+                const double apq = C[(size_t)p * m + q];
+                if (apq == 0.0) continue;
+                const double tau = (C[(size_t)q * m + q] - C[(size_t)p * m + p]) / (2.0 * apq);
+                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+                const double c = 1.0 / std::sqrt(1.0 + t * t), sn = t * c;
+                for (int i = 0; i < m; ++i) {     // C <- C J
+                    const double a = C[(size_t)i * m + p], b = C[(size_t)i * m + q];
+                    C[(size_t)i * m + p] = c * a - sn * b;
+                    C[(size_t)i * m + q] = sn * a + c * b;
+                }
+                for (int j = 0; j < m; ++j) {     // C <- J^T C
+                    const double a = C[(size_t)p * m + j], b = C[(size_t)q * m + j];
+                    C[(size_t)p * m + j] = c * a - sn * b;
+                    C[(size_t)q * m + j] = sn * a + c * b;
+                }
+                for (int i = 0; i < m; ++i) {     // V <- V J
+                    const double a = V[(size_t)i * m + p], b = V[(size_t)i * m + q];
+                    V[(size_t)i * m + p] = c * a - sn * b;
+                    V[(size_t)i * m + q] = sn * a + c * b;
+                }
+            }
+    }
+    lam.assign(m, 0.0);
+    for (int i = 0; i < m; ++i) lam[i] = C[(size_t)i * m + i];
+    // S = L^{-T} V (back substitution)
+    S.assign((size_t)m * m, 0.0);
+    for (int c = 0; c < m; ++c)
+        for (int i = m - 1; i >= 0; --i) {
+            double v = V[(size_t)i * m + c];
+            for (int q = i + 1; q < m; ++q) v -= L[(size_t)q * m + i] * S[(size_t)q * m + c];
+            S[(size_t)i * m + c] = v / L[(size_t)i * m + i];
+        }
+    return true;
+}
+
+// Tables of the fast-diagonalisation Vanka kernel for a level of n cells with constant mean
+// coefficient: the assembled 1D bands (stiffness times the coefficient) restricted to the interior
+// nodes of the first, an inner and the last cell, their generalised eigenvectors Sv[3][k+1][k+1]
+// (zero rows for Dirichlet nodes) and the inverted time blocks Tt[3^d][(k+1)^d][N_t][N_t] of
+// A_t + lambda_e B_t, lambda_e the sum of the 1D eigenvalues of eigen index e (zero blocks for unused
+// indices).  false if a restricted mass matrix is not positive definite or a time block is singular.
+bool fdm_tables(int dim, int n, int k, int NT, const std::vector<double>& At, const std::vector<double>& Bt,
+                const std::vector<double>& mb, const std::vector<double>& kb, std::vector<double>& Sv,
+                std::vector<double>& Tt) {
+    const int N1 = k + 1, n1 = n * k + 1, W = 2 * k + 1;
+    Sv.assign((size_t)3 * N1 * N1, 0.0);
+    std::vector<double> lam((size_t)3 * N1, 0.0);
+    int nint[3] = {0, 0, 0};
+    for (int v = 0; v < 3; ++v) {
+        const int pos = v == 0 ? 0 : (v == 1 ? std::min(1, n - 1) : n - 1);
+        std::vector<int> in;
+        for (int a = 0; a < N1; ++a) {
+            const int gi = pos * k + a;
+            if (gi != 0 && gi != n1 - 1) in.push_back(a);
+        }
+        const int m = (int)in.size();
+        nint[v] = m;
+        if (m == 0) continue;
+        std::vector<double> M((size_t)m * m), Kr((size_t)m * m), S, l;
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) {
+                const int gi = pos * k + in[i], gj = pos * k + in[j];
+                M[(size_t)i * m + j] = mb[(size_t)gi * W + (gj - gi + k)];
+                Kr[(size_t)i * m + j] = kb[(size_t)gi * W + (gj - gi + k)];
+            }
+        if (!sym_gen_eig(m, Kr, M, S, l)) return false;
+        for (int i = 0; i < m; ++i) {
+            lam[(size_t)v * N1 + i] = l[i];
+            for (int r = 0; r < m; ++r) Sv[((size_t)v * N1 + in[r]) * N1 + i] = S[(size_t)r * m + i];
+        }
+    }
+    const int ncls = ipow_h(3, dim), NP = ipow_h(N1, dim);
+    Tt.assign((size_t)ncls * NP * NT * NT, 0.0);
+    for (int cls = 0; cls < ncls; ++cls)
+        for (int e = 0; e < NP; ++e) {
+            double lsum = 0.0;
+            bool used = true;
+            for (int d = 0, cr = cls, er = e; d < dim; ++d, cr /= 3, er /= N1) {
+                used &= er % N1 < nint[cr % 3];
+                lsum += lam[(size_t)(cr % 3) * N1 + er % N1];
+            }
+            if (!used) continue;
+            // Gauss-Jordan with partial pivoting on [A_t + lambda B_t | I]
+            std::vector<double> a((size_t)NT * 2 * NT, 0.0);
+            for (int i = 0; i < NT; ++i) {
+                for (int j = 0; j < NT; ++j) a[(size_t)i * 2 * NT + j] = At[(size_t)i * NT + j] + (i == j ? lsum * Bt[i] : 0.0);
+                a[(size_t)i * 2 * NT + NT + i] = 1.0;
+            }
+            for (int c = 0; c < NT; ++c) {
+                int piv = c;
+                for (int i = c + 1; i < NT; ++i)
+                    if (std::fabs(a[(size_t)i * 2 * NT + c]) > std::fabs(a[(size_t)piv * 2 * NT + c])) piv = i;
+                if (a[(size_t)piv * 2 * NT + c] == 0.0) return false;
+                for (int j = 0; j < 2 * NT; ++j) std::swap(a[(size_t)c * 2 * NT + j], a[(size_t)piv * 2 * NT + j]);
+                const double ip = 1.0 / a[(size_t)c * 2 * NT + c];
+                for (int j = 0; j < 2 * NT; ++j) a[(size_t)c * 2 * NT + j] *= ip;
+                for (int i = 0; i < NT; ++i) {
+                    if (i == c) continue;
+                    const double f = a[(size_t)i * 2 * NT + c];
+                    for (int j = 0; j < 2 * NT; ++j) a[(size_t)i * 2 * NT + j] -= f * a[(size_t)c * 2 * NT + j];
+                }
+            }
+            for (int i = 0; i < NT; ++i)
+                for (int j = 0; j < NT; ++j)
+                    Tt[(((size_t)cls * NP + e) * NT + i) * NT + j] = a[(size_t)i * 2 * NT + NT + j];
+        }
+    return true;
+}
+
 // Assembled 1D mass and stiffness matrices of Q_k on n cells of width h, in band storage
 // band[i][d] = M1[i][i - k + d] (zero beyond the mesh): the Gauss-quadrature integrals of the GLL
 // basis on every cell, summed over the cells sharing a node.
@@ -376,10 +548,18 @@ sg_status set_coefficients(sg_handle h, const double* coef_qp) {
                 for (double& v : kb) v *= s0[0];
                 SG_TRY(lv.mb64.upload(mb.data(), mb.size(), "mean-block bands"));
                 SG_TRY(lv.kb64.upload(kb.data(), kb.size(), "mean-block bands"));
+                std::vector<double> fS, fT;
+                if (!fdm_tables(dim, lv.g.n, k, h->NT, h->At, h->Bt, mb, kb, fS, fT))
+                    return fail(SG_ESINGULAR, "a Vanka patch matrix is singular");
+                SG_TRY(lv.fdmS64.upload(fS.data(), fS.size(), "Vanka transforms"));
+                SG_TRY(lv.fdmT64.upload(fT.data(), fT.size(), "Vanka transforms"));
                 if (h->mixed) {
                     std::vector<float> m32(mb.begin(), mb.end()), k32(kb.begin(), kb.end());
                     SG_TRY(lv.mb32.upload(m32.data(), m32.size(), "mean-block bands"));
                     SG_TRY(lv.kb32.upload(k32.data(), k32.size(), "mean-block bands"));
+                    std::vector<float> s32(fS.begin(), fS.end()), t32(fT.begin(), fT.end());
+                    SG_TRY(lv.fdmS32.upload(s32.data(), s32.size(), "Vanka transforms"));
+                    SG_TRY(lv.fdmT32.upload(t32.data(), t32.size(), "Vanka transforms"));
                 }
             }
         }
@@ -866,6 +1046,8 @@ struct Prec<double> {
     static const double* cwm(const sg_handle h) { return h->cw_m64.p; }
     static const double* cwd(const sg_handle h) { return h->cw_d64.p; }
     static const double* inv(const Level& l) { return l.inv64.p; }
+    static const double* fdmS(const Level& l) { return l.fdmS64.p; }
+    static const double* fdmT(const Level& l) { return l.fdmT64.p; }
     static double* b(Level& l) { return l.b64.p; }
     static double* x(Level& l) { return l.x64.p; }
     static double* r(Level& l) { return l.r64.p; }
@@ -882,6 +1064,8 @@ struct Prec<float> {
     static const float* cwm(const sg_handle h) { return h->cw_m32.p; }
     static const float* cwd(const sg_handle h) { return h->cw_d32.p; }
     static const float* inv(const Level& l) { return l.inv32.p; }
+    static const float* fdmS(const Level& l) { return l.fdmS32.p; }
+    static const float* fdmT(const Level& l) { return l.fdmT32.p; }
     static float* b(Level& l) { return l.b32.p; }
     static float* x(Level& l) { return l.x32.p; }
     static float* r(Level& l) { return l.r32.p; }
@@ -1146,6 +1330,9 @@ sg_status smooth_level(sg_handle h, int l, const T* b, T* x, int sweeps, bool x_
         }
         if (h->diag)
             SG_HIP(launch_vanka_cells_modes<T>(h->d.dim, h->d.fe_degree, h->NT, lv.g, h->n_xi, inv, r, sbuf_as<T>(h), s));
+        else if (lv.mean_const && !vanka_fdm_disabled())
+            SG_HIP(launch_vanka_fdm<T>(h->d.dim, h->d.fe_degree, h->NT, lv.g, h->n_xi, Prec<T>::fdmS(lv),
+                                       Prec<T>::fdmT(lv), r, sbuf_as<T>(h), s));
         else
             SG_HIP(launch_vanka_cells<T>(h->d.dim, h->d.fe_degree, h->NT, lv.g, h->n_xi, inv, r, sbuf_as<T>(h),
                                          lv.inv_classes, s));

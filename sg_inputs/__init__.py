@@ -86,6 +86,8 @@ WORKLOADS = {
     # small meshes whose cell counts per direction are not multiples of the apply's tile widths
     "t3c2": Workload("t3c2", 3, 10, 2, 1, 1.0 / 10, 4, 3, 2, "sine"),
     "t3c3": Workload("t3c3", 3, 5, 3, 2, 1.0 / 5, 3, 4, 1, "sine"),
+    # the c3 discretisation on two levels (4 and 2 cells per direction): Vanka sweeps of Q3 dG(2) patches
+    "t3v3": Workload("t3v3", 3, 4, 3, 2, 1.0 / 4, 3, 4, 2, "sine"),
     # three-level hierarchies whose lower two levels form one persistent coarse segment
     "t2s3": Workload("t2s3", 2, 8, 3, 2, 0.02, 3, 2, 3, "sine"),
     "t3s2": Workload("t3s2", 3, 4, 2, 1, 0.05, 2, 2, 3, "sine"),

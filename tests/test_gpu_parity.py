@@ -115,6 +115,39 @@ def test_vanka_matches_oracle(torch_cuda, name):
         assert _rel_inf(xg.cpu().numpy(), ref) <= 1e-11, level
 
 
+@pytest.mark.parametrize("name", ["c1", "t2q1", "t2q4", "t2s3", "t3q1", "t3q2", "t3c2", "t3v3"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_vanka_fast_diagonalisation_matches_dense_inverses(torch_cuda, name, precision, monkeypatch):
+    """On levels with a constant mean coefficient the patch corrections come from the fast
+    diagonalisation of the Kronecker-structured patch matrices; SGHEAT_VANKA_FDM=0 switches the same
+    handle to the dense position-class inverses.  FP64: both sweeps within 1e-11 of the oracle's and
+    within 1e-12 of each other; FP32 (SG_MIXED, every level but the coarsest): both within 1e-4 of the
+    oracle's (single-precision rounding times patch condition numbers below 1e3)."""
+    torch = torch_cuda
+    w = sg_inputs.WORKLOADS[name]
+    H = hierarchy_from_workload(w)
+    G = _gpu(w, precision)
+    for level in range(w.n_levels - 1):
+        print(f"vanka fast diagonalisation {name} precision {precision} level {level}", flush=True)
+        n = G.n(level)
+        b = sg_inputs.uniform_vector(n, 51 + level)
+        x0 = sg_inputs.uniform_vector(n, 61 + level)
+        ref = H.smooth(level, b, x0, 2, w.n_chaos)
+        got = {}
+        for fdm in ("1", "0"):
+            monkeypatch.setenv("SGHEAT_VANKA_FDM", fdm)
+            xg = _to_gpu(torch, x0)
+            G.vanka_smooth(level, _to_gpu(torch, b), xg, sweeps=2)
+            got[fdm] = xg.cpu().numpy()
+        monkeypatch.delenv("SGHEAT_VANKA_FDM")
+        e_f, e_d = _rel_inf(got["1"], ref), _rel_inf(got["0"], ref)
+        print(f"  fdm {e_f:.3e}  dense {e_d:.3e}  between {_rel_inf(got['1'], got['0']):.3e}", flush=True)
+        tol = 1e-11 if precision == 0 else 1e-4
+        assert e_f <= tol and e_d <= tol, level
+        if precision == 0:
+            assert _rel_inf(got["1"], got["0"]) <= 1e-12, level
+
+
 @pytest.mark.parametrize("name", ["c1", "t2q2", "t2q3", "t2q4", "t3q1", "t3q2", "t2q2p4", "t3c2", "t2s3", "t3s2"])
 def test_vcycle_matches_oracle(torch_cuda, name):
     torch = torch_cuda
