@@ -157,11 +157,17 @@ hipError_t launch_vanka_cells_modes(int dim, int k, int nt, Grid g, int n_xi, co
 // transforms of the first / inner / last cell, Tt [3^d][(k+1)^d][N_t][N_t] inverted time blocks per
 // position class.  The modes go through LDS in passes of vanka_fdm_modes_per_pass.
 constexpr int kFdmLdsBudget = 32 * 1024;   // LDS per workgroup aimed at (several workgroups per CU)
+// LDS stride of one component: (k+1)^(d-1) x-lines of odd length (k+1) | 1
+inline int vanka_fdm_component_stride(int dim, int k) {
+    int nl = 1;
+    for (int d = 1; d < dim; ++d) nl *= k + 1;
+    return nl * ((k + 1) | 1);
+}
 inline int vanka_fdm_modes_per_pass(int dim, int k, int nt, int n_xi, size_t elem) {
     int np = 1;
     for (int d = 0; d < dim; ++d) np *= k + 1;
-    const long long per_mode = (long long)nt * (np | 1) * (long long)elem;
-    const long long tab = (long long)np * nt * nt * (long long)elem;
+    const long long per_mode = (long long)nt * vanka_fdm_component_stride(dim, k) * (long long)elem;
+    const long long tab = (long long)np * nt * nt * (long long)elem + 2LL * np * (long long)sizeof(int);
     long long mmax = (kFdmLdsBudget - tab) / per_mode;
     if (mmax < 1) mmax = 1;
     const long long passes = (n_xi + mmax - 1) / mmax;
@@ -170,7 +176,7 @@ inline int vanka_fdm_modes_per_pass(int dim, int k, int nt, int n_xi, size_t ele
 inline size_t vanka_fdm_lds_bytes(int dim, int k, int nt, int mp, size_t elem) {
     int np = 1;
     for (int d = 0; d < dim; ++d) np *= k + 1;
-    return ((size_t)np * nt * nt + (size_t)mp * nt * (np | 1)) * elem;
+    return ((size_t)np * nt * nt + (size_t)mp * nt * vanka_fdm_component_stride(dim, k)) * elem + 2 * np * sizeof(int);
 }
 template <typename T>
 hipError_t launch_vanka_fdm(int dim, int k, int nt, Grid g, int n_xi, const T* Sv, const T* Tt, const T* r,

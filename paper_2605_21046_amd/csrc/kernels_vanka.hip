@@ -767,14 +767,15 @@ template hipError_t launch_vanka_cells<float>(int, int, int, Grid, int, const fl
 //       along a direction (the 1D restriction is the same in every direction of the uniform mesh).
 //   Tt: [3^d classes][(k+1)^d eigen e][N_t][N_t], (A_t + lambda_e B_t)^{-1} (zero for unused e);
 //       class = sum_d 3^d variant_d.
-// One workgroup per cell.  The residual patch of up to `mp` modes is gathered into LDS (components
-// of odd stride P, so the line sweeps below hit different banks), transformed along every direction
+// One workgroup per cell.  The residual patch of up to `mp` modes is gathered into LDS (x-lines of odd
+// length, so the line sweeps below hit different banks), transformed along every direction
 // but the last in place, then the last direction, the time blocks and the inverse transform of the
 // last direction run in one sweep per (mode, line), and the remaining inverse transforms follow; the
 // result goes to the broken node array like k_vanka_cells' results.
 namespace {
 
 constexpr int kFdmThreads = 256;
+constexpr int kFdmBatch = 8;      // global loads a thread has in flight in the gather
 
 template <int DIM, int K, int NT, typename T>
 __global__ void __launch_bounds__(kFdmThreads)
@@ -782,12 +783,16 @@ __global__ void __launch_bounds__(kFdmThreads)
                 const T* __restrict__ r, T* __restrict__ s_out) {
     constexpr int N1 = K + 1;
     constexpr int NP = ipow(N1, DIM);
-    constexpr int P = NP | 1;                 // LDS stride of one component
     constexpr int NL = NP / N1;               // lines of one component along one direction
+    constexpr int LS = N1 | 1;                // LDS stride of an x-line (odd: the x sweeps hit different banks)
+    constexpr int PC = NL * LS;               // LDS stride of one component
     constexpr int NTT = NT * NT;
+    // all of it dynamic: a static array before it would leave the dynamic part unaligned for T
     extern __shared__ unsigned char smem_raw[];
     T* const tb = reinterpret_cast<T*>(smem_raw);   // [NP][NT][NT] of this cell's class
-    T* const X = tb + NP * NTT;                     // [mp * NT][P]
+    T* const X = tb + NP * NTT;                     // [mp * NT][PC], node p at (p / N1) LS + p % N1
+    int* const noff = reinterpret_cast<int*>(X + mp * NT * PC);   // [NP] 2 (node offset) + live
+    int* const boff = noff + NP;                                   // [NP] offset in the broken layout
 
     const int n_cells = (int)g.n_cells;
     const int pos = xcd_position(blockIdx.x, n_cells);
@@ -814,45 +819,71 @@ __global__ void __launch_bounds__(kFdmThreads)
     const int nn = (int)g.n_nodes;
     const T* const tc = Tt + (long long)cls * NP * NTT;
     for (int i = threadIdx.x; i < NP * NTT; i += kFdmThreads) tb[i] = tc[i];
+    for (int p = threadIdx.x; p < NP; p += kFdmThreads) {
+        int no = 0, bo = 0, live = 1;
+        for (int d = 0, pp = p, mn = 1, bm = 1; d < DIM; ++d, pp /= N1) {
+            const int id = cc[d] * K + pp % N1;
+            live &= (id != 0) & (id != g.n1 - 1);
+            no += (pp % N1) * mn;
+            bo += (pp % N1) * bm;
+            mn *= g.n1;
+            bm *= nb1;
+        }
+        noff[p] = 2 * no + live;
+        boff[p] = bo;
+    }
+    __syncthreads();
+    const T* const rc = r + node0;
+    T* const sc = s_out + brk0;
 
     for (int m0 = 0; m0 < n_xi; m0 += mp) {
         const int nm = min(mp, n_xi - m0);
         const int ncomp = nm * NT;
-        // gather: neighbouring threads read neighbouring nodes; Dirichlet values are zeroed
-        for (int idx = threadIdx.x; idx < ncomp * NP; idx += kFdmThreads) {
-            const int c = idx / NP, p = idx - c * NP;
-            int node = node0;
-            bool live = true;
-            for (int d = 0, pp = p, mn = 1; d < DIM; ++d, pp /= N1) {
-                const int id = cc[d] * K + pp % N1;
-                live &= (id != 0) & (id != g.n1 - 1);
-                node += (pp % N1) * mn;
-                mn *= g.n1;
+        const int total = ncomp * NP;
+        const T* const rp = rc + m0 * NT * nn;
+        // gather: neighbouring threads read neighbouring nodes, kFdmBatch loads in flight per thread
+        // (clamped to the last element where past the end); Dirichlet values are zeroed
+        for (int base = 0; base < total; base += kFdmBatch * kFdmThreads) {
+            T v[kFdmBatch];
+            int o[kFdmBatch];
+#pragma unroll
+            for (int u = 0; u < kFdmBatch; ++u) {
+                const int idx = min(base + u * kFdmThreads + (int)threadIdx.x, total - 1);
+                const int c = idx / NP, p = idx - c * NP;
+                o[u] = noff[p];
+                v[u] = rp[c * nn + (o[u] >> 1)];
             }
-            const T v = r[(m0 * NT + c) * nn + node];
-            X[c * P + p] = live ? v : T(0);
+#pragma unroll
+            for (int u = 0; u < kFdmBatch; ++u) {
+                const int idx = base + u * kFdmThreads + (int)threadIdx.x;
+                if (idx < total) {
+                    const int c = idx / NP, p = idx - c * NP;
+                    X[c * PC + (p / N1) * LS + p % N1] = (o[u] & 1) ? v[u] : T(0);
+                }
+            }
         }
         __syncthreads();
         // forward transforms along every direction but the last: u_i = sum_j S[j][i] v_j
 #pragma unroll
         for (int d = 0; d < DIM - 1; ++d) {
-            const int st = ipow(N1, d);
+            const int st = ipow(N1, d);                  // node stride of direction d
+            const int ls = d == 0 ? 1 : (st / N1) * LS;  // its LDS stride
             T S[N1 * N1];
 #pragma unroll
             for (int i = 0; i < N1 * N1; ++i) S[i] = Sd[d][i];
             for (int it = threadIdx.x; it < ncomp * NL; it += kFdmThreads) {
                 const int c = it / NL, q = it - c * NL;
-                const int lo = q % st, hi = q / st;
-                T* const line = X + c * P + lo + hi * st * N1;
+                const int pb = q % st + (q / st) * st * N1;
+                T* const line = X + c * PC + (pb / N1) * LS + pb % N1;
                 T v[N1];
 #pragma unroll
-                for (int j = 0; j < N1; ++j) v[j] = line[j * st];
+                for (int j = 0; j < N1; ++j) v[j] = line[j * ls];
 #pragma unroll
                 for (int i = 0; i < N1; ++i) {
                     T u = T(0);
 #pragma unroll
                     for (int j = 0; j < N1; ++j) u += S[j * N1 + i] * v[j];
-                    line[i * st] = u;
+                    line[i * ls] = u;
                 }
             }
             __syncthreads();
@@ -860,18 +891,20 @@ __global__ void __launch_bounds__(kFdmThreads)
         // last direction: forward transform, the time block of every eigen index, inverse transform
         {
             constexpr int st = NL;
+            constexpr int ls = DIM == 1 ? 1 : (NL / N1) * LS;
             T S[N1 * N1];
 #pragma unroll
             for (int i = 0; i < N1 * N1; ++i) S[i] = Sd[DIM - 1][i];
             for (int it = threadIdx.x; it < nm * NL; it += kFdmThreads) {
                 const int ml = it / NL, q = it - ml * NL;
+                const int qo = (q / N1) * LS + q % N1;
                 T u[NT][N1];
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
-                    const T* const line = X + (ml * NT + t) * P + q;
+                    const T* const line = X + (ml * NT + t) * PC + qo;
                     T v[N1];
 #pragma unroll
-                    for (int j = 0; j < N1; ++j) v[j] = line[j * st];
+                    for (int j = 0; j < N1; ++j) v[j] = line[j * ls];
 #pragma unroll
                     for (int i = 0; i < N1; ++i) {
                         T a = T(0);
@@ -894,13 +927,13 @@ __global__ void __launch_bounds__(kFdmThreads)
                 }
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
-                    T* const line = X + (ml * NT + t) * P + q;
+                    T* const line = X + (ml * NT + t) * PC + qo;
 #pragma unroll
                     for (int j = 0; j < N1; ++j) {
                         T a = T(0);
 #pragma unroll
                         for (int i = 0; i < N1; ++i) a += S[j * N1 + i] * w[t][i];
-                        line[j * st] = a;
+                        line[j * ls] = a;
                     }
                 }
             }
@@ -910,35 +943,33 @@ __global__ void __launch_bounds__(kFdmThreads)
 #pragma unroll
         for (int d = DIM - 2; d >= 0; --d) {
             const int st = ipow(N1, d);
+            const int ls = d == 0 ? 1 : (st / N1) * LS;
             T S[N1 * N1];
 #pragma unroll
             for (int i = 0; i < N1 * N1; ++i) S[i] = Sd[d][i];
             for (int it = threadIdx.x; it < ncomp * NL; it += kFdmThreads) {
                 const int c = it / NL, q = it - c * NL;
-                const int lo = q % st, hi = q / st;
-                T* const line = X + c * P + lo + hi * st * N1;
+                const int pb = q % st + (q / st) * st * N1;
+                T* const line = X + c * PC + (pb / N1) * LS + pb % N1;
                 T w[N1];
 #pragma unroll
-                for (int i = 0; i < N1; ++i) w[i] = line[i * st];
+                for (int i = 0; i < N1; ++i) w[i] = line[i * ls];
 #pragma unroll
                 for (int j = 0; j < N1; ++j) {
                     T a = T(0);
 #pragma unroll
                     for (int i = 0; i < N1; ++i) a += S[j * N1 + i] * w[i];
-                    line[j * st] = a;
+                    line[j * ls] = a;
                 }
             }
             __syncthreads();
         }
         // store into the broken layout [comp][b_z][b_y][b_x]
-        for (int idx = threadIdx.x; idx < ncomp * NP; idx += kFdmThreads) {
+        T* const sp = sc + m0 * NT * nbn;
+#pragma unroll 4
+        for (int idx = threadIdx.x; idx < total; idx += kFdmThreads) {
             const int c = idx / NP, p = idx - c * NP;
-            int b = brk0;
-            for (int d = 0, pp = p, bm = 1; d < DIM; ++d, pp /= N1) {
-                b += (pp % N1) * bm;
-                bm *= nb1;
-            }
-            s_out[(m0 * NT + c) * nbn + b] = X[c * P + p];
+            sp[c * nbn + boff[p]] = X[c * PC + (p / N1) * LS + p % N1];
         }
         __syncthreads();                          // the next pass reuses X
     }
@@ -958,7 +989,6 @@ hipError_t run_vanka_fdm(Grid g, int n_xi, const T* Sv, const T* Tt, const T* r,
     auto kern = k_vanka_fdm<DIM, K, NT, T>;
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    (void)NP;
     hipLaunchKernelGGL(kern, dim3((unsigned)g.n_cells), dim3(kFdmThreads), lds, s, g, n_xi, mp, Sv, Tt, r, s_out);
     return hipGetLastError();
 }
