@@ -167,7 +167,7 @@ inline int vanka_fdm_modes_per_pass(int dim, int k, int nt, int n_xi, size_t ele
     int np = 1;
     for (int d = 0; d < dim; ++d) np *= k + 1;
     const long long per_mode = (long long)nt * vanka_fdm_component_stride(dim, k) * (long long)elem;
-    const long long tab = (long long)np * nt * nt * (long long)elem + 2LL * np * (long long)sizeof(int);
+    const long long tab = (long long)np * nt * nt * (long long)elem;
     long long mmax = (kFdmLdsBudget - tab) / per_mode;
     if (mmax < 1) mmax = 1;
     const long long passes = (n_xi + mmax - 1) / mmax;
@@ -176,7 +176,7 @@ inline int vanka_fdm_modes_per_pass(int dim, int k, int nt, int n_xi, size_t ele
 inline size_t vanka_fdm_lds_bytes(int dim, int k, int nt, int mp, size_t elem) {
     int np = 1;
     for (int d = 0; d < dim; ++d) np *= k + 1;
-    return ((size_t)np * nt * nt + (size_t)mp * nt * vanka_fdm_component_stride(dim, k)) * elem + 2 * np * sizeof(int);
+    return ((size_t)np * nt * nt + (size_t)mp * nt * vanka_fdm_component_stride(dim, k)) * elem;
 }
 template <typename T>
 hipError_t launch_vanka_fdm(int dim, int k, int nt, Grid g, int n_xi, const T* Sv, const T* Tt, const T* r,

@@ -777,6 +777,8 @@ namespace {
 constexpr int kFdmThreads = 256;
 constexpr int kFdmBatch = 8;      // global loads a thread has in flight in the gather
 
+// Every thread keeps one node p of the cell (gather and store) and one line q (the sweeps) for the
+// whole launch and walks the components: the index arithmetic is done once, not per element.
 template <int DIM, int K, int NT, typename T>
 __global__ void __launch_bounds__(kFdmThreads)
     k_vanka_fdm(Grid g, int n_xi, int mp, const T* __restrict__ Sv, const T* __restrict__ Tt,
@@ -787,12 +789,12 @@ __global__ void __launch_bounds__(kFdmThreads)
     constexpr int LS = N1 | 1;                // LDS stride of an x-line (odd: the x sweeps hit different banks)
     constexpr int PC = NL * LS;               // LDS stride of one component
     constexpr int NTT = NT * NT;
-    // all of it dynamic: a static array before it would leave the dynamic part unaligned for T
-    extern __shared__ unsigned char smem_raw[];
+    constexpr int GP = kFdmThreads / NP;      // components per round of the gather and the store
+    constexpr int GL = kFdmThreads / NL;      // components (modes in the last sweep) per round of a sweep
+    static_assert(GP >= 1 && GL >= 1, "one cell's nodes must fit the workgroup");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     T* const tb = reinterpret_cast<T*>(smem_raw);   // [NP][NT][NT] of this cell's class
     T* const X = tb + NP * NTT;                     // [mp * NT][PC], node p at (p / N1) LS + p % N1
-    int* const noff = reinterpret_cast<int*>(X + mp * NT * PC);   // [NP] 2 (node offset) + live
-    int* const boff = noff + NP;                                   // [NP] offset in the broken layout
 
     const int n_cells = (int)g.n_cells;
     const int pos = xcd_position(blockIdx.x, n_cells);
@@ -819,46 +821,46 @@ __global__ void __launch_bounds__(kFdmThreads)
     const int nn = (int)g.n_nodes;
     const T* const tc = Tt + (long long)cls * NP * NTT;
     for (int i = threadIdx.x; i < NP * NTT; i += kFdmThreads) tb[i] = tc[i];
-    for (int p = threadIdx.x; p < NP; p += kFdmThreads) {
-        int no = 0, bo = 0, live = 1;
-        for (int d = 0, pp = p, mn = 1, bm = 1; d < DIM; ++d, pp /= N1) {
-            const int id = cc[d] * K + pp % N1;
-            live &= (id != 0) & (id != g.n1 - 1);
-            no += (pp % N1) * mn;
-            bo += (pp % N1) * bm;
-            mn *= g.n1;
-            bm *= nb1;
-        }
-        noff[p] = 2 * no + live;
-        boff[p] = bo;
+
+    // node role: node tp of the cell for components tg, tg + GP, ...
+    const int tp = threadIdx.x % NP, tg = threadIdx.x / NP;
+    int noff = 0, boff = 0;
+    bool live = true;
+    for (int d = 0, pp = tp, mn = 1, bm = 1; d < DIM; ++d, pp /= N1) {
+        const int id = cc[d] * K + pp % N1;
+        live &= (id != 0) & (id != g.n1 - 1);
+        noff += (pp % N1) * mn;
+        boff += (pp % N1) * bm;
+        mn *= g.n1;
+        bm *= nb1;
+    }
+    const int lpos = (tp / N1) * LS + tp % N1;
+    // line role: line tq of components tl, tl + GL, ... (LDS offset of its first node per direction)
+    const int tq = threadIdx.x % NL, tl = threadIdx.x / NL;
+    int lbase[3];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const int st = ipow(N1, d);
+        const int pb = d == DIM - 1 ? tq : tq % st + (tq / st) * st * N1;
+        lbase[d] = (pb / N1) * LS + pb % N1;
     }
     __syncthreads();
-    const T* const rc = r + node0;
-    T* const sc = s_out + brk0;
 
     for (int m0 = 0; m0 < n_xi; m0 += mp) {
         const int nm = min(mp, n_xi - m0);
         const int ncomp = nm * NT;
-        const int total = ncomp * NP;
-        const T* const rp = rc + m0 * NT * nn;
+        const T* const rp = r + node0 + noff + m0 * NT * nn;
         // gather: neighbouring threads read neighbouring nodes, kFdmBatch loads in flight per thread
-        // (clamped to the last element where past the end); Dirichlet values are zeroed
-        for (int base = 0; base < total; base += kFdmBatch * kFdmThreads) {
-            T v[kFdmBatch];
-            int o[kFdmBatch];
+        // (clamped to the last component where past the end); Dirichlet values are zeroed
+        if (tg < GP) {
+            for (int cb = tg; cb < ncomp; cb += GP * kFdmBatch) {
+                T v[kFdmBatch];
 #pragma unroll
-            for (int u = 0; u < kFdmBatch; ++u) {
-                const int idx = min(base + u * kFdmThreads + (int)threadIdx.x, total - 1);
-                const int c = idx / NP, p = idx - c * NP;
-                o[u] = noff[p];
-                v[u] = rp[c * nn + (o[u] >> 1)];
-            }
+                for (int u = 0; u < kFdmBatch; ++u) v[u] = rp[min(cb + u * GP, ncomp - 1) * nn];
 #pragma unroll
-            for (int u = 0; u < kFdmBatch; ++u) {
-                const int idx = base + u * kFdmThreads + (int)threadIdx.x;
-                if (idx < total) {
-                    const int c = idx / NP, p = idx - c * NP;
-                    X[c * PC + (p / N1) * LS + p % N1] = (o[u] & 1) ? v[u] : T(0);
+                for (int u = 0; u < kFdmBatch; ++u) {
+                    const int c = cb + u * GP;
+                    if (c < ncomp) X[c * PC + lpos] = live ? v[u] : T(0);
                 }
             }
         }
@@ -866,24 +868,23 @@ __global__ void __launch_bounds__(kFdmThreads)
         // forward transforms along every direction but the last: u_i = sum_j S[j][i] v_j
 #pragma unroll
         for (int d = 0; d < DIM - 1; ++d) {
-            const int st = ipow(N1, d);                  // node stride of direction d
-            const int ls = d == 0 ? 1 : (st / N1) * LS;  // its LDS stride
+            const int ls = d == 0 ? 1 : (ipow(N1, d) / N1) * LS;   // LDS stride of direction d
             T S[N1 * N1];
 #pragma unroll
             for (int i = 0; i < N1 * N1; ++i) S[i] = Sd[d][i];
-            for (int it = threadIdx.x; it < ncomp * NL; it += kFdmThreads) {
-                const int c = it / NL, q = it - c * NL;
-                const int pb = q % st + (q / st) * st * N1;
-                T* const line = X + c * PC + (pb / N1) * LS + pb % N1;
-                T v[N1];
+            if (tl < GL) {
+                for (int c = tl; c < ncomp; c += GL) {
+                    T* const line = X + c * PC + lbase[d];
+                    T v[N1];
 #pragma unroll
-                for (int j = 0; j < N1; ++j) v[j] = line[j * ls];
+                    for (int j = 0; j < N1; ++j) v[j] = line[j * ls];
 #pragma unroll
-                for (int i = 0; i < N1; ++i) {
-                    T u = T(0);
+                    for (int i = 0; i < N1; ++i) {
+                        T u = T(0);
 #pragma unroll
-                    for (int j = 0; j < N1; ++j) u += S[j * N1 + i] * v[j];
-                    line[i * ls] = u;
+                        for (int j = 0; j < N1; ++j) u += S[j * N1 + i] * v[j];
+                        line[i * ls] = u;
+                    }
                 }
             }
             __syncthreads();
@@ -895,45 +896,45 @@ __global__ void __launch_bounds__(kFdmThreads)
             T S[N1 * N1];
 #pragma unroll
             for (int i = 0; i < N1 * N1; ++i) S[i] = Sd[DIM - 1][i];
-            for (int it = threadIdx.x; it < nm * NL; it += kFdmThreads) {
-                const int ml = it / NL, q = it - ml * NL;
-                const int qo = (q / N1) * LS + q % N1;
-                T u[NT][N1];
-#pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    const T* const line = X + (ml * NT + t) * PC + qo;
-                    T v[N1];
-#pragma unroll
-                    for (int j = 0; j < N1; ++j) v[j] = line[j * ls];
-#pragma unroll
-                    for (int i = 0; i < N1; ++i) {
-                        T a = T(0);
-#pragma unroll
-                        for (int j = 0; j < N1; ++j) a += S[j * N1 + i] * v[j];
-                        u[t][i] = a;
-                    }
-                }
-                T w[NT][N1];
-#pragma unroll
-                for (int i = 0; i < N1; ++i) {
-                    const T* const te = tb + (q + i * st) * NTT;
+            if (tl < GL) {
+                for (int ml = tl; ml < nm; ml += GL) {
+                    T u[NT][N1];
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
-                        T a = T(0);
+                        const T* const line = X + (ml * NT + t) * PC + lbase[DIM - 1];
+                        T v[N1];
 #pragma unroll
-                        for (int t2 = 0; t2 < NT; ++t2) a += te[t * NT + t2] * u[t2][i];
-                        w[t][i] = a;
+                        for (int j = 0; j < N1; ++j) v[j] = line[j * ls];
+#pragma unroll
+                        for (int i = 0; i < N1; ++i) {
+                            T a = T(0);
+#pragma unroll
+                            for (int j = 0; j < N1; ++j) a += S[j * N1 + i] * v[j];
+                            u[t][i] = a;
+                        }
                     }
-                }
+                    T w[NT][N1];
 #pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    T* const line = X + (ml * NT + t) * PC + qo;
+                    for (int i = 0; i < N1; ++i) {
+                        const T* const te = tb + (tq + i * st) * NTT;
 #pragma unroll
-                    for (int j = 0; j < N1; ++j) {
-                        T a = T(0);
+                        for (int t = 0; t < NT; ++t) {
+                            T a = T(0);
 #pragma unroll
-                        for (int i = 0; i < N1; ++i) a += S[j * N1 + i] * w[t][i];
-                        line[j * ls] = a;
+                            for (int t2 = 0; t2 < NT; ++t2) a += te[t * NT + t2] * u[t2][i];
+                            w[t][i] = a;
+                        }
+                    }
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        T* const line = X + (ml * NT + t) * PC + lbase[DIM - 1];
+#pragma unroll
+                        for (int j = 0; j < N1; ++j) {
+                            T a = T(0);
+#pragma unroll
+                            for (int i = 0; i < N1; ++i) a += S[j * N1 + i] * w[t][i];
+                            line[j * ls] = a;
+                        }
                     }
                 }
             }
@@ -942,34 +943,32 @@ __global__ void __launch_bounds__(kFdmThreads)
         // inverse transforms along the other directions: o_j = sum_i S[j][i] w_i
 #pragma unroll
         for (int d = DIM - 2; d >= 0; --d) {
-            const int st = ipow(N1, d);
-            const int ls = d == 0 ? 1 : (st / N1) * LS;
+            const int ls = d == 0 ? 1 : (ipow(N1, d) / N1) * LS;
             T S[N1 * N1];
 #pragma unroll
             for (int i = 0; i < N1 * N1; ++i) S[i] = Sd[d][i];
-            for (int it = threadIdx.x; it < ncomp * NL; it += kFdmThreads) {
-                const int c = it / NL, q = it - c * NL;
-                const int pb = q % st + (q / st) * st * N1;
-                T* const line = X + c * PC + (pb / N1) * LS + pb % N1;
-                T w[N1];
+            if (tl < GL) {
+                for (int c = tl; c < ncomp; c += GL) {
+                    T* const line = X + c * PC + lbase[d];
+                    T w[N1];
 #pragma unroll
-                for (int i = 0; i < N1; ++i) w[i] = line[i * ls];
+                    for (int i = 0; i < N1; ++i) w[i] = line[i * ls];
 #pragma unroll
-                for (int j = 0; j < N1; ++j) {
-                    T a = T(0);
+                    for (int j = 0; j < N1; ++j) {
+                        T a = T(0);
 #pragma unroll
-                    for (int i = 0; i < N1; ++i) a += S[j * N1 + i] * w[i];
-                    line[j * ls] = a;
+                        for (int i = 0; i < N1; ++i) a += S[j * N1 + i] * w[i];
+                        line[j * ls] = a;
+                    }
                 }
             }
             __syncthreads();
         }
         // store into the broken layout [comp][b_z][b_y][b_x]
-        T* const sp = sc + m0 * NT * nbn;
+        if (tg < GP) {
+            T* const sp = s_out + brk0 + boff + m0 * NT * nbn;
 #pragma unroll 4
-        for (int idx = threadIdx.x; idx < total; idx += kFdmThreads) {
-            const int c = idx / NP, p = idx - c * NP;
-            sp[c * nbn + boff[p]] = X[c * PC + (p / N1) * LS + p % N1];
+            for (int c = tg; c < ncomp; c += GP) sp[c * nbn] = X[c * PC + lpos];
         }
         __syncthreads();                          // the next pass reuses X
     }
