@@ -44,8 +44,8 @@ APPLY_SOURCES = ["device_common.hpp", "kernels.hpp", "apply_impl.hpp", "apply_3d
 # is measured again.
 MEASURED_TRAFFIC = {
     # profiles/sg_apply_c2_c3_hbm_traffic.md
-    ("c2", "308a06b2f18b99f3", 3): {"fetch_bytes": 646070710, "write_bytes": 547065205},
-    ("c3", "308a06b2f18b99f3", 2): {"fetch_bytes": 1240629079, "write_bytes": 1000738377},
+    ("c2", "1b46a8139eecfcd1", 3): {"fetch_bytes": 645759813, "write_bytes": 547506107},
+    ("c3", "1b46a8139eecfcd1", 2): {"fetch_bytes": 1240206822, "write_bytes": 1001330517},
 }
 
 
@@ -537,6 +537,34 @@ def run_workload(torch, dev, stream, sgheat, sg_inputs, w, args, src_hash):
     return leg
 
 
+def vanka_sweeps(torch, dev, sgheat, sg_inputs, names, reps):
+    """Finest-level Vanka sweeps (residual, patch corrections, update gather) of each workload in FP64 and
+    with SG_MIXED (FP32 sweeps), with the fast-diagonalisation corrections (SGHEAT_VANKA_FDM unset) and
+    with the dense position-class inverses (SGHEAT_VANKA_FDM=0); 20 untimed sweeps first."""
+    for name in names:
+        w = sg_inputs.WORKLOADS[name]
+        for prec, label in ((sgheat.SG_FP64, "fp64"), (sgheat.SG_MIXED, "mixed")):
+            G = sgheat.problem_from_workload(w, prec)
+            n = G.n(0)
+            b = torch.from_numpy(sg_inputs.uniform_vector(n, 5)).to(dev)
+            x = torch.zeros(n, dtype=torch.float64, device=dev)
+            for fdm in ("1", "0"):
+                os.environ["SGHEAT_VANKA_FDM"] = fdm
+                G.vanka_smooth(0, b, x, sweeps=20)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                G.vanka_smooth(0, b, x, sweeps=reps)
+                e1.record()
+                torch.cuda.synchronize()
+                kind = "fast diagonalisation" if fdm == "1" else "dense inverses"
+                print(f"[bench] {name} {label} Vanka sweep ({kind}): {e0.elapsed_time(e1) / reps * 1e3:.1f} us",
+                      file=sys.stderr, flush=True)
+            os.environ.pop("SGHEAT_VANKA_FDM", None)
+            del G
+            torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -563,6 +591,10 @@ def main():
                     help="march only the first N of the 64 slabs of the finite-chaos benchmark (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy 5 times (reference for the HBM byte counters)")
+    ap.add_argument("--vanka-sweeps", default=None, metavar="W[,W]",
+                    help="only time finest-level Vanka sweeps of these workloads (FP64 and mixed), with the "
+                         "fast-diagonalisation patch corrections and with the dense position-class inverses")
+    ap.add_argument("--vanka-reps", type=int, default=5, help="timed sweeps per --vanka-sweeps case")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
@@ -581,6 +613,9 @@ def main():
             c.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": a.numel() * 8, "copy_calibration_bytes_written": c.numel() * 8}))
+        return
+    if args.vanka_sweeps:
+        vanka_sweeps(torch, dev, sgheat, sg_inputs, args.vanka_sweeps.split(","), args.vanka_reps)
         return
     w = sg_inputs.WORKLOADS[args.workload]
     stream = torch.cuda.current_stream()
