@@ -154,6 +154,11 @@ sg_status sg_operator_apply_noalloc(sg_handle h, const double* x, double* y, voi
  * A_t (x) M_x + B_t (x) K_{a_0} (Remark solver-matrix-free-sg), or with desc.diag_blocks = 1 on the
  * block-diagonal operator diag_alpha(A_alpha) with each mode's own patch inverses:
  *     x <- x + omega sum_K R_K^T W_K A_{0,K}^{-1} R_K (b - A_0 x),   then x_D = b_D on Dirichlet DoFs.
+ * A_{0,K}^{-1} is the exact patch inverse: on a level whose mean coefficient is one constant it is
+ * applied by fast diagonalisation of the patch matrix (a Kronecker product of the cell's restricted 1D
+ * mass and stiffness matrices with A_t, B_t: generalised eigenvectors per direction, one N_t x N_t
+ * time block per eigen index), otherwise as the dense inverse formed at set-up; the two agree up to
+ * rounding (the environment variable SGHEAT_VANKA_FDM=0 selects the dense one everywhere).
  * b and x are FP64 on every level; with SG_MIXED the sweep runs in FP32 internally for level 0 and
  * the levels above the coarsest.  x is updated in place.  Asynchronous on the stream. */
 sg_status sg_vanka_smooth(sg_handle h, int level, const double* b, double* x, int sweeps, void* hip_stream);
