@@ -25,6 +25,7 @@
 // branch would make the next use wait for the previous plane's stores too.  The Dirichlet rows
 // (y = x, or b - x for the residual form) are written by a separate pass over the boundary nodes.
 #include <algorithm>
+#include <cstdlib>
 
 #include "kernels.hpp"
 
@@ -400,11 +401,18 @@ size_t stencil_lds_bytes(const StencilArgs& a, int elem) {
 }
 
 bool stencil_fits(StencilArgs& a, int elem) {
-    // rows per workgroup: as many as the positions of the z march (3D) and 160 KB of LDS allow, up to 8
+    // rows per workgroup: as many as the positions of the z march (3D) and 160 KB of LDS allow, up to 8.
+    // z planes per workgroup: about 16 (SGHEAT_STENCIL_ZC overrides; a measurement switch), split evenly:
+    // each workgroup loads 2k window planes before its first output plane, so longer chunks read less
+    // (chunks of 8: c3 FP64 678 us, 15: 608 us, 19: 630 us, the last with a worse final round of
+    // workgroups; c2 FP64 251 / 241 / 237 us at 8 / 13 / 22)
     const int k = a.k;
+    int zt = 16;
+    if (const char* e = std::getenv("SGHEAT_STENCIL_ZC")) zt = std::max(1, std::atoi(e));
+    const int nzc = (a.n1 + zt - 1) / zt;
     for (int ty = 8; ty >= 1; --ty) {
         a.ty = ty;
-        a.zc = 8;
+        a.zc = (a.n1 + nzc - 1) / nzc;
         if (a.dim == 3 && (long long)(ty + 2 * k) * a.n1 > kStSlots) continue;
         if (a.dim == 3 && (long long)ty * a.n1 > kStSlots) continue;
         if (stencil_lds_bytes(a, elem) > 160 * 1024) continue;
