@@ -265,8 +265,12 @@ hipError_t launch_coarse_solve(const double* AinvT, long long inv_stride, int ni
 // ---- vector kernels (FP64 unless noted) -----------------------------------------------------------
 hipError_t launch_multidot(const double* V, long long ldv, int k, const double* w, long long n,
                            double* partial, int nblk, hipStream_t s);
+// wout = w - sum_j h[j] V[j] (j < k) with, by mode: partial sums of V[j]^T wout and of |wout|^2
+// (partial[blk][k + 1]); of |wout|^2 only (partial[blk]); or none, wout divided by
+// sqrt(h[k] - sum_j h[j]^2) (the norm by Pythagoras when h[k] = |w|^2 and V is orthonormal)
+constexpr int kUpdDotNorm = 0, kUpdNorm = 1, kUpdScaled = 2;
 hipError_t launch_update_dot(const double* V, long long ldv, int k, const double* h, const double* w,
-                             double* wout, long long n, double* partial, int nblk, bool dot,
+                             double* wout, long long n, double* partial, int nblk, int mode,
                              hipStream_t s);
 hipError_t launch_reduce_partials(const double* partial, int nblk, int k, double* out, hipStream_t s);
 hipError_t launch_multi_axpy(const double* V, long long ldv, int k, const double* y, double* x,

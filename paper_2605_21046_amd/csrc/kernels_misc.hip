@@ -389,12 +389,16 @@ __global__ void __launch_bounds__(kDotThreads)
     }
 }
 
-// wout = w - sum_j h[j] V[j]; if dot, partial[blk][j] = sum V[j] wout (j < k), else partial[blk][0] = |wout|^2
+// wout = w - sum_j h[j] V[j], and by mode:
+//   kUpdDotNorm: partial[blk][j] = sum V[j] wout (j < k) and partial[blk][k] = |wout|^2;
+//   kUpdNorm:    partial[blk][0] = |wout|^2;
+//   kUpdScaled:  wout is divided by hn = sqrt(h[k] - sum_j h[j]^2) (h[k] = |w|^2, V orthonormal: the
+//                norm of the updated vector by Pythagoras; 0 where that is not positive), no partials.
 template <int KMAX>
 __global__ void __launch_bounds__(kDotThreads)
     k_update_dot(const double* __restrict__ V, long long ldv, int k, const double* __restrict__ h,
                  const double* __restrict__ w, double* __restrict__ wout, long long n, double* __restrict__ partial,
-                 bool dot) {
+                 int mode) {
     __shared__ double sh[kDotThreads];
     double hc[KMAX];
     double acc[KMAX];
@@ -402,6 +406,13 @@ __global__ void __launch_bounds__(kDotThreads)
     for (int j = 0; j < KMAX; ++j) {
         hc[j] = j < k ? h[j] : 0.0;
         acc[j] = 0.0;
+    }
+    double scale = 1.0;
+    if (mode == kUpdScaled) {
+        double ss = 0.0;
+        for (int j = 0; j < k; ++j) ss += h[j] * h[j];
+        const double hn2 = h[k] - ss;
+        scale = hn2 > 0.0 ? 1.0 / sqrt(hn2) : 0.0;
     }
     double nrm = 0.0;
     for (long long i = blockIdx.x * (long long)kDotThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kDotThreads) {
@@ -412,23 +423,24 @@ __global__ void __launch_bounds__(kDotThreads)
             v[j] = j < k ? V[j * ldv + i] : 0.0;
             s -= hc[j] * v[j];
         }
-        wout[i] = s;
-        if (dot) {
+        wout[i] = mode == kUpdScaled ? s * scale : s;
+        if (mode == kUpdDotNorm) {
 #pragma unroll
             for (int j = 0; j < KMAX; ++j) acc[j] += v[j] * s;
-        } else {
-            nrm += s * s;
         }
+        nrm += s * s;
     }
-    if (dot) {
+    if (mode == kUpdDotNorm) {
         for (int j = 0; j < k; ++j) {
             double a = 0.0;
 #pragma unroll
             for (int u = 0; u < KMAX; ++u) if (u == j) a = acc[u];
             const double sum = block_sum(a, sh);
-            if (threadIdx.x == 0) partial[(long long)blockIdx.x * k + j] = sum;
+            if (threadIdx.x == 0) partial[(long long)blockIdx.x * (k + 1) + j] = sum;
         }
-    } else {
+        const double sum = block_sum(nrm, sh);
+        if (threadIdx.x == 0) partial[(long long)blockIdx.x * (k + 1) + k] = sum;
+    } else if (mode == kUpdNorm) {
         const double sum = block_sum(nrm, sh);
         if (threadIdx.x == 0) partial[blockIdx.x] = sum;
     }
@@ -611,10 +623,11 @@ hipError_t launch_multidot(const double* V, long long ldv, int k, const double* 
 }
 
 hipError_t launch_update_dot(const double* V, long long ldv, int k, const double* h, const double* w, double* wout,
-                             long long n, double* partial, int nblk, bool dot, hipStream_t s) {
+                             long long n, double* partial, int nblk, int mode, hipStream_t s) {
+    if (mode != kUpdDotNorm && mode != kUpdNorm && mode != kUpdScaled) return hipErrorInvalidValue;
 #define SG_UD(KM)                                                                                               \
     if (k <= KM) {                                                                                              \
-        hipLaunchKernelGGL((k_update_dot<KM>), dim3(nblk), dim3(kDotThreads), 0, s, V, ldv, k, h, w, wout, n, partial, dot); \
+        hipLaunchKernelGGL((k_update_dot<KM>), dim3(nblk), dim3(kDotThreads), 0, s, V, ldv, k, h, w, wout, n, partial, mode); \
         return hipGetLastError();                                                                              \
     }
     SG_UD(8)

@@ -1756,19 +1756,22 @@ sg_status fgmres_solve_slab(sg_handle h, const double* b, double* x, double rtol
                 inf.applies++;
                 const int kk = j + 1;
                 double* d_h1 = h->dscal.p;
-                double* d_h2 = h->dscal.p + 80;
-                double* d_nr = h->dscal.p + 160;
+                double* d_h2 = h->dscal.p + 80;       // h2, then |w'|^2
                 double* vnext = V + (size_t)(j + 1) * n;
-                // CGS2: h1 = V^T w; w' = w - V h1, h2 = V^T w'; w'' = w' - V h2, |w''|^2
+                // CGS2: h1 = V^T w; w' = w - V h1 with h2 = V^T w' and |w'|^2 in the same pass;
+                // v = (w' - V h2) / hn with hn^2 = |w'|^2 - |h2|^2 (Pythagoras: V orthonormal), so the new
+                // basis vector is written normalised in the last pass
                 SG_HIP(launch_multidot(V, n, kk, h->w1.p, n, h->partial.p, kDotBlocks, s));
                 SG_HIP(launch_reduce_partials(h->partial.p, kDotBlocks, kk, d_h1, s));
-                SG_HIP(launch_update_dot(V, n, kk, d_h1, h->w1.p, h->w2.p, n, h->partial.p, kDotBlocks, true, s));
-                SG_HIP(launch_reduce_partials(h->partial.p, kDotBlocks, kk, d_h2, s));
-                SG_HIP(launch_update_dot(V, n, kk, d_h2, h->w2.p, vnext, n, h->partial.p, kDotBlocks, false, s));
-                SG_HIP(launch_reduce_partials(h->partial.p, kDotBlocks, 1, d_nr, s));
-                SG_HIP(hipMemcpyAsync(hscal, h->dscal.p, sizeof(double) * 240, hipMemcpyDeviceToHost, s));
+                SG_HIP(launch_update_dot(V, n, kk, d_h1, h->w1.p, h->w2.p, n, h->partial.p, kDotBlocks, kUpdDotNorm, s));
+                SG_HIP(launch_reduce_partials(h->partial.p, kDotBlocks, kk + 1, d_h2, s));
+                SG_HIP(launch_update_dot(V, n, kk, d_h2, h->w2.p, vnext, n, h->partial.p, kDotBlocks, kUpdScaled, s));
+                SG_HIP(hipMemcpyAsync(hscal, h->dscal.p, sizeof(double) * 160, hipMemcpyDeviceToHost, s));
                 SG_HIP(hipStreamSynchronize(s));
-                const double hn = std::sqrt(hscal[160]);
+                double ss = 0.0;                      // the device's sum, in the same order
+                for (int i = 0; i < kk; ++i) ss += hscal[80 + i] * hscal[80 + i];
+                const double hn2 = hscal[80 + kk] - ss;
+                const double hn = hn2 > 0.0 ? std::sqrt(hn2) : 0.0;
                 for (int i = 0; i < kk; ++i) H[(size_t)i * m + j] = hscal[i] + hscal[80 + i];
                 H[(size_t)(j + 1) * m + j] = hn;
                 for (int i = 0; i < j; ++i) {
@@ -1786,7 +1789,6 @@ sg_status fgmres_solve_slab(sg_handle h, const double* b, double* x, double rtol
                 inf.iterations++;
                 kdim = j + 1;
                 if (hn == 0.0 || std::fabs(g[j + 1]) / bnorm <= rtol || inf.iterations >= max_iter) break;
-                SG_HIP(launch_axpby(1.0 / hn, vnext, 0.0, nullptr, vnext, n, s));
             }
             for (int i = kdim - 1; i >= 0; --i) {
                 double acc = g[i];
