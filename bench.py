@@ -539,8 +539,9 @@ def run_workload(torch, dev, stream, sgheat, sg_inputs, w, args, src_hash):
 
 def vanka_sweeps(torch, dev, sgheat, sg_inputs, names, reps):
     """Finest-level Vanka sweeps (residual, patch corrections, update gather) of each workload in FP64 and
-    with SG_MIXED (FP32 sweeps), with the fast-diagonalisation corrections (SGHEAT_VANKA_FDM unset) and
-    with the dense position-class inverses (SGHEAT_VANKA_FDM=0); 20 untimed sweeps first."""
+    with SG_MIXED (FP32 sweeps), with the fast-diagonalisation corrections (SGHEAT_VANKA_FDM=1: the
+    register form where the patch fits it), their LDS form (=lds) and the dense position-class
+    inverses (=0); 20 untimed sweeps first."""
     for name in names:
         w = sg_inputs.WORKLOADS[name]
         for prec, label in ((sgheat.SG_FP64, "fp64"), (sgheat.SG_MIXED, "mixed")):
@@ -548,7 +549,7 @@ def vanka_sweeps(torch, dev, sgheat, sg_inputs, names, reps):
             n = G.n(0)
             b = torch.from_numpy(sg_inputs.uniform_vector(n, 5)).to(dev)
             x = torch.zeros(n, dtype=torch.float64, device=dev)
-            for fdm in ("1", "0"):
+            for fdm in ("1", "lds", "0"):
                 os.environ["SGHEAT_VANKA_FDM"] = fdm
                 G.vanka_smooth(0, b, x, sweeps=20)
                 torch.cuda.synchronize()
@@ -557,7 +558,8 @@ def vanka_sweeps(torch, dev, sgheat, sg_inputs, names, reps):
                 G.vanka_smooth(0, b, x, sweeps=reps)
                 e1.record()
                 torch.cuda.synchronize()
-                kind = "fast diagonalisation" if fdm == "1" else "dense inverses"
+                kind = {"1": "fast diagonalisation", "lds": "fast diagonalisation, LDS form",
+                        "0": "dense inverses"}[fdm]
                 print(f"[bench] {name} {label} Vanka sweep ({kind}): {e0.elapsed_time(e1) / reps * 1e3:.1f} us",
                       file=sys.stderr, flush=True)
             os.environ.pop("SGHEAT_VANKA_FDM", None)

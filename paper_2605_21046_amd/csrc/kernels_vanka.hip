@@ -11,6 +11,9 @@
 //                      node gather then forms x <- x + omega sum_K R_K^T W_K c_K
 #include "kernels.hpp"
 
+#include <cstdlib>
+#include <cstring>
+
 
 namespace sg {
 
@@ -974,6 +977,134 @@ __global__ void __launch_bounds__(kFdmThreads)
     }
 }
 
+// The same corrections with one thread per (cell, mode) holding the mode's whole patch residual, all
+// N_t (k+1)^d values, in registers: no LDS and no barrier.  Neighbouring lanes take neighbouring cells
+// along x of one mode, so the loads of one local node and the stores of one broken entry cover
+// contiguous stretches.  Same tables and the same operations in the same order as k_vanka_fdm, so
+// the results are bitwise those of the LDS form.  For Q1 and Q2 patches of at most kFdmRegValues values
+// (larger ones spill registers).
+constexpr int kFdmRegValues = 54;
+// waves per SIMD the register form is compiled for (the compiler would otherwise keep every table
+// value live: 256 VGPRs for the 3D Q2 dG(1) patch)
+template <int NV, typename T>
+constexpr int fdm_reg_waves() { return NV * (int)sizeof(T) > 300 ? 2 : (NV * (int)sizeof(T) > 160 ? 3 : 4); }
+
+template <int DIM, int K, int NT, typename T>
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(fdm_reg_waves<NT * ipow(K + 1, DIM), T>())))
+    k_vanka_fdm_reg(Grid g, int n_xi, const T* __restrict__ Sv, const T* __restrict__ Tt, const T* __restrict__ r,
+                    T* __restrict__ s_out) {
+    constexpr int N1 = K + 1;
+    constexpr int NP = ipow(N1, DIM);
+    constexpr int NTT = NT * NT;
+    const int n_cells = (int)g.n_cells;
+    const long long gid = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (gid >= (long long)n_xi * n_cells) return;    // no barrier follows
+    const int mode = (int)(gid / n_cells);
+    const int cell = (int)(gid - (long long)mode * n_cells);
+    int cc[3] = {0, 0, 0};
+    {
+        int rr = cell;
+        for (int d = 0; d < DIM; ++d) { cc[d] = rr % g.n; rr /= g.n; }
+    }
+    int cls = 0, node0 = 0, brk0 = 0, vv[3] = {0, 0, 0};
+    const int nb1 = g.n * N1;
+    int nbn = 1;
+    for (int d = 0, m3 = 1, mn = 1; d < DIM; ++d) {
+        vv[d] = cc[d] == 0 ? 0 : (cc[d] == g.n - 1 ? 2 : 1);
+        cls += m3 * vv[d];
+        node0 += cc[d] * K * mn;
+        brk0 += cc[d] * N1 * nbn;
+        m3 *= 3;
+        mn *= g.n1;
+        nbn *= nb1;
+    }
+    const int nn = (int)g.n_nodes;
+    // the residual patch, Dirichlet values zeroed
+    T u[NT][NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        int node = node0;
+        bool live = true;
+#pragma unroll
+        for (int d = 0, pp = p, mn = 1; d < DIM; ++d, pp /= N1) {
+            const int id = cc[d] * K + pp % N1;
+            live &= (id != 0) & (id != g.n1 - 1);
+            node += (pp % N1) * mn;
+            mn *= g.n1;
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const T v = r[(mode * NT + t) * nn + node];
+            u[t][p] = live ? v : T(0);
+        }
+    }
+    // transforms along direction d (node stride st = (k+1)^d): fwd u_i = sum_j S[j][i] v_j, else
+    // o_j = sum_i S[j][i] w_i
+    auto sweep = [&](int d, bool fwd, T (&a)[NP]) {
+        const int st = ipow(N1, d);
+        const T* const S = Sv + vv[d] * N1 * N1;
+#pragma unroll
+        for (int q = 0; q < NP / N1; ++q) {
+            const int pb = q % st + (q / st) * st * N1;
+            T v[N1];
+#pragma unroll
+            for (int j = 0; j < N1; ++j) v[j] = a[pb + j * st];
+#pragma unroll
+            for (int i = 0; i < N1; ++i) {
+                T o = T(0);
+#pragma unroll
+                for (int j = 0; j < N1; ++j) o += (fwd ? S[j * N1 + i] : S[i * N1 + j]) * v[j];
+                a[pb + i * st] = o;
+            }
+        }
+    };
+#pragma unroll
+    for (int d = 0; d < DIM; ++d)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) sweep(d, true, u[t]);
+    // the time block of every eigen index
+    const T* const tc = Tt + (long long)cls * NP * NTT;
+#pragma unroll
+    for (int e = 0; e < NP; ++e) {
+        T w[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            T a = T(0);
+#pragma unroll
+            for (int t2 = 0; t2 < NT; ++t2) a += tc[e * NTT + t * NT + t2] * u[t2][e];
+            w[t] = a;
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) u[t][e] = w[t];
+        // keep the table loads of the next eigen index after this one's use (the scheduler would
+        // otherwise issue all of them at once and hold every block in registers)
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int d = DIM - 1; d >= 0; --d)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) sweep(d, false, u[t]);
+    // store into the broken layout [comp][b_z][b_y][b_x]
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        int b = brk0;
+#pragma unroll
+        for (int d = 0, pp = p, bm = 1; d < DIM; ++d, pp /= N1) {
+            b += (pp % N1) * bm;
+            bm *= nb1;
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) s_out[(mode * NT + t) * nbn + b] = u[t][p];
+    }
+}
+
+// The register form where the patch fits it, unless SGHEAT_VANKA_FDM=lds (a measurement switch).
+inline bool fdm_lds_forced() {
+    const char* e = std::getenv("SGHEAT_VANKA_FDM");
+    return e && std::strcmp(e, "lds") == 0;
+}
+
 template <int DIM, int K, int NT, typename T>
 hipError_t run_vanka_fdm(Grid g, int n_xi, const T* Sv, const T* Tt, const T* r, T* s_out, hipStream_t s) {
     constexpr int NP = ipow(K + 1, DIM);
@@ -982,6 +1113,14 @@ hipError_t run_vanka_fdm(Grid g, int n_xi, const T* Sv, const T* Tt, const T* r,
     if ((long long)n_xi * NT * g.n_nodes >= (1LL << 31) || (long long)n_xi * NT * nbn >= (1LL << 31) ||
         g.n_cells >= (1LL << 31) || n_xi < 1)
         return hipErrorInvalidValue;      // 32-bit offsets
+    if constexpr (NT * NP <= kFdmRegValues && K <= 2) {
+        if (!fdm_lds_forced()) {
+            const long long threads = (long long)n_xi * g.n_cells;
+            hipLaunchKernelGGL((k_vanka_fdm_reg<DIM, K, NT, T>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
+                               s, g, n_xi, Sv, Tt, r, s_out);
+            return hipGetLastError();
+        }
+    }
     const int mp = vanka_fdm_modes_per_pass(DIM, K, NT, n_xi, sizeof(T));
     const size_t lds = vanka_fdm_lds_bytes(DIM, K, NT, mp, sizeof(T));
     if (lds > 160 * 1024) return hipErrorInvalidConfiguration;

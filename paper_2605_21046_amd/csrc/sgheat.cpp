@@ -305,7 +305,7 @@ bool mean_stencil_disabled() {
 // smoothing call, so a process can compare both.
 bool vanka_fdm_disabled() {
     const char* e = std::getenv("SGHEAT_VANKA_FDM");
-    return e && std::atoi(e) == 0;
+    return e && std::strcmp(e, "0") == 0;     // ("lds" keeps it on and picks the kernel's LDS form)
 }
 
 // Generalised symmetric-definite eigenproblem A s = lambda B s of order m (row-major, B positive

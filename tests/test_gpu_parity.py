@@ -148,6 +148,33 @@ def test_vanka_fast_diagonalisation_matches_dense_inverses(torch_cuda, name, pre
             assert _rel_inf(got["1"], got["0"]) <= 1e-12, level
 
 
+@pytest.mark.parametrize("name", ["c1", "t2q1", "t2q2", "t2q2p4", "t3q1", "t3q2", "t3c2", "t3s2"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_vanka_register_form_is_bitwise_the_lds_form(torch_cuda, name, precision, monkeypatch):
+    """Q1 and Q2 patches of at most 54 values run the fast-diagonalisation corrections with one thread
+    per (cell, mode) in registers; SGHEAT_VANKA_FDM=lds selects the LDS form.  Same tables, same
+    operations in the same order: every level's sweep bitwise equal."""
+    torch = torch_cuda
+    w = sg_inputs.WORKLOADS[name]
+    G = _gpu(w, precision)
+    for level in range(w.n_levels - 1):
+        print(f"vanka register form {name} precision {precision} level {level}", flush=True)
+        n = G.n(level)
+        b = _to_gpu(torch, sg_inputs.uniform_vector(n, 71 + level))
+        x0 = sg_inputs.uniform_vector(n, 81 + level)
+        got = {}
+        for form in ("reg", "lds"):
+            if form == "lds":
+                monkeypatch.setenv("SGHEAT_VANKA_FDM", "lds")
+            else:
+                monkeypatch.delenv("SGHEAT_VANKA_FDM", raising=False)
+            xg = _to_gpu(torch, x0)
+            G.vanka_smooth(level, b, xg, sweeps=2)
+            got[form] = xg.cpu().numpy()
+        monkeypatch.delenv("SGHEAT_VANKA_FDM", raising=False)
+        assert np.array_equal(got["reg"], got["lds"]), level
+
+
 @pytest.mark.parametrize("name", ["c1", "t2q2", "t2q3", "t2q4", "t3q1", "t3q2", "t2q2p4", "t3c2", "t2s3", "t3s2"])
 def test_vcycle_matches_oracle(torch_cuda, name):
     torch = torch_cuda
