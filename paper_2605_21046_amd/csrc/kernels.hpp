@@ -178,9 +178,11 @@ inline size_t vanka_fdm_lds_bytes(int dim, int k, int nt, int mp, size_t elem) {
     for (int d = 0; d < dim; ++d) np *= k + 1;
     return ((size_t)np * nt * nt + (size_t)mp * nt * vanka_fdm_component_stride(dim, k)) * elem;
 }
+// sx receives the x segment length of the broken layout written, for the gather: k (one entry per cell
+// and local node) or n k (one entry per node along x, the register form summing the shared x faces).
 template <typename T>
 hipError_t launch_vanka_fdm(int dim, int k, int nt, Grid g, int n_xi, const T* Sv, const T* Tt, const T* r,
-                            T* s_out, hipStream_t s);
+                            T* s_out, int* sx, hipStream_t s);
 
 // ---- the coarse segment of the V-cycle in one launch ----------------------------------------------------
 // Levels l0 .. l0 + nlev - 1 (the last is the coarsest) of the block-Jacobi cycle with the mean block, one

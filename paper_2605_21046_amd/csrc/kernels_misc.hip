@@ -135,6 +135,7 @@ __global__ void __launch_bounds__(256)
         // weight 0 for the upper one, when the node lies inside a cell along that direction)
         unsigned lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
         T whi[3] = {T(0), T(0), T(0)};
+        T mult[3] = {T(1), T(1), T(1)};   // cells sharing the node along d (a layout may hold their sum)
         bool bnd = false;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
@@ -145,6 +146,7 @@ __global__ void __launch_bounds__(256)
                 r = q;
             }
             bnd |= (i == 0) | (i == n1 - 1);
+            if (i % (unsigned)K == 0) mult[d] = T(2);
             const unsigned sl = d == 0 ? sx : (d == 2 ? sz : (unsigned)K);   // segment length along d
             const unsigned ns = d == 0 ? nsx : (d == 2 ? nsz : nc);           // segments along d
             const unsigned c = d == 0 ? fast_quot(dv.sx, i) : (d == 2 ? fast_quot(dv.sz, i) : i / (unsigned)K);
@@ -172,7 +174,7 @@ __global__ void __launch_bounds__(256)
         if (DIM == 2) {
             const unsigned y0 = lo[1] * nbx, y1 = hi[1] * nbx;
             sum = (sc[y0 + lo[0]] + whi[0] * sc[y0 + hi[0]]) + whi[1] * (sc[y1 + lo[0]] + whi[0] * sc[y1 + hi[0]]);
-            cnt = (T(1) + whi[0]) * (T(1) + whi[1]);
+            cnt = mult[0] * mult[1];
         } else {
             const unsigned z0 = lo[2] * nb1 * nbx, z1 = hi[2] * nb1 * nbx;
             const unsigned y0 = lo[1] * nbx, y1 = hi[1] * nbx;
@@ -181,7 +183,7 @@ __global__ void __launch_bounds__(256)
             const T s10 = sc[z1 + y0 + lo[0]] + whi[0] * sc[z1 + y0 + hi[0]];
             const T s11 = sc[z1 + y1 + lo[0]] + whi[0] * sc[z1 + y1 + hi[0]];
             sum = (s00 + whi[1] * s01) + whi[2] * (s10 + whi[1] * s11);
-            cnt = (T(1) + whi[0]) * (T(1) + whi[1]) * (T(1) + whi[2]);
+            cnt = mult[0] * mult[1] * mult[2];
         }
         if (OP == GATHER_SET || OP == GATHER_INTERIOR) out[gi] = sum;
         else if (OP == GATHER_RESIDUAL) out[gi] = b[gi] - sum;

@@ -989,7 +989,7 @@ constexpr int kFdmRegValues = 54;
 template <int NV, typename T>
 constexpr int fdm_reg_waves() { return NV * (int)sizeof(T) > 300 ? 2 : (NV * (int)sizeof(T) > 160 ? 3 : 4); }
 
-template <int DIM, int K, int NT, typename T>
+template <int DIM, int K, int NT, typename T, bool MERGE>
 __global__ void __launch_bounds__(256)
     __attribute__((amdgpu_waves_per_eu(fdm_reg_waves<NT * ipow(K + 1, DIM), T>())))
     k_vanka_fdm_reg(Grid g, int n_xi, const T* __restrict__ Sv, const T* __restrict__ Tt, const T* __restrict__ r,
@@ -1014,10 +1014,12 @@ __global__ void __launch_bounds__(256)
         vv[d] = cc[d] == 0 ? 0 : (cc[d] == g.n - 1 ? 2 : 1);
         cls += m3 * vv[d];
         node0 += cc[d] * K * mn;
-        brk0 += cc[d] * N1 * nbn;
+        // MERGE: one x entry per node (b_x = node x index), the cells' shared x faces summed
+        const int ext = (MERGE && d == 0) ? g.n1 : nb1;
+        brk0 += cc[d] * (MERGE && d == 0 ? K : N1) * nbn;
         m3 *= 3;
         mn *= g.n1;
-        nbn *= nb1;
+        nbn *= ext;
     }
     const int nn = (int)g.n_nodes;
     // the residual patch, Dirichlet values zeroed
@@ -1085,17 +1087,37 @@ __global__ void __launch_bounds__(256)
     for (int d = DIM - 1; d >= 0; --d)
 #pragma unroll
         for (int t = 0; t < NT; ++t) sweep(d, false, u[t]);
-    // store into the broken layout [comp][b_z][b_y][b_x]
+    // store into the broken layout [comp][b_z][b_y][b_x], one x-line at a time.  MERGE: the next lane
+    // holds the next cell along x of the same row (rows never straddle a wave); its left x face is added
+    // into this cell's right face, in the gather's order (left cell's copy first).  Every cell but the
+    // first of a row stores the merged face of its left neighbour at its own left face, the same value to
+    // the same address (no branch around a store)
+    const bool has_right = cc[0] < g.n - 1;
+    const int bx = MERGE ? g.n1 : nb1;           // entries along x per (b_y, b_z)
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
+    for (int q = 0; q < NP / N1; ++q) {
         int b = brk0;
-#pragma unroll
-        for (int d = 0, pp = p, bm = 1; d < DIM; ++d, pp /= N1) {
-            b += (pp % N1) * bm;
+        for (int d = 1, qq = q, bm = bx; d < DIM; ++d, qq /= N1) {
+            b += (qq % N1) * bm;
             bm *= nb1;
         }
 #pragma unroll
-        for (int t = 0; t < NT; ++t) s_out[(mode * NT + t) * nbn + b] = u[t][p];
+        for (int t = 0; t < NT; ++t) {
+            T* const dst = s_out + (mode * NT + t) * nbn + b;
+            if constexpr (MERGE) {
+                const T left_of_next = __shfl_down(u[t][q * N1], 1);
+                const T merged = u[t][q * N1 + K] + (has_right ? left_of_next : T(0));
+                const T merged_prev = __shfl_up(merged, 1);
+                dst[0] = cc[0] == 0 ? u[t][q * N1] : merged_prev;
+#pragma unroll
+                for (int x = 1; x < K; ++x) dst[x] = u[t][q * N1 + x];
+                dst[K] = merged;
+            } else {
+#pragma unroll
+                for (int x = 0; x < N1; ++x) dst[x] = u[t][q * N1 + x];
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -1106,7 +1128,8 @@ inline bool fdm_lds_forced() {
 }
 
 template <int DIM, int K, int NT, typename T>
-hipError_t run_vanka_fdm(Grid g, int n_xi, const T* Sv, const T* Tt, const T* r, T* s_out, hipStream_t s) {
+hipError_t run_vanka_fdm(Grid g, int n_xi, const T* Sv, const T* Tt, const T* r, T* s_out, int* sx, hipStream_t s) {
+    *sx = K;
     constexpr int NP = ipow(K + 1, DIM);
     long long nbn = 1;
     for (int d = 0; d < DIM; ++d) nbn *= (long long)g.n * (K + 1);
@@ -1116,8 +1139,16 @@ hipError_t run_vanka_fdm(Grid g, int n_xi, const T* Sv, const T* Tt, const T* r,
     if constexpr (NT * NP <= kFdmRegValues && K <= 2) {
         if (!fdm_lds_forced()) {
             const long long threads = (long long)n_xi * g.n_cells;
-            hipLaunchKernelGGL((k_vanka_fdm_reg<DIM, K, NT, T>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
-                               s, g, n_xi, Sv, Tt, r, s_out);
+            const dim3 grid((unsigned)((threads + 255) / 256));
+            // whole rows inside one wave (n a power of two up to 64): the x faces are summed in registers
+            if (g.n <= 64 && (64 % g.n) == 0) {
+                *sx = g.n * K;
+                hipLaunchKernelGGL((k_vanka_fdm_reg<DIM, K, NT, T, true>), grid, dim3(256), 0, s, g, n_xi, Sv, Tt, r,
+                                   s_out);
+            } else {
+                hipLaunchKernelGGL((k_vanka_fdm_reg<DIM, K, NT, T, false>), grid, dim3(256), 0, s, g, n_xi, Sv, Tt, r,
+                                   s_out);
+            }
             return hipGetLastError();
         }
     }
@@ -1132,24 +1163,25 @@ hipError_t run_vanka_fdm(Grid g, int n_xi, const T* Sv, const T* Tt, const T* r,
 }
 
 template <int DIM, int K, typename T>
-hipError_t vanka_fdm_nt(int nt, Grid g, int n_xi, const T* Sv, const T* Tt, const T* r, T* s_out, hipStream_t s) {
+hipError_t vanka_fdm_nt(int nt, Grid g, int n_xi, const T* Sv, const T* Tt, const T* r, T* s_out, int* sx,
+                        hipStream_t s) {
     switch (nt) {
-        case 1: return run_vanka_fdm<DIM, K, 1, T>(g, n_xi, Sv, Tt, r, s_out, s);
-        case 2: return run_vanka_fdm<DIM, K, 2, T>(g, n_xi, Sv, Tt, r, s_out, s);
-        case 3: return run_vanka_fdm<DIM, K, 3, T>(g, n_xi, Sv, Tt, r, s_out, s);
-        case 4: return run_vanka_fdm<DIM, K, 4, T>(g, n_xi, Sv, Tt, r, s_out, s);
+        case 1: return run_vanka_fdm<DIM, K, 1, T>(g, n_xi, Sv, Tt, r, s_out, sx, s);
+        case 2: return run_vanka_fdm<DIM, K, 2, T>(g, n_xi, Sv, Tt, r, s_out, sx, s);
+        case 3: return run_vanka_fdm<DIM, K, 3, T>(g, n_xi, Sv, Tt, r, s_out, sx, s);
+        case 4: return run_vanka_fdm<DIM, K, 4, T>(g, n_xi, Sv, Tt, r, s_out, sx, s);
     }
     return hipErrorInvalidValue;
 }
 
 template <int DIM, typename T>
-hipError_t vanka_fdm_k(int k, int nt, Grid g, int n_xi, const T* Sv, const T* Tt, const T* r, T* s_out,
+hipError_t vanka_fdm_k(int k, int nt, Grid g, int n_xi, const T* Sv, const T* Tt, const T* r, T* s_out, int* sx,
                        hipStream_t s) {
     switch (k) {
-        case 1: return vanka_fdm_nt<DIM, 1, T>(nt, g, n_xi, Sv, Tt, r, s_out, s);
-        case 2: return vanka_fdm_nt<DIM, 2, T>(nt, g, n_xi, Sv, Tt, r, s_out, s);
-        case 3: return vanka_fdm_nt<DIM, 3, T>(nt, g, n_xi, Sv, Tt, r, s_out, s);
-        case 4: return vanka_fdm_nt<DIM, 4, T>(nt, g, n_xi, Sv, Tt, r, s_out, s);
+        case 1: return vanka_fdm_nt<DIM, 1, T>(nt, g, n_xi, Sv, Tt, r, s_out, sx, s);
+        case 2: return vanka_fdm_nt<DIM, 2, T>(nt, g, n_xi, Sv, Tt, r, s_out, sx, s);
+        case 3: return vanka_fdm_nt<DIM, 3, T>(nt, g, n_xi, Sv, Tt, r, s_out, sx, s);
+        case 4: return vanka_fdm_nt<DIM, 4, T>(nt, g, n_xi, Sv, Tt, r, s_out, sx, s);
     }
     return hipErrorInvalidValue;
 }
@@ -1158,15 +1190,15 @@ hipError_t vanka_fdm_k(int k, int nt, Grid g, int n_xi, const T* Sv, const T* Tt
 
 template <typename T>
 hipError_t launch_vanka_fdm(int dim, int k, int nt, Grid g, int n_xi, const T* Sv, const T* Tt, const T* r,
-                            T* s_out, hipStream_t s) {
-    if (dim == 2) return vanka_fdm_k<2, T>(k, nt, g, n_xi, Sv, Tt, r, s_out, s);
-    if (dim == 3) return vanka_fdm_k<3, T>(k, nt, g, n_xi, Sv, Tt, r, s_out, s);
+                            T* s_out, int* sx, hipStream_t s) {
+    if (dim == 2) return vanka_fdm_k<2, T>(k, nt, g, n_xi, Sv, Tt, r, s_out, sx, s);
+    if (dim == 3) return vanka_fdm_k<3, T>(k, nt, g, n_xi, Sv, Tt, r, s_out, sx, s);
     return hipErrorInvalidValue;
 }
 
 template hipError_t launch_vanka_fdm<double>(int, int, int, Grid, int, const double*, const double*, const double*,
-                                             double*, hipStream_t);
+                                             double*, int*, hipStream_t);
 template hipError_t launch_vanka_fdm<float>(int, int, int, Grid, int, const float*, const float*, const float*,
-                                            float*, hipStream_t);
+                                            float*, int*, hipStream_t);
 
 }  // namespace sg

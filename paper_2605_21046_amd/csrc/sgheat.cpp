@@ -1328,16 +1328,17 @@ sg_status smooth_level(sg_handle h, int l, const T* b, T* x, int sweeps, bool x_
             SG_TRY(op_apply<T>(h, op, x, Prec<T>::r(lv), b, s));
             r = Prec<T>::r(lv);
         }
+        int sx = h->d.fe_degree;                  // x segment length of the corrections' broken layout
         if (h->diag)
             SG_HIP(launch_vanka_cells_modes<T>(h->d.dim, h->d.fe_degree, h->NT, lv.g, h->n_xi, inv, r, sbuf_as<T>(h), s));
         else if (lv.mean_const && !vanka_fdm_disabled())
             SG_HIP(launch_vanka_fdm<T>(h->d.dim, h->d.fe_degree, h->NT, lv.g, h->n_xi, Prec<T>::fdmS(lv),
-                                       Prec<T>::fdmT(lv), r, sbuf_as<T>(h), s));
+                                       Prec<T>::fdmT(lv), r, sbuf_as<T>(h), &sx, s));
         else
             SG_HIP(launch_vanka_cells<T>(h->d.dim, h->d.fe_degree, h->NT, lv.g, h->n_xi, inv, r, sbuf_as<T>(h),
                                          lv.inv_classes, s));
         SG_HIP(launch_node_gather<T>(GATHER_VANKA, h->d.dim, h->d.fe_degree, lv.g, h->n_xi * h->NT, sbuf_as<T>(h),
-                                     nullptr, b, x, (T)h->d.vanka_omega, h->d.fe_degree, h->d.fe_degree, s));
+                                     nullptr, b, x, (T)h->d.vanka_omega, sx, h->d.fe_degree, s));
     }
     return SG_OK;
 }
