@@ -88,6 +88,8 @@ WORKLOADS = {
     "t3c3": Workload("t3c3", 3, 5, 3, 2, 1.0 / 5, 3, 4, 1, "sine"),
     # the c3 discretisation on two levels (4 and 2 cells per direction): Vanka sweeps of Q3 dG(2) patches
     "t3v3": Workload("t3v3", 3, 4, 3, 2, 1.0 / 4, 3, 4, 2, "sine"),
+    # 64 cells per row: one row of cells per wave in the register-form Vanka corrections
+    "t2w64": Workload("t2w64", 2, 64, 2, 1, 0.01, 2, 2, 2, "sine"),
     # three-level hierarchies whose lower two levels form one persistent coarse segment
     "t2s3": Workload("t2s3", 2, 8, 3, 2, 0.02, 3, 2, 3, "sine"),
     "t3s2": Workload("t3s2", 3, 4, 2, 1, 0.05, 2, 2, 3, "sine"),

@@ -115,7 +115,7 @@ def test_vanka_matches_oracle(torch_cuda, name):
         assert _rel_inf(xg.cpu().numpy(), ref) <= 1e-11, level
 
 
-@pytest.mark.parametrize("name", ["c1", "t2q1", "t2q4", "t2s3", "t3q1", "t3q2", "t3c2", "t3v3"])
+@pytest.mark.parametrize("name", ["c1", "t2q1", "t2q4", "t2s3", "t2w64", "t3q1", "t3q2", "t3c2", "t3v3"])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_vanka_fast_diagonalisation_matches_dense_inverses(torch_cuda, name, precision, monkeypatch):
     """On levels with a constant mean coefficient the patch corrections come from the fast
@@ -148,12 +148,14 @@ def test_vanka_fast_diagonalisation_matches_dense_inverses(torch_cuda, name, pre
             assert _rel_inf(got["1"], got["0"]) <= 1e-12, level
 
 
-@pytest.mark.parametrize("name", ["c1", "t2q1", "t2q2", "t2q2p4", "t3q1", "t3q2", "t3c2", "t3s2"])
+@pytest.mark.parametrize("name", ["c1", "t2q1", "t2q2", "t2q2p4", "t2w64", "t3q1", "t3q2", "t3c2", "t3s2"])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_vanka_register_form_is_bitwise_the_lds_form(torch_cuda, name, precision, monkeypatch):
     """Q1 and Q2 patches of at most 54 values run the fast-diagonalisation corrections with one thread
     per (cell, mode) in registers; SGHEAT_VANKA_FDM=lds selects the LDS form.  Same tables, same
-    operations in the same order: every level's sweep bitwise equal."""
+    operations in the same order: every level's sweep bitwise equal, also where the register form sums
+    the shared x faces across lanes (n = 2, 4, 8, 32, 64 cells per row) and the update gather reads one
+    entry per node along x."""
     torch = torch_cuda
     w = sg_inputs.WORKLOADS[name]
     G = _gpu(w, precision)
