@@ -401,7 +401,8 @@ size_t stencil_lds_bytes(const StencilArgs& a, int elem) {
 }
 
 bool stencil_fits(StencilArgs& a, int elem) {
-    // rows per workgroup: as many as the positions of the z march (3D) and 160 KB of LDS allow, up to 8.
+    // rows per workgroup: as many as the positions of the z march (3D) and 160 KB of LDS allow, up to 10
+    // in 3D (c2 FP64: 236 us with 8 rows, 194 with 10, 211 with 11) and 8 in 2D.
     // z planes per workgroup: about 16 (SGHEAT_STENCIL_ZC overrides; a measurement switch), split evenly:
     // each workgroup loads 2k window planes before its first output plane, so longer chunks read less
     // (chunks of 8: c3 FP64 678 us, 15: 608 us, 19: 630 us, the last with a worse final round of
@@ -410,7 +411,8 @@ bool stencil_fits(StencilArgs& a, int elem) {
     int zt = 16;
     if (const char* e = std::getenv("SGHEAT_STENCIL_ZC")) zt = std::max(1, std::atoi(e));
     const int nzc = (a.n1 + zt - 1) / zt;
-    for (int ty = 8; ty >= 1; --ty) {
+    const int tymax = a.dim == 3 ? 10 : 8;
+    for (int ty = tymax; ty >= 1; --ty) {
         a.ty = ty;
         a.zc = (a.n1 + nzc - 1) / nzc;
         if (a.dim == 3 && (long long)(ty + 2 * k) * a.n1 > kStSlots) continue;
