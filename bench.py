@@ -101,7 +101,7 @@ def _cpu_model() -> str:
 
 
 def _host_threads() -> int:
-    """Cores this process may use (the GPU machine gives one GPU's share of 16)."""
+    """Cores this process may use: its CPU affinity, at most 16 (a one-GPU host share)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
