@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsgheat.so")
 SOURCES = ["apply_3d_f64.hip", "apply_3d_f32.hip", "apply_2d_f64.hip", "apply_2d_f32.hip", "kernels_vanka.hip",
-           "kernels_apply.hip", "kernels_misc.hip", "kernels_forcing.hip", "kernels_segment.hip", "kernels_stencil.hip", "sgheat.cpp", "basis.cpp"]
+           "kernels_apply.hip", "kernels_misc.hip", "kernels_forcing.hip", "kernels_segment.hip", "kernels_stencil.hip", "kernels_krylov.hip", "sgheat.cpp", "basis.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -19,6 +19,7 @@
 #include "../../include/sgheat.h"
 #include "basis.hpp"
 #include "kernels.hpp"
+#include "krylov.hpp"
 #include "forcing.hpp"
 
 using namespace sg;
@@ -1028,7 +1029,7 @@ sg_status build(sg_handle h) {
     SG_TRY(h->Z.alloc((size_t)h->restart * h->N, "Krylov basis"));
     SG_TRY(h->w1.alloc(h->N, "Krylov work"));
     SG_TRY(h->w2.alloc(h->N, "Krylov work"));
-    SG_TRY(h->partial.alloc((size_t)kDotBlocks * (h->restart + 2), "partials"));
+    SG_TRY(h->partial.alloc((size_t)kDotBlocks * (2 * h->restart + 2), "partials"));
     SG_TRY(h->dscal.alloc(3 * 80, "scalars"));
     SG_TRY(h->sbuf.alloc((size_t)h->n_xi * h->NT * h->lv[0].g.n_cells * h->NP, "cell-local results"));
     SG_HIP(hipStreamSynchronize(nullptr));
@@ -1249,6 +1250,14 @@ sg_status autotune_segment(sg_handle h, int reps, hipStream_t s) {
     for (auto& e : ev) (void)hipEventDestroy(e);
     if (st == SG_OK) h->seg_on = med[1] < med[0];
     return st;
+}
+
+// FGMRES orthogonalises by classical Gram-Schmidt with the reorthogonalisation delayed into the next
+// step (DCGS2) unless SGHEAT_FGMRES_CGS2=1 (a measurement switch: both passes of classical Gram-Schmidt
+// with reorthogonalisation in every step).  Read at every solve.
+bool fgmres_classic_cgs2() {
+    const char* e = std::getenv("SGHEAT_FGMRES_CGS2");
+    return e && std::strcmp(e, "1") == 0;
 }
 
 // y = A x (b == nullptr) or y = b - A x, for the operator described by op; the cell-local results go
@@ -1744,6 +1753,90 @@ sg_status fgmres_solve_slab(sg_handle h, const double* b, double* x, double rtol
             std::fill(g.begin(), g.end(), 0.0);
             g[0] = beta;
             int kdim = 0;
+            if (!fgmres_classic_cgs2()) {
+                // DCGS2: V[j] enters step j as the tentative vector u_j (orthogonal once to V[0..j-1]); the
+                // step's dot pass also yields its reorthogonalisation coefficients a, its update pass writes
+                // the final v_j = (u_j - V a) / nu_j over it and the next tentative vector
+                // u_{j+1} = w - V b - e v_j.  Column j-1 of H (A z_{j-1} = ... + u_j) is completed here:
+                // h_{i,j-1} += a_i, h_{j,j-1} = nu_j; column j is tested with the provisional
+                // h_{j+1,j} = |u_{j+1}| and kept that way if the iteration ends there.
+                double* d_r = h->dscal.p;                 // [a (j), b (j), u.u, u.w]
+                double* d_s = h->dscal.p + 2 * kDcgsMaxBasis + 2;   // |u_{j+1}|^2
+                std::vector<double> col(m + 1);
+                for (int j = 0; j < m; ++j) {
+                    double* uj = V + (size_t)j * n;
+                    double* zj = Z + (size_t)j * n;
+                    SG_HIP(mark(ev_prec));
+                    SG_TRY(vcycle(h, uj, zj, s));
+                    SG_HIP(mark(ev_prec));
+                    inf.vcycles++;
+                    SG_HIP(mark(ev_apply));
+                    SG_TRY(op_apply<double>(h, op, zj, h->w1.p, nullptr, s));
+                    SG_HIP(mark(ev_apply));
+                    inf.applies++;
+                    SG_HIP(launch_dcgs_dots(V, n, j, uj, h->w1.p, n, h->partial.p, kDotBlocks, s));
+                    SG_HIP(launch_reduce_partials(h->partial.p, kDotBlocks, 2 * j + 2, d_r, s));
+                    SG_HIP(launch_dcgs_update(V, n, j, d_r, uj, h->w1.p, V + (size_t)(j + 1) * n, n, h->partial.p,
+                                              kDotBlocks, s));
+                    SG_HIP(launch_reduce_partials(h->partial.p, kDotBlocks, 1, d_s, s));
+                    SG_HIP(hipMemcpyAsync(hscal, h->dscal.p, sizeof(double) * (2 * kDcgsMaxBasis + 3),
+                                          hipMemcpyDeviceToHost, s));
+                    SG_HIP(hipStreamSynchronize(s));
+                    const double* ra = hscal;
+                    const double* rb = hscal + j;
+                    double ss = 0.0, ab = 0.0;            // the device's sums, in the same order
+                    for (int i = 0; i < j; ++i) {
+                        ss += ra[i] * ra[i];
+                        ab += ra[i] * rb[i];
+                    }
+                    const double nu2 = hscal[2 * j] - ss;
+                    const double nu = nu2 > 0.0 ? std::sqrt(nu2) : 0.0;
+                    const double e = nu > 0.0 ? (hscal[2 * j + 1] - ab) / nu : 0.0;
+                    const double un2 = hscal[2 * kDcgsMaxBasis + 2];
+                    const double un = un2 > 0.0 ? std::sqrt(un2) : 0.0;
+                    auto rotate_column = [&](int c) {         // rotations of columns < c, then its own
+                        for (int i = 0; i < c; ++i) {
+                            const double t = cs[i] * H[(size_t)i * m + c] + sn[i] * H[(size_t)(i + 1) * m + c];
+                            H[(size_t)(i + 1) * m + c] = -sn[i] * H[(size_t)i * m + c] + cs[i] * H[(size_t)(i + 1) * m + c];
+                            H[(size_t)i * m + c] = t;
+                        }
+                        const double den = std::hypot(H[(size_t)c * m + c], H[(size_t)(c + 1) * m + c]);
+                        cs[c] = den > 0.0 ? H[(size_t)c * m + c] / den : 1.0;
+                        sn[c] = den > 0.0 ? H[(size_t)(c + 1) * m + c] / den : 0.0;
+                        H[(size_t)c * m + c] = den;
+                        H[(size_t)(c + 1) * m + c] = 0.0;
+                        g[c + 1] = -sn[c] * g[c];
+                        g[c] = cs[c] * g[c];
+                    };
+                    if (j == 0) {
+                        if (!(nu > 0.0)) break;               // no basis (a non-finite residual): kdim = 0
+                        g[0] = beta * nu;                     // r = beta u_0 = beta nu_0 v_0
+                    } else {
+                        for (int i = 0; i < j; ++i) H[(size_t)i * m + (j - 1)] += ra[i];
+                        H[(size_t)j * m + (j - 1)] = nu;
+                        rotate_column(j - 1);
+                        if (nu == 0.0) break;                 // A z_{j-1} lies in span V[0..j-1]: kdim = j
+                    }
+                    for (int i = 0; i < j; ++i) H[(size_t)i * m + j] = rb[i];
+                    H[(size_t)j * m + j] = e;
+                    H[(size_t)(j + 1) * m + j] = un;
+                    // provisional test of column j (on copies of the column and of g)
+                    for (int i = 0; i <= j + 1; ++i) col[i] = H[(size_t)i * m + j];
+                    for (int i = 0; i < j; ++i) {
+                        const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+                        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+                        col[i] = t;
+                    }
+                    const double den = std::hypot(col[j], col[j + 1]);
+                    const double res = den > 0.0 ? std::fabs(col[j + 1] / den * g[j]) : std::fabs(g[j]);
+                    inf.iterations++;
+                    kdim = j + 1;
+                    if (nu == 0.0 || un == 0.0 || res / bnorm <= rtol || inf.iterations >= max_iter || j + 1 == m) {
+                        rotate_column(j);
+                        break;
+                    }
+                }
+            } else
             for (int j = 0; j < m; ++j) {
                 double* vj = V + (size_t)j * n;
                 double* zj = Z + (size_t)j * n;
@@ -1791,6 +1884,7 @@ sg_status fgmres_solve_slab(sg_handle h, const double* b, double* x, double rtol
                 kdim = j + 1;
                 if (hn == 0.0 || std::fabs(g[j + 1]) / bnorm <= rtol || inf.iterations >= max_iter) break;
             }
+            if (kdim == 0) break;
             for (int i = kdim - 1; i >= 0; --i) {
                 double acc = g[i];
                 for (int c = i + 1; c < kdim; ++c) acc -= H[(size_t)i * m + c] * y[c];
