@@ -174,8 +174,11 @@ sg_status gmg_vcycle(sg_handle h, const double* r, double* z, void* hip_stream);
 
 /* Solve the slab system AA x = b (Problem tensor-product-slab-system) by right-preconditioned
  * flexible GMRES with the block-Jacobi multigrid preconditioner of Remark solver-matrix-free-sg
- * (restart fgmres_restart, CGS2, preconditioner gmg_vcycle) starting from the x passed in, until ||b - AA x||_2 / ||b||_2 <= rtol
- * (true residual) or max_iter iterations.  Synchronises the stream (Krylov scalars go to the host).
+ * (restart fgmres_restart, preconditioner gmg_vcycle) starting from the x passed in, until
+ * ||b - AA x||_2 / ||b||_2 <= rtol (true residual) or max_iter iterations.  The basis is orthogonalised
+ * by classical Gram-Schmidt with reorthogonalisation, the second projection of each basis vector delayed
+ * into the next step (DCGS2: two passes over the basis per step); the convergence test of a step uses
+ * its provisional Hessenberg column.  Synchronises the stream (Krylov scalars go to the host).
  * `info` may be NULL.  Returns SG_NOT_CONVERGED if the tolerance was not reached. */
 sg_status fgmres_solve_slab(sg_handle h, const double* b, double* x, double rtol, int max_iter,
                             sg_solve_info* info, void* hip_stream);
