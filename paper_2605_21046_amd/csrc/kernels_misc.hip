@@ -68,6 +68,55 @@ __global__ void k_transfer_1d_narrow(int dim, unsigned total, int i0, int i1, Fa
     }
 }
 
+// The same pass with the inputs staged through LDS: a workgroup owns 64 columns (a column = every input
+// along dir at one position of the other directions and one component) and loads each of their inputs
+// from memory once, coalesced (for dir = 0 the 64 lines are one contiguous block), instead of once per
+// table term; then wave v computes the outputs o = v, v + 4, ... of its lane's column, o being uniform
+// over the wave, so the table entries are scalar loads.  Same terms in the same order as above (zero
+// weights skipped), so the results are bitwise those of k_transfer_1d_narrow.
+// Columns: c = outer n_inner + q; input (outer n_in + f) n_inner + q; output (outer n_out + o) n_inner + q.
+template <typename T, int W>
+__global__ void __launch_bounds__(256)
+    k_transfer_1d_lds(unsigned ncols, unsigned n_in, unsigned n_out, unsigned n_inner, FastDiv f_inner,
+                      const int* __restrict__ tidx, const T* __restrict__ tw, const T* __restrict__ in,
+                      T* __restrict__ out, bool accumulate) {
+    extern __shared__ unsigned char lds_raw[];
+    T* const st = reinterpret_cast<T*>(lds_raw);
+    const unsigned lane = threadIdx.x & 63u;
+    const unsigned wave = (unsigned)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const unsigned c0 = blockIdx.x * 64u;
+    const unsigned c = c0 + lane;
+    const bool live = c < ncols;
+    const unsigned outer = n_inner == 1u ? c : fast_quot(f_inner, c);
+    const unsigned q = c - outer * n_inner;
+    if (n_inner == 1u) {
+        // contiguous block of min(64, ncols - c0) lines of n_in values: st[line n_in + f]
+        const unsigned nl = min(64u, ncols - c0);
+        const T* const blk = in + (size_t)c0 * n_in;
+        for (unsigned e = threadIdx.x; e < nl * n_in; e += 256u) st[e] = blk[e];
+    } else {
+        // st[f 64 + lane]
+        for (unsigned f = wave; f < n_in; f += 4u)
+            st[f * 64u + lane] = live ? in[((size_t)outer * n_in + f) * n_inner + q] : T(0);
+    }
+    __syncthreads();
+    if (!live) return;
+    const unsigned sstr = n_inner == 1u ? 1u : 64u;                  // LDS stride between inputs
+    const T* const col = st + (n_inner == 1u ? lane * n_in : lane);
+    for (unsigned o = wave; o < n_out; o += 4u) {
+        T acc = T(0);
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const T wt = tw[o * W + w];
+            const T v = col[(unsigned)tidx[o * W + w] * sstr];
+            if (wt != T(0)) acc += wt * v;
+        }
+        T* const dst = out + ((size_t)outer * n_out + o) * n_inner + q;
+        if (accumulate) *dst += acc;
+        else *dst = acc;
+    }
+}
+
 // The same with 64-bit indices, for passes whose indices do not fit the narrow form.
 template <typename T>
 __global__ void k_transfer_1d(int dim, long long total, int i0, int i1, int o0, int o1, int o2, int dir,
@@ -511,6 +560,35 @@ hipError_t launch_transfer_1d(int dim, int ncomp, const int* in_dims, const int*
     const unsigned grid = grid_for(total, 256, 65536);
     // 32-bit indices when the output loop (with one grid stride of headroom) and the input fit in 2^31
     const bool narrow = total + (long long)grid * 256 < (1LL << 31) && in_comp * ncomp < (1LL << 31);
+    const int n_in = in_dims[dir], n_out = out_dims[dir];
+    const long long inner = dir == 0 ? 1LL : (dir == 1 ? (long long)in_dims[0] : (long long)in_dims[0] * in_dims[1]);
+    const long long ncols = in_comp / n_in * ncomp;
+    const size_t lds = (size_t)n_in * 64 * sizeof(T);
+    // The staged form pays where each output has many table terms (the restriction of Q3 and Q4: 11 and 13
+    // fine nodes per coarse vertex, about 2 inputs per output) and in the y and z passes of the
+    // prolongation (about half an input per output; the last pass also reads the output it adds to);
+    // elsewhere (Q1/Q2 restriction, the x pass of the prolongation, whose staged stores are one line
+    // per lane) the direct form with its higher occupancy was faster on MI355X.
+    const bool lds_ok = narrow && lds <= 64 * 1024 && ncols < (1LL << 31) &&
+                        (width == 11 || width == 13 ||
+                         (dir >= 1 && n_out > n_in && (width == 2 || width == 3 || width == 4 || width == 5)));
+    if (lds_ok) {
+        const unsigned blocks = (unsigned)((ncols + 63) / 64);
+        const FastDiv fi = make_fastdiv((unsigned)inner);
+#define SG_TL(W_)                                                                                                  \
+    hipLaunchKernelGGL((k_transfer_1d_lds<T, W_>), dim3(blocks), dim3(256), lds, s, (unsigned)ncols, (unsigned)n_in, \
+                       (unsigned)n_out, (unsigned)inner, fi, tidx, tw, in, out, accumulate)
+        switch (width) {
+            case 2: SG_TL(2); break;
+            case 3: SG_TL(3); break;
+            case 4: SG_TL(4); break;
+            case 5: SG_TL(5); break;
+            case 11: SG_TL(11); break;
+            default: SG_TL(13); break;
+        }
+#undef SG_TL
+        return hipGetLastError();
+    }
     if (narrow) {
         const FastDiv f0 = make_fastdiv((unsigned)out_dims[0]), f1 = make_fastdiv((unsigned)out_dims[1]),
                       f2 = make_fastdiv(dim == 3 ? (unsigned)out_dims[2] : 1u);
