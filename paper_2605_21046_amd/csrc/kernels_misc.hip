@@ -564,12 +564,12 @@ hipError_t launch_transfer_1d(int dim, int ncomp, const int* in_dims, const int*
     const long long inner = dir == 0 ? 1LL : (dir == 1 ? (long long)in_dims[0] : (long long)in_dims[0] * in_dims[1]);
     const long long ncols = in_comp / n_in * ncomp;
     const size_t lds = (size_t)n_in * 64 * sizeof(T);
-    // The staged form pays where each output has many table terms (the restriction of Q3 and Q4: 11 and 13
-    // fine nodes per coarse vertex, about 2 inputs per output) and in the y and z passes of the
+    // In 3D the staged form pays where each output has many table terms (the restriction of Q3 and Q4: 11
+    // and 13 fine nodes per coarse vertex, about 2 inputs per output) and in the y and z passes of the
     // prolongation (about half an input per output; the last pass also reads the output it adds to);
     // elsewhere (Q1/Q2 restriction, the x pass of the prolongation, whose staged stores are one line
-    // per lane) the direct form with its higher occupancy was faster on MI355X.
-    const bool lds_ok = narrow && lds <= 64 * 1024 && ncols < (1LL << 31) &&
+    // per lane, and the 2D passes) the direct form with its higher occupancy was faster on MI355X.
+    const bool lds_ok = dim == 3 && narrow && lds <= 64 * 1024 && ncols < (1LL << 31) &&
                         (width == 11 || width == 13 ||
                          (dir >= 1 && n_out > n_in && (width == 2 || width == 3 || width == 4 || width == 5)));
     if (lds_ok) {
