@@ -88,6 +88,9 @@ WORKLOADS = {
     "t3c3": Workload("t3c3", 3, 5, 3, 2, 1.0 / 5, 3, 4, 1, "sine"),
     # the c3 discretisation on two levels (4 and 2 cells per direction): Vanka sweeps of Q3 dG(2) patches
     "t3v3": Workload("t3v3", 3, 4, 3, 2, 1.0 / 4, 3, 4, 2, "sine"),
+    # two-level 3D Q3 and Q4 hierarchies with few modes: the Q3/Q4 restriction and prolongation passes
+    "t3m3": Workload("t3m3", 3, 4, 3, 1, 0.05, 1, 1, 2, "sine"),
+    "t3m4": Workload("t3m4", 3, 4, 4, 0, 0.05, 1, 1, 2, "sine"),
     # 64 cells per row: one row of cells per wave in the register-form Vanka corrections
     "t2w64": Workload("t2w64", 2, 64, 2, 1, 0.01, 2, 2, 2, "sine"),
     # three-level hierarchies whose lower two levels form one persistent coarse segment

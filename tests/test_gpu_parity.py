@@ -177,7 +177,8 @@ def test_vanka_register_form_is_bitwise_the_lds_form(torch_cuda, name, precision
         assert np.array_equal(got["reg"], got["lds"]), level
 
 
-@pytest.mark.parametrize("name", ["c1", "t2q2", "t2q3", "t2q4", "t3q1", "t3q2", "t2q2p4", "t3c2", "t2s3", "t3s2"])
+@pytest.mark.parametrize("name", ["c1", "t2q2", "t2q3", "t2q4", "t3q1", "t3q2", "t2q2p4", "t3c2", "t2s3", "t3s2",
+                                  "t3m3", "t3m4"])
 def test_vcycle_matches_oracle(torch_cuda, name):
     torch = torch_cuda
     w = sg_inputs.WORKLOADS[name]
